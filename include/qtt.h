@@ -1,0 +1,237 @@
+/*
+ * qtt.h -- C ABI of the MI355X QTT denoising-convolution library.
+ *
+ * The library implements the hot path of Chertock, Leonard, Tsynkov and
+ * Utyuzhnikov, "Denoising Convolution Algorithms and Applications to SAR
+ * Signal Processing" (arXiv 2301.13339): decomposition of a 2^d-sample signal
+ * or image into quantized tensor-train (QTT) cores by TT-SVD with truncation
+ * at a tolerance (Algorithm 1, with the max-rank modification (1) of
+ * Section 5), an exact convolution with a sinc kernel (GAF (3.1), kernels
+ * (7.2)/(7.3), discrete convolution (2.2)) carried out in QTT format,
+ * TT-rounding of the result, and reconstruction of the full array
+ * (Algorithm 3).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  * All array arguments are DEVICE pointers (HIP global memory) owned by the
+ *    caller unless stated otherwise.  The library never allocates device
+ *    memory; every call takes a caller-owned workspace `ws` of `ws_bytes`
+ *    bytes whose required size is returned by the matching qtt_query_* call.
+ *  * Every call is asynchronous on `stream` (0 = the default stream) and
+ *    performs no host/device synchronisation.  Ranks that depend on the data
+ *    live in device memory (`qtt_tensor.ranks`); the host only knows their
+ *    capacities.
+ *  * QTT index map (Section 4): a vector v of length 2^d is the d-mode tensor
+ *    V(i_1..i_d) = v(i), i = sum_k i_k 2^(k-1); i_1 is the least significant
+ *    bit.  A row-major 2^dy x 2^dx image is its flattened row-major vector,
+ *    so modes 1..dx are the column bits and modes dx+1..dx+dy the row bits.
+ *  * Core k (k = 1..d) has shape (r_{k-1}, 2, r_k), r_0 = r_d = 1, stored
+ *    C-contiguously with the ACTUAL ranks: entry (a, i, b) at element offset
+ *    off_k + (a*2 + i)*r_k + b, where off_k = sum_{j<k} cap_j * 2 * cap_{j+1}
+ *    is fixed by the host-side capacities (0-based arrays below).
+ *  * Return value: QTT_OK (0) or a negative error code (see below).  Codes
+ *    are returned synchronously, before anything is enqueued, for invalid
+ *    arguments and undersized workspaces.  Conditions found on the device
+ *    (non-finite input, a rank limited by a capacity) are OR-ed into the
+ *    tensor's `status` word, which the caller reads after synchronising.
+ *  * No C++ exception crosses this boundary.  The library keeps no pointer
+ *    after a call returns.  Concurrent calls on different streams must use
+ *    different workspaces and output tensors.
+ */
+#ifndef QTT_H
+#define QTT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+#define QTT_OK 0
+#define QTT_EINVAL (-1)   /* invalid argument                                  */
+#define QTT_ENOSPC (-2)   /* workspace or tensor capacity too small            */
+#define QTT_ENOTSUP (-3)  /* valid but unsupported size or option              */
+#define QTT_EHIP (-4)     /* a HIP runtime call failed (see qtt_last_hip_error) */
+
+/* device status bits (OR-ed into *status) */
+#define QTT_STATUS_NONFINITE 1  /* the input held NaN or Inf                    */
+#define QTT_STATUS_RANKCAP 2    /* an eps-rank exceeded the rank capacity       */
+
+/* element types */
+#define QTT_F32 0
+#define QTT_F64 1
+
+/* rounding methods for qtt_round */
+#define QTT_ROUND_EXACT 0       /* TT-SVD of the represented tensor, FP64 sums  */
+#define QTT_ROUND_SKETCH_F32 1  /* randomized range finder, FP32 sketch GEMMs   */
+#define QTT_ROUND_SKETCH_BF16 2 /* randomized range finder, BF16 MFMA sketches  */
+
+#define QTT_MAXD 48             /* largest number of binary modes               */
+#define QTT_MAX_RANK 64         /* largest TT-rank a decomposition can produce  */
+
+/*
+ * A QTT tensor.  `d`, `dtype` and `cap` are host values written by the
+ * caller (normally copied from a qtt_query_* result); `ranks`, `cores` and
+ * `status` point to device memory of at least (d+1) int32, qtt_core_elems()
+ * elements of `dtype`, and one int32.  Producers write `ranks` (r_0..r_d) and
+ * the cores; `status` may be NULL, in which case device conditions are
+ * dropped.
+ */
+typedef struct {
+  int32_t d;
+  int32_t dtype;
+  int32_t cap[QTT_MAXD + 1];
+  int32_t* ranks;
+  void* cores;
+  int32_t* status;
+} qtt_tensor;
+
+/* Number of core elements for the capacities cap[0..d]. */
+size_t qtt_core_elems(int d, const int32_t* cap);
+
+/* Text for an error code or status bit set (static storage). */
+const char* qtt_strerror(int code);
+
+/* Text of the last HIP error seen by the calling thread ("" if none). */
+const char* qtt_last_hip_error(void);
+
+/* ------------------------------------------------------------- decompose */
+/*
+ * Sizes for qtt_decompose / qtt_kernel_sinc.
+ *   d         number of modes of the decomposed tensor (N = 2^d samples)
+ *   max_rank  rank cap R of modification (1); 0 = no cap.  The effective cap
+ *             is min(R, QTT_MAX_RANK); an eps-rank above it is truncated and
+ *             flagged with QTT_STATUS_RANKCAP.
+ *   dtype     element type of the data and of the cores
+ * Outputs (any may be NULL): cap[0..d] = min(2^k, 2^(d-k), effective cap)
+ * with cap[0] = cap[d] = 1, the workspace size and the core element count.
+ */
+int qtt_query_decompose(int d, int max_rank, int dtype, int32_t* cap, size_t* ws_bytes,
+                        size_t* core_elems);
+
+/*
+ * TT-SVD of a vector (Algorithm 1 with modification (1); Lemma 5.1 shapes).
+ *   x         device, 2^d elements of `dtype`, read only
+ *   eps       relative tolerance >= 0: each unfolding k is truncated to the
+ *             smallest rank r >= 1 whose discarded tail satisfies
+ *             sum_{i>r} sigma_i^2 <= tau^2, tau = eps*||x||_F/sqrt(d-1), then
+ *             to min(r, cap_k)
+ *   max_rank  as in qtt_query_decompose
+ *   out       tensor with out->d == d, out->dtype == dtype and capacities at
+ *             least those returned by qtt_query_decompose
+ *   sv        optional device buffer (NULL to skip) of (d-1)*2*QTT_MAX_RANK
+ *             doubles: row k-1 receives the singular values of unfolding k in
+ *             non-increasing order, zero padded
+ * Singular values and vectors come from FP64 Gram sums of the unfoldings
+ * (wavefront-shuffle reductions) and a one-workgroup FP64 Jacobi
+ * eigensolver, whatever `dtype` is.
+ */
+int qtt_decompose(const void* x, int d, int dtype, double eps, int max_rank, qtt_tensor* out,
+                  double* sv, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * QTT of the Toeplitz generator of the normalised sinc kernel.
+ * For N = 2^d the kernel is g_m = sinc(B x_m)/Z on x_m = -1/2 + m/N
+ * (sinc(t) = sin(pi t)/(pi t), kernel (7.2) with B = 1/Delta_x and Z the
+ * midpoint sum dx*sum_m sinc(B x_m)); the generator w has 2N entries,
+ * w_u = dx*g_{u-N/2} for N/2 <= u < 3N/2 and 0 otherwise, so that (2.2) is
+ * y_j = sum_i w_{j-i+N} f_i.  The samples are computed on the device (no
+ * input array) and decomposed like qtt_decompose on d+1 modes at tolerance
+ * eps_w, uncapped (up to QTT_MAX_RANK).
+ *   w_out     tensor with d+1 modes and capacities from
+ *             qtt_query_decompose(d+1, 0, dtype, ...)
+ */
+int qtt_kernel_sinc(int d, double B, double eps_w, int dtype, qtt_tensor* w_out, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ conv */
+/*
+ * Sizes for qtt_conv.  `f_cap` are the capacities of the signal (d modes),
+ * `w_caps[a]` those of the kernel generator of axis a (d_a + 1 modes, axes
+ * ordered column axis first), n_axes = 1 (signal) or 2 (image, d = d_0 + d_1).
+ * Returns the output capacities y_cap[0..d] (y_cap[k] = 2*capW*capF inside an
+ * axis, capF at an axis boundary) and the sizes.
+ */
+int qtt_query_conv(int d, int n_axes, const int32_t* axis_modes, const int32_t* f_cap,
+                   const int32_t* const* w_caps, int dtype, int32_t* y_cap, size_t* ws_bytes,
+                   size_t* core_elems);
+
+/*
+ * Exact convolution (2.2) in QTT format: y = T(w) f with T(j,i) = w_{j-i+N}
+ * per axis.  The index u = j + (N-1-i) + 1 is a binary addition with carry,
+ * so each mode of the Toeplitz operator is a QTT-matrix core whose bond is
+ * (kernel bond, carry bit); the output cores are the mode-wise products with
+ * the signal cores (bond 2*rho_k*r_k).  No truncation.
+ *   f         signal tensor (d modes)
+ *   w         array of n_axes kernel tensors, w[a] with axis_modes[a]+1 modes
+ *   y         output tensor with capacities from qtt_query_conv
+ */
+int qtt_conv(const qtt_tensor* f, const qtt_tensor* w, int n_axes, const int32_t* axis_modes,
+             qtt_tensor* y, void* ws, size_t ws_bytes, void* stream);
+
+/* ----------------------------------------------------------------- round */
+/*
+ * Sizes for qtt_round of a tensor with capacities y_cap into a tensor with
+ * capacities z_cap = qtt_query_decompose(d, max_rank, ...).
+ */
+int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int method,
+                    int32_t* z_cap, size_t* ws_bytes, size_t* core_elems);
+
+/*
+ * TT-rounding of y at tolerance eps (the paper gives no rounding algorithm;
+ * TT-rounding of an exact TT returns the TT-SVD of the tensor it represents).
+ *   method QTT_ROUND_EXACT: the result is the TT-SVD (Algorithm 1, same
+ *          truncation rule and threshold with ||y||_F) of the represented
+ *          tensor; it is computed by reconstructing the tensor into the
+ *          workspace (Algorithm 3) and running the qtt_decompose sweep.
+ *   method QTT_ROUND_SKETCH_*: randomized rounding (range finder of
+ *          Algorithm 4 on every unfolding, one sketch per mode against a
+ *          random Gaussian TT drawn from `seed` with Philox-4x32-10) followed
+ *          by the exact truncation of the sketched tensor.
+ *   z      output tensor with capacities from qtt_query_round
+ */
+int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_t seed,
+              qtt_tensor* z, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ full */
+/* Workspace for qtt_full of a tensor with capacities cap[0..d]. */
+int qtt_query_full(int d, const int32_t* cap, int dtype, size_t* ws_bytes);
+
+/*
+ * Full (Algorithm 3): out[i] = G_1[:, i_1, :] ... G_d[:, i_d, :] for all
+ * i < 2^d, written as 2^d elements of t->dtype.  Computed as two half
+ * chains (left and right interface matrices) and one tiled product.
+ */
+int qtt_full(const qtt_tensor* t, void* out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------ measurement */
+/*
+ * Kernel classes for the launch probe.  Between qtt_probe_start and
+ * qtt_probe_stop the library records a HIP event pair on the launch stream
+ * around every launch of kernels of class `cls` (at most `max_launches`
+ * pairs); qtt_probe_stop waits for the recorded events and returns the summed
+ * GPU time (ms) and the number of launches.  Measurement aid only: one probe
+ * per process, not thread-safe, events are created and destroyed by these
+ * two calls (no device memory is allocated).
+ */
+#define QTT_K_LEVEL_GRAM 1   /* streaming Gram of the samples (first pass)     */
+#define QTT_K_REDUCE 2       /* fixed-order sum of partial Gram matrices       */
+#define QTT_K_LEVEL_EIG 3    /* steps 1..6 from the level Gram                  */
+#define QTT_K_PROJECT 4      /* streaming projection + Gram of the remainder   */
+#define QTT_K_EIG_STEP 5     /* one truncated SVD step (Jacobi eigensolver)    */
+#define QTT_K_TAIL 6         /* last steps of the sweep in one workgroup       */
+#define QTT_K_CONV 7         /* Toeplitz-operator x signal cores               */
+#define QTT_K_FULL_CHAIN 8   /* half-chain products of Full                    */
+#define QTT_K_FULL_FINAL 9   /* final product of Full (writes the 2^d outputs) */
+#define QTT_K_OTHER 10       /* bookkeeping kernels                            */
+
+int qtt_probe_start(int cls, int max_launches);
+int qtt_probe_stop(double* total_ms, int* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QTT_H */

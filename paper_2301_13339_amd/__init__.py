@@ -1,0 +1,288 @@
+"""Python binding of libqtt (include/qtt.h): QTT denoising convolution on MI355X.
+
+Argument marshalling only: every step runs in the HIP library.  torch is
+used for device memory (the caching allocator) and the current stream.  The
+binding never computes on the CPU; without the built library every call
+raises.
+
+    t   = decompose(x, eps, max_rank)      # Algorithm 1 (+ modification (1))
+    w   = kernel_sinc(d, B, eps_w)         # QTT of the sinc Toeplitz generator
+    y   = conv(t, [w])                     # exact (2.2) in QTT format
+    z   = round(y, eps)                    # TT-rounding
+    out = full(z)                          # Algorithm 3
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+from ._lib import (QTT_F32, QTT_F64, QTT_MAX_RANK, QTT_MAXD, QTT_ROUND_EXACT,
+                   QTT_ROUND_SKETCH_BF16, QTT_ROUND_SKETCH_F32, QTT_STATUS_NONFINITE,
+                   QTT_STATUS_RANKCAP, QttError, lib, lib_path, qtt_tensor)
+
+__all__ = [
+    "QTT", "probe", "from_cores", "decompose", "kernel_sinc", "conv", "round", "full", "pipeline", "lib_path",
+    "QttError", "QTT_MAX_RANK",
+]
+
+_DT = {torch.float32: QTT_F32, torch.float64: QTT_F64}
+
+
+class probe:
+    """Context manager timing every launch of one kernel class with HIP events.
+
+    ``with probe("eig_step") as p: ...`` then ``p.ms`` (summed GPU time) and
+    ``p.launches``.  The events are recorded by the library on the stream the
+    kernels are launched on.
+    """
+
+    def __init__(self, cls: str, max_launches: int = 100000):
+        from ._lib import K_CLASSES
+        self.cls = K_CLASSES[cls]
+        self.max = int(max_launches)
+        self.ms = 0.0
+        self.launches = 0
+
+    def __enter__(self):
+        _check(lib().qtt_probe_start(self.cls, self.max), "qtt_probe_start")
+        return self
+
+    def __exit__(self, *exc):
+        ms = ctypes.c_double()
+        n = ctypes.c_int()
+        _check(lib().qtt_probe_stop(ctypes.byref(ms), ctypes.byref(n)), "qtt_probe_stop")
+        self.ms = ms.value
+        self.launches = n.value
+        return False
+_TORCH = {QTT_F32: torch.float32, QTT_F64: torch.float64}
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        msg = lib().qtt_strerror(rc).decode()
+        extra = lib().qtt_last_hip_error().decode() if rc == -4 else ""
+        raise QttError(rc, f"{what}: {msg} {extra}".strip())
+
+
+def _stream(device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+class QTT:
+    """A QTT tensor whose cores and ranks live on the GPU.
+
+    ``cap`` are the host-side rank capacities; ``ranks`` (device int32,
+    ``d+1`` entries) and ``cores`` (device, capacity-strided) are written by
+    the producing call.  ``status`` collects device-side condition bits.
+    """
+
+    def __init__(self, d: int, dtype: int, cap, device):
+        self.d = int(d)
+        self.dtype = int(dtype)
+        self.cap = [int(c) for c in cap]
+        self.device = torch.device(device)
+        n = int(lib().qtt_core_elems(self.d, (ctypes.c_int32 * (self.d + 1))(*self.cap)))
+        # the producer writes every entry inside the actual ranks
+        self.cores = torch.empty(max(n, 1), dtype=_TORCH[self.dtype], device=self.device)
+        self.ranks = torch.empty(self.d + 1, dtype=torch.int32, device=self.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._keep = []
+
+    # ------------------------------------------------------------ marshal
+    def _c(self) -> qtt_tensor:
+        t = qtt_tensor()
+        t.d = self.d
+        t.dtype = self.dtype
+        for k in range(QTT_MAXD + 1):
+            t.cap[k] = self.cap[k] if k <= self.d else 0
+        t.ranks = ctypes.c_void_p(self.ranks.data_ptr())
+        t.cores = ctypes.c_void_p(self.cores.data_ptr())
+        t.status = ctypes.c_void_p(self.status.data_ptr())
+        return t
+
+    # ----------------------------------------------------------- inspect
+    def ranks_host(self):
+        return [int(v) for v in self.ranks.cpu()]
+
+    def status_host(self) -> int:
+        return int(self.status.cpu()[0])
+
+    def core_offsets(self):
+        offs, o = [], 0
+        for k in range(self.d):
+            offs.append(o)
+            o += self.cap[k] * 2 * self.cap[k + 1]
+        return offs
+
+    def core_list(self):
+        """Cores as CPU float64 numpy arrays of shape ``(r_{k-1}, 2, r_k)``."""
+        r = self.ranks_host()
+        flat = self.cores.detach().cpu().double().numpy()
+        out = []
+        for k, o in enumerate(self.core_offsets()):
+            n = r[k] * 2 * r[k + 1]
+            out.append(flat[o:o + n].reshape(r[k], 2, r[k + 1]).copy())
+        return out
+
+
+def _make(d, dtype, cap, device) -> QTT:
+    return QTT(d, dtype, cap, device)
+
+
+def from_cores(cores, dtype=torch.float64, device="cuda") -> QTT:
+    """Upload host cores ``(r_{k-1}, 2, r_k)`` (capacities = their ranks)."""
+    d = len(cores)
+    ranks = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
+    t = _make(d, _DT[dtype], ranks, device)
+    flat = torch.cat([torch.as_tensor(c, dtype=torch.float64).reshape(-1) for c in cores])
+    t.cores[: flat.numel()].copy_(flat.to(dtype))
+    t.ranks.copy_(torch.tensor(ranks, dtype=torch.int32))
+    return t
+
+
+def decompose(x: torch.Tensor, eps: float, max_rank: int = 0, return_sv: bool = False):
+    """TT-SVD of the QTT reshape of ``x`` (length ``2**d``; images row-major)."""
+    if not x.is_cuda:
+        raise ValueError("decompose expects a device tensor")
+    x = x.contiguous().reshape(-1)
+    n = x.numel()
+    d = n.bit_length() - 1
+    if n < 2 or (1 << d) != n:
+        raise ValueError("length must be a power of two >= 2")
+    dt = _DT[x.dtype]
+    cap = (ctypes.c_int32 * (d + 1))()
+    ws = ctypes.c_size_t()
+    _check(lib().qtt_query_decompose(d, int(max_rank), dt, cap, ctypes.byref(ws), None),
+           "qtt_query_decompose")
+    out = _make(d, dt, list(cap), x.device)
+    w = _workspace(ws.value, x.device)
+    sv = None
+    if return_sv:
+        sv = torch.zeros((max(d - 1, 1), 2 * QTT_MAX_RANK), dtype=torch.float64, device=x.device)
+    t = out._c()
+    _check(lib().qtt_decompose(ctypes.c_void_p(x.data_ptr()), d, dt, float(eps), int(max_rank),
+                               ctypes.byref(t),
+                               ctypes.c_void_p(sv.data_ptr()) if sv is not None else None,
+                               ctypes.c_void_p(w.data_ptr()), ws.value, _stream(x.device)),
+           "qtt_decompose")
+    out._keep = [w, x]
+    return (out, sv) if return_sv else out
+
+
+def kernel_sinc(d: int, B: float, eps_w: float, dtype=torch.float64, device="cuda") -> QTT:
+    """QTT (``d+1`` modes) of the normalised sinc Toeplitz generator of a ``2**d`` grid."""
+    dt = _DT[dtype]
+    cap = (ctypes.c_int32 * (d + 2))()
+    ws = ctypes.c_size_t()
+    _check(lib().qtt_query_decompose(d + 1, 0, dt, cap, ctypes.byref(ws), None),
+           "qtt_query_decompose")
+    dev = torch.device(device)
+    out = _make(d + 1, dt, list(cap), dev)
+    w = _workspace(ws.value, dev)
+    t = out._c()
+    _check(lib().qtt_kernel_sinc(int(d), float(B), float(eps_w), dt, ctypes.byref(t),
+                                 ctypes.c_void_p(w.data_ptr()), ws.value, _stream(dev)),
+           "qtt_kernel_sinc")
+    out._keep = [w]
+    return out
+
+
+def conv(f: QTT, w, axis_modes=None) -> QTT:
+    """Exact convolution in QTT format with one kernel per axis (column axis first)."""
+    ws_list = list(w)
+    n_axes = len(ws_list)
+    if axis_modes is None:
+        axis_modes = [f.d] if n_axes == 1 else None
+    if axis_modes is None:
+        raise ValueError("axis_modes required for images")
+    am = (ctypes.c_int32 * n_axes)(*axis_modes)
+    fcap = (ctypes.c_int32 * (f.d + 1))(*f.cap)
+    wcaps = [(ctypes.c_int32 * (t.d + 1))(*t.cap) for t in ws_list]
+    wcp = (ctypes.POINTER(ctypes.c_int32) * n_axes)(
+        *[ctypes.cast(c, ctypes.POINTER(ctypes.c_int32)) for c in wcaps])
+    ycap = (ctypes.c_int32 * (f.d + 1))()
+    wsb = ctypes.c_size_t()
+    _check(lib().qtt_query_conv(f.d, n_axes, am, fcap, wcp, f.dtype, ycap, ctypes.byref(wsb), None),
+           "qtt_query_conv")
+    y = _make(f.d, f.dtype, list(ycap), f.device)
+    warr = (qtt_tensor * n_axes)(*[t._c() for t in ws_list])
+    fc = f._c()
+    yc = y._c()
+    _check(lib().qtt_conv(ctypes.byref(fc), warr, n_axes, am, ctypes.byref(yc), None, 0,
+                          _stream(f.device)), "qtt_conv")
+    y._keep = [f, ws_list]
+    return y
+
+
+_METHODS = {"exact": QTT_ROUND_EXACT, "sketch_f32": QTT_ROUND_SKETCH_F32,
+            "sketch_bf16": QTT_ROUND_SKETCH_BF16}
+
+
+def round(y: QTT, eps: float, max_rank: int = 0, method: str = "exact", seed: int = 0) -> QTT:  # noqa: A001
+    """TT-rounding of ``y`` at tolerance ``eps``."""
+    m = _METHODS[method]
+    ycap = (ctypes.c_int32 * (y.d + 1))(*y.cap)
+    zcap = (ctypes.c_int32 * (y.d + 1))()
+    wsb = ctypes.c_size_t()
+    _check(lib().qtt_query_round(y.d, ycap, int(max_rank), y.dtype, m, zcap, ctypes.byref(wsb),
+                                 None), "qtt_query_round")
+    z = _make(y.d, y.dtype, list(zcap), y.device)
+    w = _workspace(wsb.value, y.device)
+    yc, zc = y._c(), z._c()
+    _check(lib().qtt_round(ctypes.byref(yc), float(eps), int(max_rank), m, ctypes.c_uint64(seed),
+                           ctypes.byref(zc), ctypes.c_void_p(w.data_ptr()), wsb.value,
+                           _stream(y.device)), "qtt_round")
+    z._keep = [w, y]
+    return z
+
+
+def full(t: QTT, out: torch.Tensor | None = None) -> torch.Tensor:
+    """Algorithm 3: the ``2**d`` entries of ``t`` (QTT index order)."""
+    cap = (ctypes.c_int32 * (t.d + 1))(*t.cap)
+    wsb = ctypes.c_size_t()
+    _check(lib().qtt_query_full(t.d, cap, t.dtype, ctypes.byref(wsb)), "qtt_query_full")
+    if out is None:
+        out = torch.empty(1 << t.d, dtype=_TORCH[t.dtype], device=t.device)
+    w = _workspace(wsb.value, t.device)
+    tc = t._c()
+    _check(lib().qtt_full(ctypes.byref(tc), ctypes.c_void_p(out.data_ptr()),
+                          ctypes.c_void_p(w.data_ptr()), wsb.value, _stream(t.device)),
+           "qtt_full")
+    t._keep = t._keep + [w]
+    return out
+
+
+def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | None = None,
+             round_method: str = "exact", round_max_rank: int = 0, shape2d=None):
+    """Decompose, build the kernel QTT, convolve, round and reconstruct.
+
+    ``B`` is one bandwidth (signal) or ``(Bx, By)`` with ``shape2d = (ny, nx)``
+    for a row-major image.  Returns ``(out, stages)``.
+    """
+    if eps_w is None:
+        eps_w = eps / 10.0
+    f = decompose(x, eps, max_rank)
+    dt = x.dtype
+    if shape2d is None:
+        w = [kernel_sinc(f.d, float(B), eps_w, dt, x.device)]
+        am = [f.d]
+    else:
+        ny, nx = shape2d
+        dy, dx = ny.bit_length() - 1, nx.bit_length() - 1
+        bx, by = B
+        w = [kernel_sinc(dx, float(bx), eps_w, dt, x.device),
+             kernel_sinc(dy, float(by), eps_w, dt, x.device)]
+        am = [dx, dy]
+    y = conv(f, w, am)
+    z = round(y, eps, round_max_rank, round_method)
+    out = full(z)
+    if shape2d is not None:
+        out = out.reshape(shape2d)
+    return out, dict(f=f, w=w, y=y, z=z)

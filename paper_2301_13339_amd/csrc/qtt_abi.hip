@@ -1,0 +1,352 @@
+// extern "C" entry points of libqtt: argument checks, workspace planning and
+// dispatch to the HIP kernels.  See include/qtt.h for the contract.
+#include <math.h>
+#include <string.h>
+
+#include "qtt_internal.hpp"
+
+namespace qtt {
+
+static thread_local char g_hip_err[256] = "";
+
+void set_hip_error(hipError_t e) {
+  const char* s = hipGetErrorString(e);
+  strncpy(g_hip_err, s ? s : "unknown HIP error", sizeof(g_hip_err) - 1);
+  g_hip_err[sizeof(g_hip_err) - 1] = 0;
+}
+
+// ------------------------------------------------------------ launch probe
+struct ProbeState {
+  int cls = 0;
+  int cap = 0;
+  int n = 0;
+  hipEvent_t* ev = nullptr;
+};
+static ProbeState g_probe;
+
+void probe_pre(int cls, hipStream_t s) {
+  if (g_probe.cls != cls || g_probe.n >= g_probe.cap) return;
+  hipEventRecord(g_probe.ev[2 * g_probe.n], s);
+}
+
+void probe_post(int cls, hipStream_t s) {
+  if (g_probe.cls != cls || g_probe.n >= g_probe.cap) return;
+  hipEventRecord(g_probe.ev[2 * g_probe.n + 1], s);
+  ++g_probe.n;
+}
+
+static void probe_free() {
+  if (g_probe.ev) {
+    for (int i = 0; i < 2 * g_probe.cap; ++i) hipEventDestroy(g_probe.ev[i]);
+    delete[] g_probe.ev;
+  }
+  g_probe = ProbeState();
+}
+
+static int eff_rank(int max_rank) {
+  return (max_rank <= 0 || max_rank > kMaxRank) ? kMaxRank : max_rank;
+}
+
+static bool dtype_ok(int dt) { return dt == QTT_F32 || dt == QTT_F64; }
+
+constexpr int kMaxModes = 30;  // largest d for operations on full arrays (2^30 samples)
+
+static void caps_decompose(int d, int rcap, int32_t* cap) {
+  for (int k = 0; k <= d; ++k) {
+    long long c = rcap;
+    const long long lo = 1LL << (k < 40 ? k : 40), hi = 1LL << ((d - k) < 40 ? (d - k) : 40);
+    if (lo < c) c = lo;
+    if (hi < c) c = hi;
+    cap[k] = (k == 0 || k == d) ? 1 : (int32_t)c;
+  }
+}
+
+static size_t core_elems_of(int d, const int32_t* cap) {
+  size_t s = 0;
+  for (int k = 0; k < d; ++k) s += (size_t)cap[k] * 2 * (size_t)cap[k + 1];
+  return s;
+}
+
+// the tensor descriptor is usable as an output with at least the given capacities
+static int check_tensor(const qtt_tensor* t, int d, int dtype, const int32_t* need) {
+  if (!t || t->d != d || t->dtype != dtype || !t->ranks || !t->cores) return QTT_EINVAL;
+  if (t->cap[0] != 1 || t->cap[d] != 1) return QTT_EINVAL;
+  for (int k = 0; k <= d; ++k)
+    if (t->cap[k] < need[k]) return QTT_ENOSPC;
+  return QTT_OK;
+}
+
+static int check_tensor_in(const qtt_tensor* t) {
+  if (!t || t->d < 1 || t->d > kMaxModes + 1 || !dtype_ok(t->dtype) || !t->ranks || !t->cores)
+    return QTT_EINVAL;
+  if (t->cap[0] != 1 || t->cap[t->d] != 1) return QTT_EINVAL;
+  for (int k = 1; k < t->d; ++k)
+    if (t->cap[k] < 1) return QTT_EINVAL;
+  return QTT_OK;
+}
+
+}  // namespace qtt
+
+using namespace qtt;
+
+extern "C" {
+
+size_t qtt_core_elems(int d, const int32_t* cap) {
+  if (d < 1 || d > QTT_MAXD || !cap) return 0;
+  return core_elems_of(d, cap);
+}
+
+const char* qtt_strerror(int code) {
+  switch (code) {
+    case QTT_OK: return "ok";
+    case QTT_EINVAL: return "invalid argument";
+    case QTT_ENOSPC: return "workspace or tensor capacity too small";
+    case QTT_ENOTSUP: return "unsupported size or option";
+    case QTT_EHIP: return "HIP runtime error";
+    case QTT_STATUS_NONFINITE: return "input held a non-finite value";
+    case QTT_STATUS_RANKCAP: return "an eps-rank exceeded the rank capacity";
+    case QTT_STATUS_NONFINITE | QTT_STATUS_RANKCAP:
+      return "non-finite input; an eps-rank exceeded the rank capacity";
+    default: return "unknown code";
+  }
+}
+
+const char* qtt_last_hip_error(void) { return g_hip_err; }
+
+int qtt_probe_start(int cls, int max_launches) {
+  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_OTHER || max_launches < 1 || max_launches > (1 << 20))
+    return QTT_EINVAL;
+  probe_free();
+  g_probe.ev = new hipEvent_t[2 * (size_t)max_launches];
+  for (int i = 0; i < 2 * max_launches; ++i) {
+    const hipError_t e = hipEventCreate(&g_probe.ev[i]);
+    if (e != hipSuccess) {
+      for (int j = 0; j < i; ++j) hipEventDestroy(g_probe.ev[j]);
+      delete[] g_probe.ev;
+      g_probe = ProbeState();
+      set_hip_error(e);
+      return QTT_EHIP;
+    }
+  }
+  g_probe.cap = max_launches;
+  g_probe.cls = cls;
+  return QTT_OK;
+}
+
+int qtt_probe_stop(double* total_ms, int* launches) {
+  double tot = 0.0;
+  const int n = g_probe.n;
+  for (int i = 0; i < n; ++i) {
+    const hipError_t e = hipEventSynchronize(g_probe.ev[2 * i + 1]);
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      probe_free();
+      return QTT_EHIP;
+    }
+    float ms = 0.f;
+    hipEventElapsedTime(&ms, g_probe.ev[2 * i], g_probe.ev[2 * i + 1]);
+    tot += ms;
+  }
+  if (total_ms) *total_ms = tot;
+  if (launches) *launches = n;
+  probe_free();
+  return QTT_OK;
+}
+
+// ------------------------------------------------------------- decompose
+int qtt_query_decompose(int d, int max_rank, int dtype, int32_t* cap, size_t* ws_bytes,
+                        size_t* core_elems) {
+  if (d < 1 || d > kMaxModes + 1 || max_rank < 0 || !dtype_ok(dtype)) return QTT_EINVAL;
+  DecompPlan p;
+  plan_decompose(d, eff_rank(max_rank), dtype, nullptr, &p);
+  int32_t c[QTT_MAXD + 1];
+  caps_decompose(d, eff_rank(max_rank), c);
+  if (cap) memcpy(cap, c, sizeof(int32_t) * (d + 1));
+  if (ws_bytes) *ws_bytes = p.ws_bytes;
+  if (core_elems) *core_elems = core_elems_of(d, c);
+  return QTT_OK;
+}
+
+static int decompose_common(const Source& src, int D, int dtype, double eps, int max_rank,
+                            qtt_tensor* out, double* sv, void* ws, size_t ws_bytes,
+                            void* stream) {
+  if (D < 1 || D > kMaxModes + 1 || !dtype_ok(dtype) || !(eps >= 0.0) || !isfinite(eps) ||
+      max_rank < 0)
+    return QTT_EINVAL;
+  if (!ws) return QTT_EINVAL;
+  DecompPlan p;
+  plan_decompose(D, eff_rank(max_rank), dtype, nullptr, &p);
+  if (ws_bytes < p.ws_bytes) return QTT_ENOSPC;
+  int32_t need[QTT_MAXD + 1];
+  caps_decompose(D, eff_rank(max_rank), need);
+  const int rc = check_tensor(out, D, dtype, need);
+  if (rc) return rc;
+  plan_decompose(D, eff_rank(max_rank), dtype, ws, &p);
+  TensorDev td = make_dev(out);
+  return run_decompose(p, src, eps, td, sv, static_cast<hipStream_t>(stream));
+}
+
+int qtt_decompose(const void* x, int d, int dtype, double eps, int max_rank, qtt_tensor* out,
+                  double* sv, void* ws, size_t ws_bytes, void* stream) {
+  if (!x) return QTT_EINVAL;
+  Source src{x, 0, 0.0, 0};
+  return decompose_common(src, d, dtype, eps, max_rank, out, sv, ws, ws_bytes, stream);
+}
+
+int qtt_kernel_sinc(int d, double B, double eps_w, int dtype, qtt_tensor* w_out, void* ws,
+                    size_t ws_bytes, void* stream) {
+  if (d < 1 || d > kMaxModes || !(B > 0.0) || !isfinite(B)) return QTT_EINVAL;
+  Source src{nullptr, 1, B, d};
+  return decompose_common(src, d + 1, dtype, eps_w, 0, w_out, nullptr, ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------------------------ conv
+static int conv_caps(int d, int n_axes, const int32_t* axis_modes, const int32_t* f_cap,
+                     const int32_t* const* w_caps, int32_t* y_cap) {
+  if (n_axes < 1 || n_axes > 2 || !axis_modes || !f_cap || !w_caps) return QTT_EINVAL;
+  int sum = 0;
+  for (int a = 0; a < n_axes; ++a) {
+    if (axis_modes[a] < 1 || !w_caps[a]) return QTT_EINVAL;
+    sum += axis_modes[a];
+  }
+  if (sum != d) return QTT_EINVAL;
+  int k = 0;
+  y_cap[0] = 1;
+  for (int a = 0; a < n_axes; ++a) {
+    for (int kap = 1; kap <= axis_modes[a]; ++kap, ++k) {
+      const long long fc = f_cap[k + 1];
+      const long long c = (kap == axis_modes[a]) ? fc : 2LL * w_caps[a][kap] * fc;
+      if (c > (1LL << 30)) return QTT_ENOTSUP;
+      y_cap[k + 1] = (int32_t)c;
+    }
+  }
+  y_cap[d] = 1;
+  return QTT_OK;
+}
+
+int qtt_query_conv(int d, int n_axes, const int32_t* axis_modes, const int32_t* f_cap,
+                   const int32_t* const* w_caps, int dtype, int32_t* y_cap, size_t* ws_bytes,
+                   size_t* core_elems) {
+  if (d < 1 || d > kMaxModes || !dtype_ok(dtype)) return QTT_EINVAL;
+  int32_t yc[QTT_MAXD + 1];
+  const int rc = conv_caps(d, n_axes, axis_modes, f_cap, w_caps, yc);
+  if (rc) return rc;
+  if (y_cap) memcpy(y_cap, yc, sizeof(int32_t) * (d + 1));
+  if (ws_bytes) *ws_bytes = 0;
+  if (core_elems) *core_elems = core_elems_of(d, yc);
+  return QTT_OK;
+}
+
+int qtt_conv(const qtt_tensor* f, const qtt_tensor* w, int n_axes, const int32_t* axis_modes,
+             qtt_tensor* y, void* ws, size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (check_tensor_in(f) || !w || n_axes < 1 || n_axes > 2 || !axis_modes) return QTT_EINVAL;
+  const int d = f->d;
+  if (d > kMaxModes) return QTT_EINVAL;
+  const int32_t* wc[2] = {nullptr, nullptr};
+  for (int a = 0; a < n_axes; ++a) {
+    if (check_tensor_in(&w[a]) || w[a].dtype != f->dtype || w[a].d != axis_modes[a] + 1)
+      return QTT_EINVAL;
+    wc[a] = w[a].cap;
+  }
+  int32_t yc[QTT_MAXD + 1];
+  int rc = conv_caps(d, n_axes, axis_modes, f->cap, wc, yc);
+  if (rc) return rc;
+  rc = check_tensor(y, d, f->dtype, yc);
+  if (rc) return rc;
+  TensorDev fd = make_dev(f), yd = make_dev(y);
+  TensorDev wd[2];
+  for (int a = 0; a < n_axes; ++a) wd[a] = make_dev(&w[a]);
+  return run_conv(fd, wd, n_axes, axis_modes, yd, f->dtype, static_cast<hipStream_t>(stream));
+}
+
+// ------------------------------------------------------------------ full
+int qtt_query_full(int d, const int32_t* cap, int dtype, size_t* ws_bytes) {
+  if (d < 1 || d > kMaxModes || !cap || !dtype_ok(dtype)) return QTT_EINVAL;
+  void* bufs[4];
+  size_t b = 0;
+  plan_full(d, cap, dtype, nullptr, &b, bufs);
+  if (ws_bytes) *ws_bytes = b;
+  return QTT_OK;
+}
+
+int qtt_full(const qtt_tensor* t, void* out, void* ws, size_t ws_bytes, void* stream) {
+  if (check_tensor_in(t) || !out || t->d > kMaxModes) return QTT_EINVAL;
+  size_t need = 0;
+  void* bufs[4];
+  plan_full(t->d, t->cap, t->dtype, nullptr, &need, bufs);
+  if (need > 0 && (!ws || ws_bytes < need)) return need > ws_bytes ? QTT_ENOSPC : QTT_EINVAL;
+  TensorDev td = make_dev(t);
+  return run_full(td, t->dtype, out, ws, static_cast<hipStream_t>(stream));
+}
+
+// ----------------------------------------------------------------- round
+struct RoundPlan {
+  void* yfull;
+  void* full_ws;
+  size_t full_bytes;
+  void* dec_ws;
+  size_t dec_bytes;
+  size_t total;
+};
+
+static void plan_round(int d, const int32_t* y_cap, int rcap, int dtype, void* ws,
+                       RoundPlan* rp) {
+  Arena ar(ws);
+  const size_t es = elem_size(dtype);
+  rp->yfull = ar.take<char>(((size_t)1 << d) * es);
+  void* bufs[4];
+  size_t fb = 0;
+  plan_full(d, y_cap, dtype, nullptr, &fb, bufs);
+  rp->full_ws = ar.take<char>(fb);
+  rp->full_bytes = fb;
+  DecompPlan p;
+  plan_decompose(d, rcap, dtype, nullptr, &p);
+  rp->dec_ws = ar.take<char>(p.ws_bytes);
+  rp->dec_bytes = p.ws_bytes;
+  rp->total = ar.size();
+}
+
+int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int method,
+                    int32_t* z_cap, size_t* ws_bytes, size_t* core_elems) {
+  if (d < 1 || d > kMaxModes || !y_cap || !dtype_ok(dtype) || max_rank < 0) return QTT_EINVAL;
+  if (method != QTT_ROUND_EXACT) return QTT_ENOTSUP;
+  RoundPlan rp;
+  plan_round(d, y_cap, eff_rank(max_rank), dtype, nullptr, &rp);
+  int32_t zc[QTT_MAXD + 1];
+  caps_decompose(d, eff_rank(max_rank), zc);
+  if (z_cap) memcpy(z_cap, zc, sizeof(int32_t) * (d + 1));
+  if (ws_bytes) *ws_bytes = rp.total;
+  if (core_elems) *core_elems = core_elems_of(d, zc);
+  return QTT_OK;
+}
+
+int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_t seed,
+              qtt_tensor* z, void* ws, size_t ws_bytes, void* stream) {
+  (void)seed;
+  if (check_tensor_in(y) || y->d > kMaxModes || !(eps >= 0.0) || !isfinite(eps) || max_rank < 0 ||
+      !ws)
+    return QTT_EINVAL;
+  if (method != QTT_ROUND_EXACT) return QTT_ENOTSUP;
+  const int d = y->d;
+  RoundPlan rp;
+  plan_round(d, y->cap, eff_rank(max_rank), y->dtype, nullptr, &rp);
+  if (ws_bytes < rp.total) return QTT_ENOSPC;
+  int32_t zc[QTT_MAXD + 1];
+  caps_decompose(d, eff_rank(max_rank), zc);
+  int rc = check_tensor(z, d, y->dtype, zc);
+  if (rc) return rc;
+  plan_round(d, y->cap, eff_rank(max_rank), y->dtype, ws, &rp);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TensorDev yd = make_dev(y);
+  rc = run_full(yd, y->dtype, rp.yfull, rp.full_ws, st);
+  if (rc) return rc;
+  DecompPlan p;
+  plan_decompose(d, eff_rank(max_rank), y->dtype, rp.dec_ws, &p);
+  Source src{rp.yfull, 0, 0.0, 0};
+  TensorDev zd = make_dev(z);
+  return run_decompose(p, src, eps, zd, nullptr, st);
+}
+
+}  // extern "C"

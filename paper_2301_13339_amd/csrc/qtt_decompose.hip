@@ -1,0 +1,892 @@
+// TT-SVD sweep (Algorithm 1 with the max-rank modification (1)) on gfx950.
+//
+// Notation.  For step k (1..D-1) the remainder X_k is an n_k x m_k row-major
+// matrix, n_k = 2^(D-k), m_k = 2 r_{k-1}; its column c = a + r_{k-1} i_k is
+// the row of the paper's unfolding A^{k} (Lemma 5.1), so X_k = (A^{k})^T and
+// the left singular vectors of A^{k} are the eigenvectors of X_k^T X_k.  With
+// U_k the kept eigenvectors, core k is U_k reshaped (r_{k-1}, 2, r_k) and the
+// next remainder X_{k+1} is the memory of X_k U_k (n_k x r_k) read as an
+// (n_k/2) x (2 r_k) matrix -- the reshape is free in row-major order.
+//
+// Schedule (D modes, N = 2^D samples):
+//  * N <= kTailElems: one workgroup holds the samples in LDS and runs the
+//    whole sweep (k_tail).
+//  * otherwise
+//    - k_level_gram streams the samples once and forms the 64 x 64 Gram of
+//      the data viewed as (N/64) x 64 (FP64, per-block partials);
+//    - k_level_eig runs steps 1..6 from it: the Gram of X_k is
+//      P_k^T G_k P_k, G_k a block sum of the 64 x 64 Gram and P_k the
+//      block-diagonal embedding of the left interface Phi_{k-1};
+//    - k_project_gram computes X_{k+1} = X_k U_k block by block and the
+//      partial Grams of X_{k+1} in the same pass (one read, one write);
+//    - k_reduce sums the partials in a fixed order (deterministic);
+//    - k_eig_step solves one step;
+//    - once X_k fits kTailElems, k_tail finishes in LDS (dual Gram X X^T
+//      when n_k < m_k).
+// Ranks stay in device memory; no kernel needs a host synchronisation.
+#include <math.h>
+
+#include "qtt_eig.hpp"
+#include "qtt_internal.hpp"
+
+namespace qtt {
+
+// ------------------------------------------------------------ sample access
+// Generator of the sinc-kernel Toeplitz vector, unnormalised: for a kernel
+// grid of 2^nk samples x_m = -1/2 + m/2^nk, s_u = sinc(B x_{u - 2^(nk-1)}) for
+// 2^(nk-1) <= u < 3*2^(nk-1), else 0 (normalised later by the sample sum).
+__device__ __forceinline__ double sinc_gen(long long u, double B, int nk) {
+  const long long nn = 1LL << nk;
+  const long long m = u - (nn >> 1);
+  if (m < 0 || m >= nn) return 0.0;
+  const double x = -0.5 + (double)m / (double)nn;
+  const double t = B * x;
+  if (t == 0.0) return 1.0;
+  return sinpi(t) / (M_PI * t);
+}
+
+template <typename T, int GEN>
+__device__ __forceinline__ double sample(const T* x, long long u, double B, int nk) {
+  if (GEN) return sinc_gen(u, B, nk);
+  return (double)x[u];
+}
+
+__device__ __forceinline__ int finite_d(double v) { return isfinite(v) ? 1 : 0; }
+
+// write core k (1-based) from U (m x r, row-major, rows c = a + rp*i)
+template <typename T>
+__device__ void write_core_from_u(T* cores, long long off, const double* U, int ldu, int rp, int r,
+                                  int tid, int nt) {
+  const int total = rp * 2 * r;
+  for (int e = tid; e < total; e += nt) {
+    const int b = e % r;
+    const int ai = e / r;
+    const int i = ai & 1, a = ai >> 1;
+    cores[off + e] = (T)U[(a + rp * i) * ldu + b];
+  }
+}
+
+// ----------------------------------------------------------------- D == 1
+template <typename T, int GEN>
+__global__ void k_single(const T* x, double B, int nk, T* cores, int32_t* ranks, double* scal,
+                         int32_t* status) {
+  if (threadIdx.x == 0) {
+    const double v0 = sample<T, GEN>(x, 0, B, nk), v1 = sample<T, GEN>(x, 1, B, nk);
+    double s = GEN ? v0 + v1 : 1.0;
+    if (GEN && s == 0.0) s = 1.0;
+    cores[0] = (T)(v0 / s);
+    cores[1] = (T)(v1 / s);
+    ranks[0] = 1;
+    ranks[1] = 1;
+    if (status && !(finite_d(v0) && finite_d(v1))) atomicOr(status, QTT_STATUS_NONFINITE);
+    scal[0] = v0 * v0 + v1 * v1;
+  }
+}
+
+// ------------------------------------------------------------ level Gram
+// Partial Gram of the samples viewed as rows x 64 (row-major), 256 threads,
+// thread (ty, tx) owns the 4 x 4 tile rows 4ty.., cols 4tx.. .
+template <typename T, int GEN>
+__global__ void __launch_bounds__(256) k_level_gram(const T* x, double B, int nk, long long rows,
+                                                    double* partials, int pstride,
+                                                    double* gsum_part, int32_t* iflags) {
+  constexpr int W = 64, SR = 32;
+  __shared__ double st[SR * W];
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  double gsum = 0.0;
+  int fin = 1;
+  const long long nstage = (rows + SR - 1) / SR;
+  for (long long sidx = blockIdx.x; sidx < nstage; sidx += gridDim.x) {
+    const long long r0 = sidx * SR;
+    const long long base = r0 * W;
+    for (int e = tid; e < SR * W; e += 256) {
+      double v = 0.0;
+      if (r0 + e / W < rows) v = sample<T, GEN>(x, base + e, B, nk);
+      fin &= finite_d(v);
+      gsum += v;
+      st[e] = v;
+    }
+    __syncthreads();
+    for (int rr = 0; rr < SR; ++rr) {
+      double xa[4], xb[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) xa[a] = st[rr * W + 4 * ty + a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) xb[b] = st[rr * W + 4 * tx + b];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xa[a], xb[b], acc[a][b]);
+    }
+    __syncthreads();
+  }
+  double* P = partials + (size_t)blockIdx.x * pstride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) P[(4 * ty + a) * W + 4 * tx + b] = acc[a][b];
+  // block sum of the samples (generator normalisation), fixed order
+  __shared__ double red[256];
+  red[tid] = gsum;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
+    __syncthreads();
+  }
+  if (tid == 0) gsum_part[blockIdx.x] = red[0];
+  if (!fin) atomicOr(iflags, 1);
+}
+
+// --------------------------------------------------------------- reduction
+// out[e] = sum_b partials[b*pstride + e] for e < count.  Block of 256 threads
+// = 64 entries x 4 partial groups; group g sums partials g, g+4, ... and the
+// four group sums are added in a fixed order (deterministic).  Block 0 also
+// sums the generator partial sums into scal[2].
+__global__ void __launch_bounds__(256) k_reduce(const double* partials, int pstride, int nparts,
+                                                int count, double* out, const double* gsum_part,
+                                                double* scal) {
+  __shared__ double red[4][64];
+  const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + el;
+  double s = 0.0;
+  if (e < count)
+    for (int b = g; b < nparts; b += 4) s += partials[(size_t)b * pstride + e];
+  red[g][el] = s;
+  __syncthreads();
+  if (g == 0 && e < count) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
+  if (gsum_part && blockIdx.x == 0 && threadIdx.x == 0) {
+    double t = 0.0;
+    for (int b = 0; b < nparts; ++b) t += gsum_part[b];
+    scal[2] = t;
+  }
+}
+
+// ----------------------------------------------------- step bookkeeping
+// capacities and core offsets, passed by value to the kernels
+struct Meta {
+  int caps[QTT_MAXD + 1];
+  long long offs[QTT_MAXD + 1];
+};
+
+struct StepOut {
+  int32_t* ranks;
+  int32_t* status;
+  double* sv;  // may be null
+  int lib_capped;
+  int32_t* dbg;  // Jacobi sweeps per step (workspace diagnostics)
+};
+
+// eigen-solve the Gram in A (E x E), choose the rank, fill lam/perm.
+// Returns r (also in *r_sh).  Must be called by all threads.
+template <int NT>
+__device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* cs, int* iscr,
+                                  double* lam, int* perm, double tau2, int cap, int k,
+                                  const StepOut& so) {
+  const int tid = threadIdx.x;
+  // finiteness of the Gram (NaN/Inf input)
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < E; ++i) tr += A[i * lda + i];
+    iscr[1] = isfinite(tr) ? 1 : 0;
+  }
+  __syncthreads();
+  const int finite = iscr[1];
+  double* lam_raw = cs;  // scratch (>= E doubles)
+  if (finite) {
+    const int sw = gram_eig<NT>(A, V, E, lda, lam_raw, reinterpret_cast<double*>(iscr + 8), iscr,
+                                so.dbg ? so.dbg + 64 + 4 * k : nullptr);
+    if (tid == 0 && so.dbg) so.dbg[k] = sw;
+  } else {
+    for (int idx = tid; idx < E * E; idx += NT) {
+      const int r = idx / E, c = idx - r * E;
+      V[r * lda + c] = (r == c) ? 1.0 : 0.0;
+    }
+  }
+  __syncthreads();
+  sort_vals<NT>(lam_raw, E, lam, perm, finite);
+  __syncthreads();
+  if (tid == 0) {
+    int over = 0;
+    const int r = truncation_rank_dev(lam, E, tau2, cap, &over);
+    iscr[2] = r;
+    so.ranks[k] = r;
+    if (so.status) {
+      if (!finite) atomicOr(so.status, QTT_STATUS_NONFINITE);
+      if (over && so.lib_capped) atomicOr(so.status, QTT_STATUS_RANKCAP);
+    }
+  }
+  if (so.sv) {
+    for (int i = tid; i < kSvStride; i += NT) {
+      const double l = (i < E) ? lam[i] : 0.0;
+      so.sv[(size_t)(k - 1) * kSvStride + i] = l > 0.0 ? sqrt(l) : 0.0;
+    }
+  }
+  __syncthreads();
+  return iscr[2];
+}
+
+// ------------------------------------------------------------- level eig
+// Steps 1..L from the Gram GZ (64 x 64) of the samples viewed as (N/64) x 64.
+// Writes cores 1..L, ranks 1..L, tau^2 (scal[1]) and Phi_L (64 x r_L) to umat.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_level_eig(const double* gram, int L, int D, double eps,
+                                                    const Meta meta, T* cores, double* scal,
+                                                    double* umat, StepOut so) {
+  constexpr int NT = 1024, W = 64, LDA = 65;
+  extern __shared__ double smem[];
+  double* GZ = smem;                 // 64*64
+  double* A = GZ + W * W;            // 65*65
+  double* V = A + LDA * LDA;         // 65*65
+  double* T1 = V + LDA * LDA;        // 64*64 (also Phi_k scratch)
+  double* Phi = T1 + W * W;          // 32*32
+  double* lam = Phi + 32 * 32;       // 65
+  double* cs = lam + 72;             // 2*33 -> 72
+  int* perm = (int*)(cs + 72);       // 65
+  int* iscr = perm + 72;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < W * W; e += NT) GZ[e] = gram[e];
+  if (tid == 0) {
+    Phi[0] = 1.0;
+    so.ranks[0] = 1;
+  }
+  __syncthreads();
+  double nrm2 = 0.0;
+  for (int i = 0; i < W; ++i) nrm2 += GZ[i * W + i];
+  const double tau2 = (D > 1) ? eps * eps * nrm2 / (double)(D - 1) : 0.0;
+  if (tid == 0) {
+    scal[0] = nrm2;
+    scal[1] = tau2;
+  }
+  int rp = 1;  // r_{k-1}
+  for (int k = 1; k <= L; ++k) {
+    const int w = 1 << k, half = w >> 1;
+    const int m = 2 * rp;
+    // T1 = G_k P_k  (w x m); G_k[c][c'] = sum_h GZ[c + h w][c' + h w]
+    const int reps = W / w;
+    for (int e = tid; e < w * m; e += NT) {
+      const int c = e / m, col = e - c * m;
+      const int i = col / rp, a = col - i * rp;
+      double s = 0.0;
+      for (int cl = 0; cl < half; ++cl) {
+        const int cc = cl + half * i;
+        double g = 0.0;
+        for (int h = 0; h < reps; ++h) g += GZ[(c + h * w) * W + cc + h * w];
+        s = fma(g, Phi[cl * 32 + a], s);
+      }
+      T1[c * m + col] = s;
+    }
+    __syncthreads();
+    // A = P_k^T T1  (m x m)
+    for (int e = tid; e < m * m; e += NT) {
+      const int row = e / m, col = e - row * m;
+      const int i = row / rp, a = row - i * rp;
+      double s = 0.0;
+      for (int cl = 0; cl < half; ++cl) s = fma(Phi[cl * 32 + a], T1[(cl + half * i) * m + col], s);
+      A[row * LDA + col] = s;
+    }
+    __syncthreads();
+    const int r =
+        solve_and_truncate<NT>(A, V, m, LDA, cs, iscr, lam, perm, tau2, meta.caps[k], k, so);
+    // core k = V[:, perm[:r]]
+    {
+      const int total = rp * 2 * r;
+      for (int e = tid; e < total; e += NT) {
+        const int b = e % r, ai = e / r;
+        const int i = ai & 1, a = ai >> 1;
+        cores[meta.offs[k - 1] + e] = (T)V[(a + rp * i) * LDA + perm[b]];
+      }
+    }
+    // Phi_k = P_k U_k  (w x r) into T1
+    for (int e = tid; e < w * r; e += NT) {
+      const int c = e / r, b = e - c * r;
+      const int i = c / half, cl = c - i * half;
+      double s = 0.0;
+      for (int a = 0; a < rp; ++a) s = fma(Phi[cl * 32 + a], V[(a + rp * i) * LDA + perm[b]], s);
+      T1[c * r + b] = s;
+    }
+    __syncthreads();
+    if (k < L) {
+      for (int e = tid; e < w * r; e += NT) {
+        const int c = e / r, b = e - c * r;
+        Phi[c * 32 + b] = T1[e];
+      }
+    } else {
+      for (int e = tid; e < w * r; e += NT) umat[e] = T1[e];
+    }
+    __syncthreads();
+    rp = r;
+  }
+}
+
+// --------------------------------------------------------- project + Gram
+// Y = A U for A (rowsA x WA, row-major) and U (WA x r); Y is written to X
+// (row-major, r columns) and is the next remainder; X_next rows pair two Y
+// rows.  Partial Gram (2r x 2r, square stride mstride) per block when
+// do_gram.  WA is either fixed (wa_fixed > 0) or 2*ranks[kin-1].
+template <typename T, int GEN, int TS>
+__global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, int nk,
+                                                      long long rowsA, int wa_fixed,
+                                                      const int32_t* ranks, int kin,
+                                                      const double* U, T* Xout, int do_gram,
+                                                      double* partials, int pstride,
+                                                      int mstride) {
+  constexpr int SR = 32;
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x;
+  const int WA = wa_fixed > 0 ? wa_fixed : 2 * ranks[kin - 1];
+  const int r = ranks[kin];
+  const int M = 2 * r;
+  double* Us = smem;              // WA*r
+  double* As = Us + WA * r;       // SR*WA
+  double* Ys = As + SR * WA;      // SR*r
+  for (int e = tid; e < WA * r; e += 256) Us[e] = U[e];
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[TS][TS];
+#pragma unroll
+  for (int a = 0; a < TS; ++a)
+#pragma unroll
+    for (int b = 0; b < TS; ++b) acc[a][b] = 0.0;
+  __syncthreads();
+  const long long nstage = (rowsA + SR - 1) / SR;
+  for (long long sidx = blockIdx.x; sidx < nstage; sidx += gridDim.x) {
+    const long long r0 = sidx * SR;
+    const int nr = (int)((rowsA - r0) < SR ? (rowsA - r0) : SR);
+    for (int e = tid; e < nr * WA; e += 256) As[e] = sample<T, GEN>(Ain, r0 * WA + e, B, nk);
+    __syncthreads();
+    for (int e = tid; e < nr * r; e += 256) {
+      const int row = e / r, col = e - row * r;
+      double s = 0.0;
+      for (int c = 0; c < WA; ++c) s = fma(As[row * WA + c], Us[c * r + col], s);
+      Ys[e] = s;
+      Xout[r0 * r + e] = (T)s;
+    }
+    __syncthreads();
+    if (do_gram) {
+      const int nx = nr >> 1;
+      for (int b = 0; b < nx; ++b) {
+        const double* xr = Ys + 2 * b * r;
+        double xa[TS], xb[TS];
+#pragma unroll
+        for (int a = 0; a < TS; ++a) {
+          const int i = ty * TS + a;
+          xa[a] = i < M ? xr[i] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < TS; ++c) {
+          const int j = tx * TS + c;
+          xb[c] = j < M ? xr[j] : 0.0;
+        }
+#pragma unroll
+        for (int a = 0; a < TS; ++a)
+#pragma unroll
+          for (int c = 0; c < TS; ++c) acc[a][c] = fma(xa[a], xb[c], acc[a][c]);
+      }
+    }
+    __syncthreads();
+  }
+  if (do_gram) {
+    double* P = partials + (size_t)blockIdx.x * pstride;
+#pragma unroll
+    for (int a = 0; a < TS; ++a)
+#pragma unroll
+      for (int c = 0; c < TS; ++c) {
+        const int i = ty * TS + a, j = tx * TS + c;
+        if (i < mstride && j < mstride) P[i * mstride + j] = acc[a][c];
+      }
+  }
+}
+
+// --------------------------------------------------------------- eig step
+// Step k from the reduced Gram (M x M, stride mstride), M = 2 r_{k-1}.
+// Writes core k, ranks[k] and U_k (M x r_k, row-major) to umat.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_eig_step(const double* gram, int mstride, int k,
+                                                   const double* scal, int cap_k, T* cores,
+                                                   long long off_k, double* umat,
+                                                   double* gA, double* gV, StepOut so) {
+  constexpr int NT = 1024;
+  extern __shared__ double smem[];
+  const int tid = threadIdx.x;
+  const int rp = so.ranks[k - 1];
+  const int M = 2 * rp;
+  double *A, *V;
+  int lda;
+  double* lam;
+  if (M <= kEigLds) {
+    lda = kEigLds + 1;
+    A = smem;
+    V = A + lda * lda;
+    lam = V + lda * lda;
+  } else {
+    lda = kMaxM + 1;
+    A = gA;
+    V = gV;
+    lam = smem;
+  }
+  double* cs = lam + kMaxM + 8;
+  int* perm = (int*)(cs + kMaxM + 8);
+  int* iscr = perm + kMaxM + 8;
+  for (int e = tid; e < M * M; e += NT) {
+    const int i = e / M, j = e - i * M;
+    A[i * lda + j] = gram[i * mstride + j];
+  }
+  __syncthreads();
+  const double tau2 = scal[1];
+  const int r = solve_and_truncate<NT>(A, V, M, lda, cs, iscr, lam, perm, tau2, cap_k, k, so);
+  for (int e = tid; e < M * r; e += NT) {
+    const int c = e / r, b = e - c * r;
+    umat[e] = V[c * lda + perm[b]];
+  }
+  const int total = rp * 2 * r;
+  for (int e = tid; e < total; e += NT) {
+    const int b = e % r, ai = e / r;
+    const int i = ai & 1, a = ai >> 1;
+    cores[off_k + e] = (T)V[(a + rp * i) * lda + perm[b]];
+  }
+}
+
+// -------------------------------------------------------------------- tail
+// Finish the sweep from step k0 in one workgroup.  X_{k0} (n x m) comes from
+// Xin (k0 > 1) or from the samples (k0 == 1, m = 2).  With k0 == 1 the norm
+// and tau^2 are computed here; otherwise scal[1] holds tau^2.  gen_scale:
+// divide the last core by scal[2] (generator normalisation).
+template <typename T, int GEN>
+__global__ void __launch_bounds__(1024) k_tail(const T* Xin, double B, int nk, int k0, int D,
+                                               double eps, const Meta meta, T* cores,
+                                               double* scal, int gen_scale, StepOut so,
+                                               int32_t* iflags) {
+  constexpr int NT = 1024, LDA = kEigLds + 1;
+  extern __shared__ double smem[];
+  double* X = smem;                   // kTailElems
+  double* A = X + kTailElems;         // LDA*LDA  (also Y after the eigen solve)
+  double* V = A + LDA * LDA;          // LDA*LDA
+  double* lam = V + LDA * LDA;        // 72
+  double* cs = lam + 72;              // 72
+  double* red = cs + 72;              // NT
+  int* perm = (int*)(red + NT);       // 72
+  int* iscr = perm + 72;              // 8 + pair table (136)
+  const int tid = threadIdx.x;
+  int n = 1 << (D - k0);
+  int rp = (k0 == 1) ? 1 : so.ranks[k0 - 1];
+  int m = 2 * rp;
+  double tau2;
+  if (k0 == 1) {
+    const long long N = 1LL << D;
+    double s2 = 0.0, s1 = 0.0;
+    int fin = 1;
+    for (long long e = tid; e < N; e += NT) {
+      const double v = sample<T, GEN>(Xin, e, B, nk);
+      fin &= finite_d(v);
+      X[e] = v;
+      s2 += v * v;
+      s1 += v;
+    }
+    if (!fin) atomicOr(iflags, 1);
+    red[tid] = s2;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    const double nrm2 = red[0];
+    __syncthreads();
+    red[tid] = s1;
+    __syncthreads();
+    for (int s = NT / 2; s > 0; s >>= 1) {
+      if (tid < s) red[tid] += red[tid + s];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      scal[0] = nrm2;
+      scal[2] = red[0];
+      scal[1] = (D > 1) ? eps * eps * nrm2 / (double)(D - 1) : 0.0;
+      so.ranks[0] = 1;
+    }
+    __syncthreads();
+    tau2 = scal[1];
+  } else {
+    for (int e = tid; e < n * m; e += NT) X[e] = (double)Xin[e];
+    tau2 = scal[1];
+    __syncthreads();
+  }
+  constexpr int kPer = kTailElems / NT;  // remainder entries per thread
+  for (int k = k0; k <= D - 1; ++k) {
+    const bool dual = n < m;
+    const int E = dual ? n : m;
+    // Gram (primal X^T X or dual X X^T)
+    for (int e = tid; e < E * E; e += NT) {
+      const int i = e / E, j = e - i * E;
+      double s = 0.0;
+      if (!dual) {
+        for (int b = 0; b < n; ++b) s = fma(X[b * m + i], X[b * m + j], s);
+      } else {
+        for (int c = 0; c < m; ++c) s = fma(X[i * m + c], X[j * m + c], s);
+      }
+      A[i * LDA + j] = s;
+    }
+    __syncthreads();
+    const int r =
+        solve_and_truncate<NT>(A, V, E, LDA, cs, iscr, lam, perm, tau2, meta.caps[k], k, so);
+    const long long off = meta.offs[k - 1];
+    const int total = rp * 2 * r;
+    double yv[kPer];
+    if (!dual) {
+      for (int e = tid; e < total; e += NT) {
+        const int b = e % r, ai = e / r;
+        const int i = ai & 1, a = ai >> 1;
+        cores[off + e] = (T)V[(a + rp * i) * LDA + perm[b]];
+      }
+      // Y = X U (n x r), held in registers until every thread has read X
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int e = tid + j * NT;
+        double s = 0.0;
+        if (e < n * r) {
+          const int row = e / r, b = e - row * r;
+          const int col = perm[b];
+          for (int c = 0; c < m; ++c) s = fma(X[row * m + c], V[c * LDA + col], s);
+        }
+        yv[j] = s;
+      }
+    } else {
+      // U[:, b] = X^T v_b / sigma_b, Y[:, b] = sigma_b v_b
+      for (int e = tid; e < total; e += NT) {
+        const int b = e % r, ai = e / r;
+        const int i = ai & 1, a = ai >> 1;
+        const int c = a + rp * i;
+        const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
+        double s = 0.0;
+        for (int row = 0; row < n; ++row) s = fma(X[row * m + c], V[row * LDA + perm[b]], s);
+        cores[off + e] = (T)(sg > 1e-300 ? s / sg : 0.0);
+      }
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int e = tid + j * NT;
+        double s = 0.0;
+        if (e < n * r) {
+          const int row = e / r, b = e - row * r;
+          const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
+          s = sg * V[row * LDA + perm[b]];
+        }
+        yv[j] = s;
+      }
+    }
+    __syncthreads();
+    // next remainder: Y (n x r) read as (n/2) x (2r)
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+      const int e = tid + j * NT;
+      if (e < n * r) X[e] = yv[j];
+    }
+    __syncthreads();
+    n >>= 1;
+    rp = r;
+    m = 2 * r;
+  }
+  // last core (r_{D-1}, 2, 1): core[a*2 + i] = X_D[i, a] where X holds Y (2 x r)
+  const double scale = (gen_scale && scal[2] != 0.0) ? 1.0 / scal[2] : 1.0;
+  const long long off = meta.offs[D - 1];
+  for (int e = tid; e < 2 * rp; e += NT) {
+    const int a = e >> 1, i = e & 1;
+    cores[off + e] = (T)(X[i * rp + a] * scale);
+  }
+  if (tid == 0) so.ranks[D] = 1;
+}
+
+// ----------------------------------------------------------- final scaling
+// Scale the last core by 1/scal[2] (used when the tail did not run the
+// generator itself).
+template <typename T>
+__global__ void k_scale_last(T* cores, long long off, const int32_t* ranks, int D,
+                             const double* scal) {
+  const int rp = ranks[D - 1];
+  const double s = scal[2] != 0.0 ? 1.0 / scal[2] : 1.0;
+  for (int e = threadIdx.x; e < 2 * rp; e += blockDim.x) cores[off + e] = (T)((double)cores[off + e] * s);
+}
+
+__global__ void k_flag_status(const int32_t* iflags, int32_t* status) {
+  if (threadIdx.x == 0 && status && iflags[0]) atomicOr(status, QTT_STATUS_NONFINITE);
+}
+
+// =================================================================== host
+static size_t lds_level_eig() {
+  return sizeof(double) * (64 * 64 + 2 * 65 * 65 + 64 * 64 + 32 * 32 + 72 + 72) +
+         sizeof(int) * (72 + 8 + 256);
+}
+static size_t lds_eig_step() {
+  const int lda = kEigLds + 1;
+  return sizeof(double) * (2 * lda * lda + 3 * (kMaxM + 8)) + sizeof(int) * (kMaxM + 8 + 8 + 256);
+}
+static size_t lds_tail() {
+  const int lda = kEigLds + 1;
+  return sizeof(double) * (kTailElems + 2 * lda * lda + 72 + 72 + 1024) +
+         sizeof(int) * (72 + 8 + 256);
+}
+static size_t lds_project(int wa, int r) {
+  return sizeof(double) * ((size_t)wa * r + 32 * (size_t)wa + 32 * (size_t)r);
+}
+
+int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p) {
+  DecompPlan& P = *p;
+  P.D = D;
+  P.dtype = dtype;
+  P.rcap = rcap;
+  for (int k = 0; k <= D; ++k) {
+    int c = rcap;
+    const int lo = k < 30 ? (1 << k) : (1 << 30);
+    const int hi = (D - k) < 30 ? (1 << (D - k)) : (1 << 30);
+    if (lo < c) c = lo;
+    if (hi < c) c = hi;
+    P.cap[k] = (k == 0 || k == D) ? 1 : c;
+  }
+  const long long N = 1LL << D;
+  P.use_level = (D > 1 && N > kTailElems) ? 1 : 0;
+  // first tail step
+  P.tail_k = 1;
+  if (P.use_level) {
+    int k = kLevel + 1;
+    while (k < D && !((1LL << (D - k)) * 2LL * P.cap[k - 1] <= kTailElems)) ++k;
+    P.tail_k = k;
+  }
+  int mcap = 2;
+  for (int k = 1; k < D; ++k) mcap = mcap > 2 * P.cap[k - 1] ? mcap : 2 * P.cap[k - 1];
+  if (mcap < 64) mcap = 64;
+  P.gstride = mcap;
+  P.pstride = mcap * mcap;
+  Arena ar(ws);
+  P.scal = ar.take<double>(16);
+  // [0] non-finite flag, [16+k] Jacobi sweeps of step k, [80+4k..] optional timings
+  P.iflags = ar.take<int32_t>(16 + 64 + 256);
+  P.gram = ar.take<double>((size_t)mcap * mcap);
+  P.umat = ar.take<double>((size_t)kMaxM * kMaxRank);
+  P.gpart_sum = ar.take<double>(kMaxPartials);
+  if (P.use_level) {
+    P.partials = ar.take<double>((size_t)kMaxPartials * P.pstride);
+    P.eigA = ar.take<double>((size_t)(kMaxM + 1) * (kMaxM + 1));
+    P.eigV = ar.take<double>((size_t)(kMaxM + 1) * (kMaxM + 1));
+    const size_t es = elem_size(dtype);
+    char* b0 = ar.take<char>((size_t)N * es);
+    char* b1 = ar.take<char>((size_t)N * es);
+    P.xbuf[0] = b0;
+    P.xbuf[1] = b1;
+  } else {
+    P.partials = nullptr;
+    P.eigA = P.eigV = nullptr;
+    P.xbuf[0] = P.xbuf[1] = nullptr;
+  }
+  P.ws_bytes = ar.size();
+  return QTT_OK;
+}
+
+template <typename T, int GEN>
+static void set_attrs() {
+  hipFuncSetAttribute((const void*)k_level_eig<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds_level_eig());
+  hipFuncSetAttribute((const void*)k_eig_step<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds_eig_step());
+  hipFuncSetAttribute((const void*)k_tail<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds_tail());
+  hipFuncSetAttribute((const void*)k_tail<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds_tail());
+  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 1>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 2>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 4>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 8>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 1>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 2>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 4>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 8>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+}
+
+template <typename T, int GEN>
+static int launch_project(const T* Ain, const Source& src, long long rowsA, int wa_fixed,
+                          int wa_cap, const int32_t* ranks, int kin, int rcap_out,
+                          const double* U, T* Xout, int do_gram, const DecompPlan& P,
+                          int mstride, int* nparts, hipStream_t stream) {
+  constexpr int SR = 32;
+  long long nstage = (rowsA + SR - 1) / SR;
+  int blocks = (int)(nstage < kMaxPartials ? nstage : kMaxPartials);
+  if (blocks < 1) blocks = 1;
+  *nparts = blocks;
+  const size_t lds = lds_project(wa_cap, rcap_out);
+  const int Mc = 2 * rcap_out;
+  ProbeScope _ps(QTT_K_PROJECT, stream);
+  if (Mc <= 16) {
+    k_project_gram<T, GEN, 1><<<blocks, 256, lds, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
+                                                            ranks, kin, U, Xout, do_gram,
+                                                            P.partials, P.pstride, mstride);
+  } else if (Mc <= 32) {
+    k_project_gram<T, GEN, 2><<<blocks, 256, lds, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
+                                                            ranks, kin, U, Xout, do_gram,
+                                                            P.partials, P.pstride, mstride);
+  } else if (Mc <= 64) {
+    k_project_gram<T, GEN, 4><<<blocks, 256, lds, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
+                                                            ranks, kin, U, Xout, do_gram,
+                                                            P.partials, P.pstride, mstride);
+  } else {
+    k_project_gram<T, GEN, 8><<<blocks, 256, lds, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
+                                                            ranks, kin, U, Xout, do_gram,
+                                                            P.partials, P.pstride, mstride);
+  }
+  QTT_LAUNCH_CHECK();
+  return QTT_OK;
+}
+
+template <typename T, int GEN>
+static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
+                           const TensorDev& out, double* sv, hipStream_t stream) {
+  static bool attrs = false;
+  if (!attrs) {
+    set_attrs<T, GEN>();
+    attrs = true;
+  }
+  const int D = P.D;
+  const T* x = static_cast<const T*>(src.x);
+  T* cores = static_cast<T*>(out.cores);
+  StepOut so;
+  so.ranks = out.ranks;
+  so.status = out.status;
+  so.sv = sv;
+  so.lib_capped = P.rcap >= kMaxRank ? 1 : 0;
+  so.dbg = P.iflags + 16;
+  Meta meta;
+  for (int k = 0; k <= QTT_MAXD; ++k) {
+    meta.caps[k] = k <= D ? P.cap[k] : 0;
+    meta.offs[k] = k <= D ? out.off[k] : 0;
+  }
+  QTT_HIP_CHECK(hipMemsetAsync(P.iflags, 0, sizeof(int32_t) * 16, stream));
+  if (D == 1) {
+    {
+      ProbeScope _ps(QTT_K_OTHER, stream);
+      k_single<T, GEN><<<1, 64, 0, stream>>>(x, src.B, src.nk, cores, out.ranks, P.scal, out.status);
+    }
+    QTT_LAUNCH_CHECK();
+    return QTT_OK;
+  }
+  if (!P.use_level) {
+    {
+      ProbeScope _ps(QTT_K_TAIL, stream);
+      k_tail<T, GEN><<<1, 1024, lds_tail(), stream>>>(x, src.B, src.nk, 1, D, eps, meta, cores,
+                                                     P.scal, src.gen, so, P.iflags);
+    }
+    QTT_LAUNCH_CHECK();
+    {
+      ProbeScope _ps(QTT_K_OTHER, stream);
+      k_flag_status<<<1, 64, 0, stream>>>(P.iflags, out.status);
+    }
+    QTT_LAUNCH_CHECK();
+    return QTT_OK;
+  }
+  const long long N = 1LL << D;
+  const int L = kLevel;
+  // 1. Gram of the samples viewed as (N/64) x 64
+  {
+    const long long rows = N >> L;
+    long long nstage = (rows + 31) / 32;
+    int blocks = (int)(nstage < kMaxPartials ? nstage : kMaxPartials);
+    {
+      ProbeScope _ps(QTT_K_LEVEL_GRAM, stream);
+      k_level_gram<T, GEN><<<blocks, 256, 0, stream>>>(x, src.B, src.nk, rows, P.partials, P.pstride,
+                                                     P.gpart_sum, P.iflags);
+    }
+    QTT_LAUNCH_CHECK();
+    {
+      ProbeScope _ps(QTT_K_REDUCE, stream);
+      k_reduce<<<(64 * 64 + 63) / 64, 256, 0, stream>>>(P.partials, P.pstride, blocks, 64 * 64,
+                                                         P.gram, P.gpart_sum, P.scal);
+    }
+    QTT_LAUNCH_CHECK();
+  }
+  // 2. steps 1..L
+  {
+    ProbeScope _ps(QTT_K_LEVEL_EIG, stream);
+    k_level_eig<T><<<1, 1024, lds_level_eig(), stream>>>(P.gram, L, D, eps, meta, cores, P.scal,
+                                                       P.umat, so);
+  }
+  QTT_LAUNCH_CHECK();
+  // 3. X_{L+1} = Z_L Phi_L, Gram of X_{L+1}
+  int cur = 0;
+  int k = L + 1;
+  int nparts = 0;
+  {
+    const bool tail_now = (k >= P.tail_k);
+    const int mstride = 2 * P.cap[L];
+    int rc = launch_project<T, GEN>(x, src, N >> L, 1 << L, 1 << L, out.ranks, L, P.cap[L],
+                                    P.umat, static_cast<T*>(P.xbuf[cur]), tail_now ? 0 : 1, P,
+                                    mstride, &nparts, stream);
+    if (rc) return rc;
+  }
+  while (k < P.tail_k) {
+    // Gram of X_k is in the partials (stride 2 cap_{k-1})
+    const int mstride = 2 * P.cap[k - 1];
+    {
+      ProbeScope _ps(QTT_K_REDUCE, stream);
+      k_reduce<<<(mstride * mstride + 63) / 64, 256, 0, stream>>>(
+        P.partials, P.pstride, nparts, mstride * mstride, P.gram, nullptr, nullptr);
+    }
+    QTT_LAUNCH_CHECK();
+    {
+      ProbeScope _ps(QTT_K_EIG_STEP, stream);
+      k_eig_step<T><<<1, 1024, lds_eig_step(), stream>>>(P.gram, mstride, k, P.scal, P.cap[k], cores,
+                                                       out.off[k - 1], P.umat, P.eigA, P.eigV, so);
+    }
+    QTT_LAUNCH_CHECK();
+    // X_{k+1} = X_k U_k
+    const long long rowsA = 1LL << (D - k);
+    const bool tail_next = (k + 1 >= P.tail_k);
+    const int mnext = 2 * P.cap[k];
+    int rc = launch_project<T, 0>(static_cast<const T*>(P.xbuf[cur]), src, rowsA, 0,
+                                  2 * P.cap[k - 1], out.ranks, k, P.cap[k], P.umat,
+                                  static_cast<T*>(P.xbuf[cur ^ 1]), tail_next ? 0 : 1, P, mnext,
+                                  &nparts, stream);
+    if (rc) return rc;
+    cur ^= 1;
+    ++k;
+  }
+  {
+    ProbeScope _ps(QTT_K_TAIL, stream);
+    k_tail<T, 0><<<1, 1024, lds_tail(), stream>>>(static_cast<const T*>(P.xbuf[cur]), src.B,
+                                                src.nk, k, D, eps, meta, cores, P.scal, 0, so,
+                                                P.iflags);
+  }
+  QTT_LAUNCH_CHECK();
+  if (src.gen) {
+    {
+      ProbeScope _ps(QTT_K_OTHER, stream);
+      k_scale_last<T><<<1, 256, 0, stream>>>(cores, out.off[D - 1], out.ranks, D, P.scal);
+    }
+    QTT_LAUNCH_CHECK();
+  }
+  {
+    ProbeScope _ps(QTT_K_OTHER, stream);
+    k_flag_status<<<1, 64, 0, stream>>>(P.iflags, out.status);
+  }
+  QTT_LAUNCH_CHECK();
+  return QTT_OK;
+}
+
+int run_decompose(const DecompPlan& P, const Source& src, double eps, const TensorDev& out,
+                  double* sv, hipStream_t stream) {
+  if (P.dtype == QTT_F64) {
+    return src.gen ? run_decompose_t<double, 1>(P, src, eps, out, sv, stream)
+                   : run_decompose_t<double, 0>(P, src, eps, out, sv, stream);
+  }
+  return src.gen ? run_decompose_t<float, 1>(P, src, eps, out, sv, stream)
+                 : run_decompose_t<float, 0>(P, src, eps, out, sv, stream);
+}
+
+}  // namespace qtt

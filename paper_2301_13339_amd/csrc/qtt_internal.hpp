@@ -1,0 +1,150 @@
+// Internal declarations shared by the HIP translation units of libqtt.
+//
+// Device helpers: the one-workgroup FP64 Jacobi eigensolver used for every
+// truncated SVD (through the Gram matrix of the unfolding), the truncation
+// rule of Algorithm 1 with the max-rank modification (1), and a small host
+// arena that carves the caller's workspace.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "qtt.h"
+
+namespace qtt {
+
+// ----------------------------------------------------------------- limits
+constexpr int kMaxRank = QTT_MAX_RANK;       // largest TT-rank of a decomposition
+constexpr int kMaxM = 2 * kMaxRank;          // largest unfolding row count m_k = 2 r_{k-1}
+constexpr int kLevel = 6;                    // levels handled from one data Gram (2^6 = 64)
+constexpr int kTailElems = 8192;             // remainder size a single workgroup finishes in LDS
+constexpr int kEigLds = 64;                  // eigen problems up to this size live in LDS
+constexpr int kMaxPartials = 128;            // partial Gram matrices per streaming pass
+constexpr int kSvStride = 2 * kMaxRank;      // row stride of the optional singular-value output
+
+// -------------------------------------------------------------- host arena
+struct Arena {
+  char* base;
+  size_t off;
+  explicit Arena(void* b) : base(static_cast<char*>(b)), off(0) {}
+  template <class T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base ? base + off : nullptr);
+    off += n * sizeof(T);
+    return p;
+  }
+  size_t size() const { return (off + 255) & ~size_t(255); }
+};
+
+inline size_t elem_size(int dtype) { return dtype == QTT_F64 ? 8 : 4; }
+
+// offsets (elements) of the cores for capacities cap[0..d]
+inline size_t core_offset(const int32_t* cap, int k) {  // k is 0-based core index
+  size_t off = 0;
+  for (int j = 0; j < k; ++j) off += size_t(cap[j]) * 2 * size_t(cap[j + 1]);
+  return off;
+}
+
+// Device-side description of a QTT tensor: capacities are baked into the
+// per-core offsets; actual ranks are read from device memory.
+struct TensorDev {
+  int d;
+  int32_t* ranks;
+  void* cores;
+  int32_t* status;
+  long long off[QTT_MAXD + 1];  // element offsets of cores 0..d-1 (off[d] = total)
+  int cap[QTT_MAXD + 1];
+};
+
+inline TensorDev make_dev(const qtt_tensor* t) {
+  TensorDev o;
+  o.d = t->d;
+  o.ranks = t->ranks;
+  o.cores = t->cores;
+  o.status = t->status;
+  long long off = 0;
+  for (int k = 0; k <= t->d; ++k) {
+    o.cap[k] = t->cap[k];
+    o.off[k] = off;
+    if (k < t->d) off += (long long)t->cap[k] * 2 * t->cap[k + 1];
+  }
+  return o;
+}
+
+// ------------------------------------------------------------ launch probe
+// Records a HIP event pair around launches of the probed class (see
+// qtt_probe_start).  Cheap no-op when the class is not probed.
+void probe_pre(int cls, hipStream_t s);
+void probe_post(int cls, hipStream_t s);
+struct ProbeScope {
+  int cls;
+  hipStream_t s;
+  ProbeScope(int c, hipStream_t st) : cls(c), s(st) { probe_pre(c, st); }
+  ~ProbeScope() { probe_post(cls, s); }
+};
+
+// ------------------------------------------------------------ host errors
+void set_hip_error(hipError_t e);
+#define QTT_HIP_CHECK(expr)                     \
+  do {                                          \
+    hipError_t _e = (expr);                     \
+    if (_e != hipSuccess) {                     \
+      ::qtt::set_hip_error(_e);                 \
+      return QTT_EHIP;                          \
+    }                                           \
+  } while (0)
+#define QTT_LAUNCH_CHECK()                      \
+  do {                                          \
+    hipError_t _e = hipGetLastError();          \
+    if (_e != hipSuccess) {                     \
+      ::qtt::set_hip_error(_e);                 \
+      return QTT_EHIP;                          \
+    }                                           \
+  } while (0)
+
+// ------------------------------------------------------- decomposition API
+// Sample source for the decomposition sweep: a stored vector, or the sinc
+// generator evaluated on the fly.
+struct Source {
+  const void* x;     // stored samples (nullptr when generated)
+  int gen;           // 1: sinc generator of a 2^(D-1)-sample kernel grid
+  double B;          // generator bandwidth
+  int nk;            // generator: log2 of the kernel grid size (D - 1)
+};
+
+struct DecompPlan {
+  int D;             // modes
+  int dtype;
+  int rcap;          // effective rank cap
+  int cap[QTT_MAXD + 1];
+  int use_level;     // 1 when the level start is used
+  int tail_k;        // first step handled by the tail kernel (1-based)
+  // workspace pieces
+  double* scal;      // [0]=||x||^2, [1]=tau^2, [2]=generator sum, [3..] reserved
+  int32_t* iflags;   // [0] non-finite flag
+  double* partials;  // kMaxPartials * pstride
+  double* gram;      // reduced Gram, gstride*gstride
+  double* umat;      // projection matrix (rows x r)
+  double* eigA;      // global scratch for eigen problems larger than kEigLds
+  double* eigV;
+  void* xbuf[2];     // remainder buffers (elements of dtype)
+  double* gpart_sum; // partial sums of generator samples
+  size_t ws_bytes;
+  int pstride;       // doubles per partial Gram
+  int gstride;       // row stride of the reduced Gram
+};
+
+int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p);
+int run_decompose(const DecompPlan& p, const Source& src, double eps, const TensorDev& out,
+                  double* sv, hipStream_t stream);
+
+// --------------------------------------------------------------- other ops
+int plan_full(int d, const int32_t* cap, int dtype, void* ws, size_t* ws_bytes, void** bufs);
+int run_full(const TensorDev& t, int dtype, void* out, void* ws, hipStream_t stream);
+
+int run_conv(const TensorDev& f, const TensorDev* w, int n_axes, const int32_t* axis_modes,
+             const TensorDev& y, int dtype, hipStream_t stream);
+
+}  // namespace qtt
