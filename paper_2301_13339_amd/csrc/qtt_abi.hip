@@ -311,6 +311,7 @@ static void plan_round(int d, const int32_t* y_cap, int rcap, int dtype, void* w
 int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int method,
                     int32_t* z_cap, size_t* ws_bytes, size_t* core_elems) {
   if (d < 1 || d > kMaxModes || !y_cap || !dtype_ok(dtype) || max_rank < 0) return QTT_EINVAL;
+  if (method < QTT_ROUND_EXACT || method > QTT_ROUND_SKETCH_BF16) return QTT_EINVAL;
   if (method != QTT_ROUND_EXACT) return QTT_ENOTSUP;
   RoundPlan rp;
   plan_round(d, y_cap, eff_rank(max_rank), dtype, nullptr, &rp);
@@ -328,6 +329,7 @@ int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_
   if (check_tensor_in(y) || y->d > kMaxModes || !(eps >= 0.0) || !isfinite(eps) || max_rank < 0 ||
       !ws)
     return QTT_EINVAL;
+  if (method < QTT_ROUND_EXACT || method > QTT_ROUND_SKETCH_BF16) return QTT_EINVAL;
   if (method != QTT_ROUND_EXACT) return QTT_ENOTSUP;
   const int d = y->d;
   RoundPlan rp;
