@@ -182,13 +182,28 @@ struct StepOut {
   int32_t* dbg;  // Jacobi sweeps per step (workspace diagnostics)
 };
 
-// eigen-solve the Gram in A (E x E), choose the rank, fill lam/perm.
-// Returns r (also in *r_sh).  Must be called by all threads.
-template <int NT>
-__device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* cs, int* iscr,
+// Eigen-solve the Gram matrix in A (E x E), choose the rank, and leave the
+// kept eigenvectors in the first r columns of V (descending eigenvalues):
+// lam[0..E) = eigenvalues in non-increasing order, perm[b] = b.  sx: scratch
+// of kEigScratch doubles.  Returns r.  Must be called by all threads.
+constexpr int kEigScratch = 7 * kMaxM + 16;
+// one workgroup of 4 waves: a barrier costs ~40 cycles with 4 waves and
+// ~470 with 16 on gfx950, and every eigen step is barrier/latency bound
+constexpr int kEigThreads = 256;
+
+template <int NT, bool BIG = false>
+__device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* sx, int* iscr,
                                   double* lam, int* perm, double tau2, int cap, int k,
                                   const StepOut& so) {
   const int tid = threadIdx.x;
+  double* dg = sx;
+  double* od = dg + kMaxM;
+  double* bt = od + kMaxM;
+  double* pv = bt + kMaxM;
+  double* e2 = pv + kMaxM;
+  double* la = e2 + kMaxM;  // ascending eigenvalues
+  // the tridiagonalisation takes pv .. pv + 4 kMaxM (over e2 and la, which are
+  // used only after it) for its column and p buffers
   // finiteness of the Gram (NaN/Inf input)
   if (tid == 0) {
     double tr = 0.0;
@@ -197,19 +212,27 @@ __device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* 
   }
   __syncthreads();
   const int finite = iscr[1];
-  double* lam_raw = cs;  // scratch (>= E doubles)
+#ifdef QTT_EIG_TIMING
+  long long tt[6];
+  tt[0] = wall_clock64();
+#endif
   if (finite) {
-    const int sw = gram_eig<NT>(A, V, E, lda, lam_raw, reinterpret_cast<double*>(iscr + 8), iscr,
-                                so.dbg ? so.dbg + 64 + 4 * k : nullptr);
-    if (tid == 0 && so.dbg) so.dbg[k] = sw;
-  } else {
-    for (int idx = tid; idx < E * E; idx += NT) {
-      const int r = idx / E, c = idx - r * E;
-      V[r * lda + c] = (r == c) ? 1.0 : 0.0;
-    }
+    if (BIG && E > 64)
+      sy_tridiag<NT, BIG ? 8 : 4>(A, E, lda, dg, od, bt, pv);
+    else
+      sy_tridiag<NT, 4>(A, E, lda, dg, od, bt, pv);
+#ifdef QTT_EIG_TIMING
+    tt[1] = wall_clock64();
+#endif
+    tridiag_eigvals<NT>(dg, od, E, la, e2, pv);
   }
-  __syncthreads();
-  sort_vals<NT>(lam_raw, E, lam, perm, finite);
+#ifdef QTT_EIG_TIMING
+  tt[2] = wall_clock64();
+#endif
+  for (int i = tid; i < E; i += NT) {
+    lam[i] = finite ? la[E - 1 - i] : 0.0;
+    perm[i] = i;
+  }
   __syncthreads();
   if (tid == 0) {
     int over = 0;
@@ -228,26 +251,66 @@ __device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* 
     }
   }
   __syncthreads();
-  return iscr[2];
+  const int r = iscr[2];
+  if (!finite) {
+    for (int idx = tid; idx < E * E; idx += NT) {
+      const int a = idx / E, c = idx - a * E;
+      V[a * lda + c] = (a == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    return r;
+  }
+  // eigenvectors of T for the kept eigenvalues, one lane per vector
+  {
+    double nrm = 0.0;
+    for (int i = 0; i < E; ++i)
+      nrm = fmax(nrm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0));
+    const double tiny = 1e-300 + 1e-30 * nrm;
+    for (int b = tid; b < r; b += NT) tridiag_vec(dg, od, E, lam[b], V + b, lda, tiny);
+  }
+  __syncthreads();
+#ifdef QTT_EIG_TIMING
+  tt[3] = wall_clock64();
+#endif
+  mgs_cols<NT>(V, E, lda, r);
+#ifdef QTT_EIG_TIMING
+  tt[4] = wall_clock64();
+#endif
+  back_transform<NT>(A, bt, E, lda, V, lda, r);
+#ifdef QTT_EIG_TIMING
+  tt[5] = wall_clock64();
+  if (tid == 0 && so.dbg) {
+    so.dbg[k] = E;
+    int* tm = so.dbg + 64 + 4 * k;
+    (void)tm;
+    int* t5 = so.dbg + 64 + 5 * k;
+    t5[0] = (int)(tt[1] - tt[0]);
+    t5[1] = (int)(tt[2] - tt[1]);
+    t5[2] = (int)(tt[3] - tt[2]);
+    t5[3] = (int)(tt[4] - tt[3]);
+    t5[4] = (int)(tt[5] - tt[4]);
+  }
+#endif
+  return r;
 }
 
 // ------------------------------------------------------------- level eig
 // Steps 1..L from the Gram GZ (64 x 64) of the samples viewed as (N/64) x 64.
 // Writes cores 1..L, ranks 1..L, tau^2 (scal[1]) and Phi_L (64 x r_L) to umat.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_level_eig(const double* gram, int L, int D, double eps,
+__global__ void __launch_bounds__(kEigThreads) k_level_eig(const double* gram, int L, int D, double eps,
                                                     const Meta meta, T* cores, double* scal,
                                                     double* umat, StepOut so) {
-  constexpr int NT = 1024, W = 64, LDA = 65;
+  constexpr int NT = kEigThreads, W = 64, LDA = 65;
   extern __shared__ double smem[];
   double* GZ = smem;                 // 64*64
   double* A = GZ + W * W;            // 65*65
   double* V = A + LDA * LDA;         // 65*65
   double* T1 = V + LDA * LDA;        // 64*64 (also Phi_k scratch)
   double* Phi = T1 + W * W;          // 32*32
-  double* lam = Phi + 32 * 32;       // 65
-  double* cs = lam + 72;             // 2*33 -> 72
-  int* perm = (int*)(cs + 72);       // 65
+  double* lam = Phi + 32 * 32;       // 72
+  double* sx = lam + 72;             // kEigScratch
+  int* perm = (int*)(sx + kEigScratch);  // 72
   int* iscr = perm + 72;
   const int tid = threadIdx.x;
   for (int e = tid; e < W * W; e += NT) GZ[e] = gram[e];
@@ -292,7 +355,7 @@ __global__ void __launch_bounds__(1024) k_level_eig(const double* gram, int L, i
     }
     __syncthreads();
     const int r =
-        solve_and_truncate<NT>(A, V, m, LDA, cs, iscr, lam, perm, tau2, meta.caps[k], k, so);
+        solve_and_truncate<NT>(A, V, m, LDA, sx, iscr, lam, perm, tau2, meta.caps[k], k, so);
     // core k = V[:, perm[:r]]
     {
       const int total = rp * 2 * r;
@@ -406,11 +469,11 @@ __global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, in
 // Step k from the reduced Gram (M x M, stride mstride), M = 2 r_{k-1}.
 // Writes core k, ranks[k] and U_k (M x r_k, row-major) to umat.
 template <typename T>
-__global__ void __launch_bounds__(1024) k_eig_step(const double* gram, int mstride, int k,
+__global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, int mstride, int k,
                                                    const double* scal, int cap_k, T* cores,
                                                    long long off_k, double* umat,
                                                    double* gA, double* gV, StepOut so) {
-  constexpr int NT = 1024;
+  constexpr int NT = kEigThreads;
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int rp = so.ranks[k - 1];
@@ -429,8 +492,8 @@ __global__ void __launch_bounds__(1024) k_eig_step(const double* gram, int mstri
     V = gV;
     lam = smem;
   }
-  double* cs = lam + kMaxM + 8;
-  int* perm = (int*)(cs + kMaxM + 8);
+  double* sx = lam + kMaxM + 8;
+  int* perm = (int*)(sx + kEigScratch);
   int* iscr = perm + kMaxM + 8;
   for (int e = tid; e < M * M; e += NT) {
     const int i = e / M, j = e - i * M;
@@ -438,7 +501,8 @@ __global__ void __launch_bounds__(1024) k_eig_step(const double* gram, int mstri
   }
   __syncthreads();
   const double tau2 = scal[1];
-  const int r = solve_and_truncate<NT>(A, V, M, lda, cs, iscr, lam, perm, tau2, cap_k, k, so);
+  const int r =
+      solve_and_truncate<NT, true>(A, V, M, lda, sx, iscr, lam, perm, tau2, cap_k, k, so);
   for (int e = tid; e < M * r; e += NT) {
     const int c = e / r, b = e - c * r;
     umat[e] = V[c * lda + perm[b]];
@@ -457,18 +521,18 @@ __global__ void __launch_bounds__(1024) k_eig_step(const double* gram, int mstri
 // and tau^2 are computed here; otherwise scal[1] holds tau^2.  gen_scale:
 // divide the last core by scal[2] (generator normalisation).
 template <typename T, int GEN>
-__global__ void __launch_bounds__(1024) k_tail(const T* Xin, double B, int nk, int k0, int D,
+__global__ void __launch_bounds__(kEigThreads) k_tail(const T* Xin, double B, int nk, int k0, int D,
                                                double eps, const Meta meta, T* cores,
                                                double* scal, int gen_scale, StepOut so,
                                                int32_t* iflags) {
-  constexpr int NT = 1024, LDA = kEigLds + 1;
+  constexpr int NT = kEigThreads, LDA = kEigLds + 1;
   extern __shared__ double smem[];
   double* X = smem;                   // kTailElems
   double* A = X + kTailElems;         // LDA*LDA  (also Y after the eigen solve)
   double* V = A + LDA * LDA;          // LDA*LDA
   double* lam = V + LDA * LDA;        // 72
-  double* cs = lam + 72;              // 72
-  double* red = cs + 72;              // NT
+  double* sx = lam + 72;              // kEigScratch
+  double* red = sx + kEigScratch;     // NT
   int* perm = (int*)(red + NT);       // 72
   int* iscr = perm + 72;              // 8 + pair table (136)
   const int tid = threadIdx.x;
@@ -532,7 +596,7 @@ __global__ void __launch_bounds__(1024) k_tail(const T* Xin, double B, int nk, i
     }
     __syncthreads();
     const int r =
-        solve_and_truncate<NT>(A, V, E, LDA, cs, iscr, lam, perm, tau2, meta.caps[k], k, so);
+        solve_and_truncate<NT>(A, V, E, LDA, sx, iscr, lam, perm, tau2, meta.caps[k], k, so);
     const long long off = meta.offs[k - 1];
     const int total = rp * 2 * r;
     double yv[kPer];
@@ -616,16 +680,17 @@ __global__ void k_flag_status(const int32_t* iflags, int32_t* status) {
 
 // =================================================================== host
 static size_t lds_level_eig() {
-  return sizeof(double) * (64 * 64 + 2 * 65 * 65 + 64 * 64 + 32 * 32 + 72 + 72) +
+  return sizeof(double) * (64 * 64 + 2 * 65 * 65 + 64 * 64 + 32 * 32 + 72 + kEigScratch) +
          sizeof(int) * (72 + 8 + 256);
 }
 static size_t lds_eig_step() {
   const int lda = kEigLds + 1;
-  return sizeof(double) * (2 * lda * lda + 3 * (kMaxM + 8)) + sizeof(int) * (kMaxM + 8 + 8 + 256);
+  return sizeof(double) * (2 * lda * lda + (kMaxM + 8) + kEigScratch) +
+         sizeof(int) * (kMaxM + 8 + 8 + 256);
 }
 static size_t lds_tail() {
   const int lda = kEigLds + 1;
-  return sizeof(double) * (kTailElems + 2 * lda * lda + 72 + 72 + 1024) +
+  return sizeof(double) * (kTailElems + 2 * lda * lda + 72 + kEigScratch + kEigThreads) +
          sizeof(int) * (72 + 8 + 256);
 }
 static size_t lds_project(int wa, int r) {
@@ -662,7 +727,7 @@ int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p) {
   Arena ar(ws);
   P.scal = ar.take<double>(16);
   // [0] non-finite flag, [16+k] Jacobi sweeps of step k, [80+4k..] optional timings
-  P.iflags = ar.take<int32_t>(16 + 64 + 256);
+  P.iflags = ar.take<int32_t>(16 + 64 + 512);
   P.gram = ar.take<double>((size_t)mcap * mcap);
   P.umat = ar.take<double>((size_t)kMaxM * kMaxRank);
   P.gpart_sum = ar.take<double>(kMaxPartials);
@@ -780,7 +845,7 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
   if (!P.use_level) {
     {
       ProbeScope _ps(QTT_K_TAIL, stream);
-      k_tail<T, GEN><<<1, 1024, lds_tail(), stream>>>(x, src.B, src.nk, 1, D, eps, meta, cores,
+      k_tail<T, GEN><<<1, kEigThreads, lds_tail(), stream>>>(x, src.B, src.nk, 1, D, eps, meta, cores,
                                                      P.scal, src.gen, so, P.iflags);
     }
     QTT_LAUNCH_CHECK();
@@ -814,7 +879,7 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
   // 2. steps 1..L
   {
     ProbeScope _ps(QTT_K_LEVEL_EIG, stream);
-    k_level_eig<T><<<1, 1024, lds_level_eig(), stream>>>(P.gram, L, D, eps, meta, cores, P.scal,
+    k_level_eig<T><<<1, kEigThreads, lds_level_eig(), stream>>>(P.gram, L, D, eps, meta, cores, P.scal,
                                                        P.umat, so);
   }
   QTT_LAUNCH_CHECK();
@@ -841,7 +906,7 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
     QTT_LAUNCH_CHECK();
     {
       ProbeScope _ps(QTT_K_EIG_STEP, stream);
-      k_eig_step<T><<<1, 1024, lds_eig_step(), stream>>>(P.gram, mstride, k, P.scal, P.cap[k], cores,
+      k_eig_step<T><<<1, kEigThreads, lds_eig_step(), stream>>>(P.gram, mstride, k, P.scal, P.cap[k], cores,
                                                        out.off[k - 1], P.umat, P.eigA, P.eigV, so);
     }
     QTT_LAUNCH_CHECK();
@@ -859,7 +924,7 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
   }
   {
     ProbeScope _ps(QTT_K_TAIL, stream);
-    k_tail<T, 0><<<1, 1024, lds_tail(), stream>>>(static_cast<const T*>(P.xbuf[cur]), src.B,
+    k_tail<T, 0><<<1, kEigThreads, lds_tail(), stream>>>(static_cast<const T*>(P.xbuf[cur]), src.B,
                                                 src.nk, k, D, eps, meta, cores, P.scal, 0, so,
                                                 P.iflags);
   }

@@ -1,0 +1,501 @@
+// One-workgroup FP64 symmetric eigensolver for the Gram matrices of the
+// TT-SVD sweep (Algorithm 1): every truncated SVD is taken through
+// G = X^T X = U diag(sigma^2) U^T.
+//
+//   1. Householder tridiagonalisation G = Q T Q^T (the reflector of step j
+//      annihilates column j below the subdiagonal; two barriers per step);
+//   2. all eigenvalues of T by parallel multisection: a 16-lane group brackets
+//      one eigenvalue and narrows it 17-fold per iteration with Sturm counts
+//      (sign changes of the leading principal minors of T - x I), to an
+//      absolute width of 1e-15 ||T||;
+//   3. the caller picks the rank from the eigenvalues;
+//   4. eigenvectors of T for the kept eigenvalues only, one lane each, by a
+//      twisted factorisation of T - lambda I (top-down and bottom-up LDL^T
+//      sweeps; the twist index minimises |gamma_r|; the vector follows from
+//      the two bidiagonal factors), then modified Gram-Schmidt;
+//   5. back-transformation by the stored reflectors: U = Q Z.
+// All work is on the 2^m-entry LDS arrays of one workgroup; no global memory.
+#pragma once
+
+#include "qtt_internal.hpp"
+
+namespace qtt {
+
+// ---------------------------------------------------------- lane reductions
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double swz16_d(double x) {
+  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
+  return __hiloint2double(hi, lo);
+}
+// sum over the 16 lanes of a DPP row (all lanes of the row get the sum)
+__device__ __forceinline__ double sum16(double v) {
+  v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  return v;
+}
+// sum over the 32 lanes of a half wave
+__device__ __forceinline__ double sum32(double v) {
+  const double s = sum16(v);
+  return s + swz16_d(s);
+}
+// sum over the whole wave (uniform result)
+__device__ __forceinline__ double sum64(double v) {
+  v = sum16(v);
+  v += swz16_d(v);
+  const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
+                                    __builtin_amdgcn_readlane(__double2loint(v), 0));
+  const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
+                                    __builtin_amdgcn_readlane(__double2loint(v), 32));
+  return a + b;
+}
+
+// 1/x to FP64 accuracy from the hardware estimate (two Newton steps)
+__device__ __forceinline__ double rcp_acc(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
+// ------------------------------------------------------- tridiagonalisation
+// A (E x E symmetric, full storage, stride lda >= 16*BS, at least 16*BS
+// rows allocated, E <= 16*BS) -> T (dg, od)
+// and reflectors.  The matrix is held in registers: thread (br, bc) =
+// (tid / 16, tid % 16) owns the BS x BS block at rows br*BS.., columns
+// bc*BS.., so the 16 owners of a block row are one DPP row of a wave.  Step
+// j applies H_j = I - beta_j v v^T (v zero in entries 0..j) to the whole
+// matrix, A <- H A H, as A - v w^T - w v^T with p = beta A v and
+// w = p - (beta/2)(p.v) v; rows and columns 0..j-1 stay untouched because
+// v vanishes there and A is already reduced there.  v_j is left in
+// A[j+1.., j] (LDS) and beta_j in bt[j].  buf: >= 4*kMaxM doubles (double-
+// buffered column and p vectors, so two barriers per step suffice).
+template <int NT, int BS>
+__device__ void sy_tridiag(double* A, int E, int lda, double* dg, double* od, double* bt,
+                           double* buf) {
+  static_assert(NT == 256, "16 x 16 thread grid");
+  const int tid = threadIdx.x;
+  const int br = tid >> 4, bc = tid & 15;
+  const int l64 = tid & 63;
+  const int r0 = br * BS, c0 = bc * BS;
+  double a[BS][BS];
+#pragma unroll
+  for (int ii = 0; ii < BS; ++ii)
+#pragma unroll
+    for (int cc = 0; cc < BS; ++cc) {
+      const int r = r0 + ii, c = c0 + cc;
+      const double t = A[r * lda + c];  // r, c < 16*BS <= lda: in bounds
+      a[ii][cc] = (r < E && c < E) ? t : 0.0;
+    }
+  __syncthreads();  // A (LDS) now only receives reflectors
+  for (int j = 0; j + 2 < E; ++j) {
+    double* colb = buf + (j & 1) * (2 * kMaxM);
+    double* pb = colb + kMaxM;
+    // 1. publish column j
+    if (bc == j / BS) {
+      const int jc = j - c0;
+#pragma unroll
+      for (int ii = 0; ii < BS; ++ii) {
+        double v = a[ii][0];
+#pragma unroll
+        for (int cc = 1; cc < BS; ++cc) v = (jc == cc) ? a[ii][cc] : v;
+        colb[r0 + ii] = v;  // rows >= E hold zeros
+      }
+    }
+    __syncthreads();
+    // 2. reflector (every wave, redundantly); loads are unconditional (the
+    // buffers hold 16*BS <= kMaxM entries) and masked afterwards
+    double xs = 0.0;
+#pragma unroll
+    for (int h = 0; h < BS / 4; ++h) {
+      const int i = l64 + 64 * h;
+      const double t = colb[i];
+      xs = (i > j && i < E) ? fma(t, t, xs) : xs;
+    }
+    xs = sum64(xs);
+    const double x0 = colb[j + 1];
+    double vc[BS], cr[BS];
+#pragma unroll
+    for (int cc = 0; cc < BS; ++cc) vc[cc] = colb[c0 + cc];
+#pragma unroll
+    for (int ii = 0; ii < BS; ++ii) cr[ii] = colb[r0 + ii];
+    if (xs - x0 * x0 <= 1e-300 + 1e-32 * xs) {  // column already reduced (uniform)
+      if (tid == 0) {
+        bt[j] = 0.0;
+        od[j] = x0;
+      }
+      if (br == j / BS && bc == j / BS) {
+        const int jj = j - r0;
+#pragma unroll
+        for (int ii = 0; ii < BS; ++ii)
+          if (ii == jj) dg[j] = a[ii][ii];
+      }
+      continue;
+    }
+    const double alpha = sqrt(xs);
+    const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+    const double v0 = x0 + sg * alpha;
+    const double beta = 2.0 / (xs - x0 * x0 + v0 * v0);
+    // 3. p = beta A v: partial over the own columns, summed over the block row
+#pragma unroll
+    for (int cc = 0; cc < BS; ++cc) {
+      const int c = c0 + cc;
+      vc[cc] = (c <= j || c >= E) ? 0.0 : (c == j + 1 ? v0 : vc[cc]);
+    }
+    double vr[BS];
+#pragma unroll
+    for (int ii = 0; ii < BS; ++ii) {
+      const int r = r0 + ii;
+      vr[ii] = (r <= j || r >= E) ? 0.0 : (r == j + 1 ? v0 : cr[ii]);
+    }
+    double pp[BS];
+#pragma unroll
+    for (int ii = 0; ii < BS; ++ii) {
+      double t0 = 0.0, t1 = 0.0;
+#pragma unroll
+      for (int cc = 0; cc < BS; cc += 2) {
+        t0 = fma(a[ii][cc], vc[cc], t0);
+        t1 = fma(a[ii][cc + 1], vc[cc + 1], t1);
+      }
+      pp[ii] = t0 + t1;
+    }
+#pragma unroll
+    for (int ii = 0; ii < BS; ++ii) pp[ii] = sum16(pp[ii]);
+    if (bc == 0) {
+#pragma unroll
+      for (int ii = 0; ii < BS; ++ii) pb[r0 + ii] = beta * pp[ii];
+    }
+    // reflector storage and the diagonal entry (unchanged by this step)
+    if (tid < 64) {
+#pragma unroll
+      for (int h = 0; h < BS / 4; ++h) {
+        const int i = l64 + 64 * h;
+        if (i > j && i < E) A[i * lda + j] = (i == j + 1) ? v0 : colb[i];
+      }
+    }
+    if (br == j / BS && bc == j / BS) {
+      const int jj = j - r0;
+#pragma unroll
+      for (int ii = 0; ii < BS; ++ii)
+        if (ii == jj) dg[j] = a[ii][ii];
+    }
+    if (tid == 0) {
+      od[j] = -sg * alpha;
+      bt[j] = beta;
+    }
+    __syncthreads();
+    // 4. K = beta/2 p.v ; w = p - K v on own rows and columns
+    double pv = 0.0;
+#pragma unroll
+    for (int h = 0; h < BS / 4; ++h) {
+      const int i = l64 + 64 * h;
+      const double pi = pb[i], ci = colb[i];
+      pv = (i > j && i < E) ? fma(pi, (i == j + 1) ? v0 : ci, pv) : pv;
+    }
+    const double K = 0.5 * beta * sum64(pv);
+    double wr[BS], wc[BS];
+#pragma unroll
+    for (int ii = 0; ii < BS; ++ii) wr[ii] = pb[r0 + ii];
+#pragma unroll
+    for (int cc = 0; cc < BS; ++cc) wc[cc] = pb[c0 + cc];
+#pragma unroll
+    for (int ii = 0; ii < BS; ++ii) wr[ii] = (r0 + ii < E) ? fma(-K, vr[ii], wr[ii]) : 0.0;
+#pragma unroll
+    for (int cc = 0; cc < BS; ++cc) wc[cc] = (c0 + cc < E) ? fma(-K, vc[cc], wc[cc]) : 0.0;
+    // 5. rank-2 update
+#pragma unroll
+    for (int ii = 0; ii < BS; ++ii)
+#pragma unroll
+      for (int cc = 0; cc < BS; ++cc)
+        a[ii][cc] = fma(-vr[ii], wc[cc], fma(-wr[ii], vc[cc], a[ii][cc]));
+  }
+  // trailing 2 x 2 block
+  const int jl = E - 2;
+#pragma unroll
+  for (int ii = 0; ii < BS; ++ii)
+#pragma unroll
+    for (int cc = 0; cc < BS; ++cc) {
+      const int r = r0 + ii, c = c0 + cc;
+      if (E >= 2 && r == jl + 1 && c == jl) od[jl] = a[ii][cc];
+      if (r == c && r >= jl && r < E && r >= 0) dg[r] = a[ii][cc];
+    }
+  if (tid == 0) {
+    if (E >= 2) bt[E - 2] = 0.0;
+    bt[E - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Sturm counts (number of eigenvalues below x[t]) for NC shifts at once, on
+// T scaled to ||T|| ~ 1 (diagonal dn, squared off-diagonal e2n).  Three-term
+// recurrence of the leading principal minors
+//   p_i = (a_i - x) p_{i-1} - b_{i-1}^2 p_{i-2},  p_0 = 1,
+// counting sign changes.  An exact zero p_i needs no special case: then
+// p_{i+1} = -b_i^2 p_{i-1} has the sign opposite to p_{i-1}, so the pair of
+// steps contributes one change whatever sign the zero is given.  Division-
+// free: one FMA on the dependent path per step.  The pair (p_i, p_{i-1}) is
+// rescaled by a power of two every 4 steps; with |a - x| <= 3 and b^2 in
+// [1e-60, 1] it stays within the double range.
+__device__ __forceinline__ int sign_change(double a, double b) {
+  return (int)(((unsigned int)(__double2hiint(a) ^ __double2hiint(b))) >> 31);
+}
+
+template <int NC>
+__device__ __forceinline__ void sturm_counts(const double* dn, const double* e2n, int E,
+                                             const double* x, int* c) {
+  double pm[NC], pc[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    pm[t] = 1.0;
+    pc[t] = dn[0] - x[t];
+    c[t] = sign_change(pc[t], 1.0);
+  }
+  auto step = [&](double a, double b2) {
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const double pn = fma(a - x[t], pc[t], -b2 * pm[t]);
+      c[t] += sign_change(pn, pc[t]);
+      pm[t] = pc[t];
+      pc[t] = pn;
+    }
+  };
+  int i = 1;
+  for (; i + 3 < E; i += 4) {
+    const double a0 = dn[i], a1 = dn[i + 1], a2 = dn[i + 2], a3 = dn[i + 3];
+    const double b0 = e2n[i - 1], b1 = e2n[i], b2 = e2n[i + 1], b3 = e2n[i + 2];
+    step(a0, b0);
+    step(a1, b1);
+    step(a2, b2);
+    step(a3, b3);
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pc[t]), fabs(pm[t])));
+      pc[t] = ldexp(pc[t], -ex);
+      pm[t] = ldexp(pm[t], -ex);
+    }
+  }
+  for (; i < E; ++i) step(dn[i], e2n[i - 1]);
+}
+
+// Multisection over NC chains per lane: a 16-lane group brackets the
+// eigenvalues k = g, g + NT/16, ... and shrinks each bracket 17x per pass.
+template <int NT, int NC>
+__device__ void multisect(const double* dn, const double* e2n, int E, double lo, double hi,
+                          double width_stop, double scale, double* lam) {
+  const int tid = threadIdx.x;
+  const int l16 = tid & 15, g16 = tid >> 4;
+  constexpr int NG16 = NT / 16;
+  int nk = 0;
+  for (int k = g16; k < E; k += NG16) ++nk;
+  if (nk == 0) return;
+  const int gshift = (tid & 48);  // first lane of the 16-group within the wave
+  const double frac = (double)(l16 + 1) * (1.0 / 17.0);
+  double l[NC], u[NC];
+#pragma unroll
+  for (int t = 0; t < NC; ++t) {
+    l[t] = lo;
+    u[t] = hi;
+  }
+  for (int it = 0; it < 40; ++it) {
+    // all brackets shrink by the same factor, so one test serves every chain
+    if (!((u[0] - l[0]) > width_stop)) break;
+    double x[NC];
+    int c[NC];
+#pragma unroll
+    for (int t = 0; t < NC; ++t) x[t] = l[t] + (u[t] - l[t]) * frac;
+    sturm_counts<NC>(dn, e2n, E, x, c);
+#pragma unroll
+    for (int t = 0; t < NC; ++t) {
+      const int k = g16 + t * NG16;
+      const unsigned long long b = __ballot(c[t] > k);
+      const unsigned int gb = (unsigned int)((b >> gshift) & 0xFFFFull);
+      const int first = gb ? __builtin_ctz(gb) : 16;
+      const double w = (u[t] - l[t]) * (1.0 / 17.0);
+      const double nl = (first == 0) ? l[t] : l[t] + w * (double)first;
+      const double nu = (first == 16) ? u[t] : l[t] + w * (double)(first + 1);
+      l[t] = nl;
+      u[t] = nu;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NC; ++t)
+    if (t < nk && l16 == 0) lam[g16 + t * NG16] = 0.5 * (l[t] + u[t]) * scale;
+}
+
+// All eigenvalues of T in ascending order into lam[0..E), to an absolute
+// accuracy of about 1e-15 ||T||.  e2, dn: >= E doubles of scratch each.
+template <int NT>
+__device__ void tridiag_eigvals(const double* dg, const double* od, int E, double* lam,
+                                double* e2, double* dn) {
+  const int tid = threadIdx.x;
+  // Gershgorin scale (every thread)
+  double nrm = 0.0;
+  for (int i = 0; i < E; ++i) {
+    const double r = (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0);
+    nrm = fmax(nrm, fabs(dg[i]) + r);
+  }
+  if (!(nrm > 0.0)) {
+    for (int i = tid; i < E; i += NT) lam[i] = 0.0;
+    __syncthreads();
+    return;
+  }
+  const double sc = 1.0 / nrm;
+  for (int i = tid; i < E; i += NT) {
+    dn[i] = dg[i] * sc;
+    if (i + 1 < E) {
+      const double b = od[i] * sc;
+      e2[i] = fmax(b * b, 1e-60);
+    }
+  }
+  __syncthreads();
+  // scaled Gershgorin interval lies inside [-1, 1]; widen by the stop width
+  const double ws = 1e-15;
+  constexpr int NG16 = NT / 16;
+  const int nkmax = (E + NG16 - 1) / NG16;
+  if (nkmax <= 1)
+    multisect<NT, 1>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
+  else if (nkmax <= 2)
+    multisect<NT, 2>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
+  else if (nkmax <= 4)
+    multisect<NT, 4>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
+  else
+    multisect<NT, 8>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
+  __syncthreads();
+}
+
+// Eigenvector of T for eigenvalue lam by a twisted factorisation; written
+// (normalised) to z[i*ldz] for i < E.  One lane per vector.
+__device__ inline void tridiag_vec(const double* dg, const double* od, int E, double lam,
+                                   double* z, int ldz, double tiny) {
+  if (E == 1) {
+    z[0] = 1.0;
+    return;
+  }
+  // top-down: T - lam I = L D+ L^T ; l_i stored in z[i]
+  double dp = dg[0] - lam;
+  if (fabs(dp) < tiny) dp = tiny;
+  double gam_best = 1e308;
+  int rbest = 0;
+  // keep D+ values to form gamma: recompute on the bottom-up sweep instead
+  for (int i = 0; i + 1 < E; ++i) {
+    const double li = od[i] * rcp_acc(dp);
+    z[i * ldz] = li;
+    dp = (dg[i + 1] - lam) - li * od[i];
+    if (fabs(dp) < tiny) dp = tiny;
+  }
+  // bottom-up: T - lam I = U D- U^T ; gamma_r = D+_r + D-_r - (a_r - lam)
+  // (D+_r recomputed from the stored l: D+_{i+1} = a_{i+1} - lam - l_i b_i)
+  double dm = dg[E - 1] - lam;
+  if (fabs(dm) < tiny) dm = tiny;
+  {
+    // D+_{E-1}
+    const double dpl = (dg[E - 1] - lam) - z[(E - 2) * ldz] * od[E - 2];
+    const double g = dpl + dm - (dg[E - 1] - lam);
+    gam_best = fabs(g);
+    rbest = E - 1;
+  }
+  for (int i = E - 1; i >= 1; --i) {
+    const double ui = od[i - 1] * rcp_acc(dm);
+    dm = (dg[i - 1] - lam) - ui * od[i - 1];
+    if (fabs(dm) < tiny) dm = tiny;
+    const double dpl = (i - 1 == 0) ? (dg[0] - lam)
+                                    : (dg[i - 1] - lam) - z[(i - 2) * ldz] * od[i - 2];
+    const double g = dpl + dm - (dg[i - 1] - lam);
+    if (fabs(g) < gam_best) {
+      gam_best = fabs(g);
+      rbest = i - 1;
+    }
+  }
+  const int r = rbest;
+  // u_i for i > r (recomputed bottom-up), stored in z[i] (the l there is no longer needed)
+  dm = dg[E - 1] - lam;
+  if (fabs(dm) < tiny) dm = tiny;
+  for (int i = E - 1; i > r; --i) {
+    const double ui = od[i - 1] * rcp_acc(dm);
+    z[i * ldz] = ui;
+    dm = (dg[i - 1] - lam) - ui * od[i - 1];
+    if (fabs(dm) < tiny) dm = tiny;
+  }
+  // z_r = 1; upward z_i = -l_i z_{i+1} (i < r); downward z_{i+1} = -u_{i+1} z_i (i >= r)
+  double nrm2 = 1.0;
+  double zc = 1.0;
+  for (int i = r - 1; i >= 0; --i) {
+    zc = -z[i * ldz] * zc;
+    z[i * ldz] = zc;
+    nrm2 = fma(zc, zc, nrm2);
+  }
+  zc = 1.0;
+  for (int i = r; i + 1 < E; ++i) {
+    zc = -z[(i + 1) * ldz] * zc;
+    z[(i + 1) * ldz] = zc;
+    nrm2 = fma(zc, zc, nrm2);
+  }
+  z[r * ldz] = 1.0;
+  const double inv = 1.0 / sqrt(nrm2);
+  for (int i = 0; i < E; ++i) z[i * ldz] *= inv;
+}
+
+// Modified Gram-Schmidt on columns 0..r-1 of Z (E rows, stride ldz), in
+// order.  Column c belongs to the 16-lane group c mod (NT/16), which alone
+// updates it; step j removes the (unnormalised) column j from every later
+// column, and all columns are normalised at the end.  One barrier per step.
+template <int NT>
+__device__ void mgs_cols(double* Z, int E, int ldz, int r) {
+  const int tid = threadIdx.x;
+  const int l16 = tid & 15, g16 = tid >> 4;
+  constexpr int NG16 = NT / 16;
+  for (int j = 0; j + 1 < r; ++j) {
+    double s = 0.0;
+    for (int i = l16; i < E; i += 16) s = fma(Z[i * ldz + j], Z[i * ldz + j], s);
+    s = sum16(s);
+    const double inv = s > 0.0 ? 1.0 / s : 0.0;
+    for (int c = j + 1 + ((g16 - (j + 1) % NG16 + NG16) % NG16); c < r; c += NG16) {
+      double d = 0.0;
+      for (int i = l16; i < E; i += 16) d = fma(Z[i * ldz + j], Z[i * ldz + c], d);
+      d = sum16(d) * inv;
+      for (int i = l16; i < E; i += 16) Z[i * ldz + c] -= d * Z[i * ldz + j];
+    }
+    __syncthreads();
+  }
+  for (int c = g16; c < r; c += NG16) {
+    double s = 0.0;
+    for (int i = l16; i < E; i += 16) s = fma(Z[i * ldz + c], Z[i * ldz + c], s);
+    s = sum16(s);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int i = l16; i < E; i += 16) Z[i * ldz + c] *= inv;
+  }
+  __syncthreads();
+}
+
+// Z <- Q Z for the r columns of Z, Q = H_0 H_1 ... H_{E-3} (reflectors in A).
+// A 16-lane group owns columns g, g + NT/16, ...; it applies every reflector
+// to them in turn (no barrier between reflectors).
+template <int NT>
+__device__ void back_transform(const double* A, const double* bt, int E, int lda, double* Z,
+                               int ldz, int r) {
+  const int tid = threadIdx.x;
+  const int l16 = tid & 15, g16 = tid >> 4;
+  constexpr int NG16 = NT / 16;
+  for (int j = E - 3; j >= 0; --j) {
+    const double beta = bt[j];
+    if (beta == 0.0) continue;  // uniform
+    const int m = E - 1 - j;
+    const double* v = A + (j + 1) * lda + j;  // v[i*lda], rows j+1..
+    for (int c = g16; c < r; c += NG16) {
+      double d = 0.0;
+      for (int i = l16; i < m; i += 16) d = fma(v[i * lda], Z[(j + 1 + i) * ldz + c], d);
+      d = sum16(d) * beta;
+      for (int i = l16; i < m; i += 16) Z[(j + 1 + i) * ldz + c] -= d * v[i * lda];
+    }
+  }
+  __syncthreads();
+}
+
+}  // namespace qtt
