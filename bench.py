@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--eps", type=float, default=1e-4)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="budget for the CPU oracle baseline (0 disables it)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the timed steps, run one plain device copy of this many MiB "
+                         "(a known-size kernel for scaling hardware byte counters)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also report GPU time per step of every kernel class")
     return ap.parse_args()
@@ -104,13 +107,22 @@ def main():
         torch.cuda.synchronize()
         t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # per-step spread (separate, synchronised steps; not part of the value)
+    spread = []
+    for _ in range(min(args.steps, 10)):
+        torch.cuda.synchronize()
+        a0 = time.perf_counter()
+        step()
+        torch.cuda.synchronize()
+        spread.append((time.perf_counter() - a0) * 1e3)
+    spread.sort()
     value = n * args.steps / (t1 - t0)
     avg_ms = pd.ms / max(pd.launches, 1)
     launches_per_step = pd.launches / args.steps
 
     fr = st["f"].ranks_host()
     zr = st["z"].ranks_host()
-    roof = roofline(dom, avg_ms, launches_per_step, d, es, fr, zr, st)
+    roof = roofline(dom, avg_ms, launches_per_step, d, es, st, args.workload, R)
 
     res = {
         "metric": "samples/s for QTT decompose+conv+round+reconstruct at eps=1e-4",
@@ -129,50 +141,113 @@ def main():
                                f"5% noise, sinc B={B:g}, eps={args.eps:g}, rank cap {R}",
                    "d": d, "samples": n, "eps": args.eps, "max_rank": R, "B": B},
         "roofline": roof,
+        "step_ms_p10_p50_p90": [spread[int(0.1 * (len(spread) - 1))],
+                                spread[len(spread) // 2], spread[int(0.9 * (len(spread) - 1))]],
     }
     if args.breakdown:
         res["kernels_ms_per_step"] = {c: round(v[0], 4) for c, v in per_step.items()}
         res["kernel_launches_per_step"] = {c: v[1] for c, v in per_step.items()}
         res["ranks"] = {"F": fr, "Z": zr}
+    if args.calib_copy_mib > 0:
+        nb = args.calib_copy_mib << 20
+        src = torch.ones(nb // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        res["calib_copy_bytes"] = nb
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(noisy, B, args.eps, R, n, args.cpu_seconds)
     print(json.dumps(res), flush=True)
 
 
-def roofline(cls, avg_ms, launches_per_step, d, es, fr, zr, st):
+K_LEVEL = 6          # steps taken from one 64 x 64 data Gram
+TAIL_ELEMS = 8192    # remainders up to this size finish in one workgroup
+MAX_RANK = 64        # library rank capacity when uncapped
+
+
+def eig_step_sizes(D, R, ranks):
+    """Gram orders E = 2 r_{k-1} of the eig_step launches of one decomposition.
+
+    Mirrors the library's schedule: for N = 2^D > 8192 samples, steps
+    1..6 come from one 64 x 64 Gram, steps 7.. run one eig_step each until
+    the remainder (2^(D-k) x 2 cap_{k-1}) fits 8192 entries, then the tail.
+    """
+    Reff = MAX_RANK if R == 0 else R
+    cap = [1] + [min(1 << k, 1 << (D - k), Reff) for k in range(1, D)] + [1]
+    if (1 << D) <= TAIL_ELEMS:
+        return []
+    k = K_LEVEL + 1
+    while k < D and not ((1 << (D - k)) * 2 * cap[k - 1] <= TAIL_ELEMS):
+        k += 1
+    return [2 * ranks[j - 1] for j in range(K_LEVEL + 1, k)]
+
+
+def source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2301_13339_amd", "csrc")
+    for fn in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, fn), "rb") as f:
+            h.update(fn.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cls, workload):
+    """HBM bytes per launch from the committed counter summary, if it was taken
+    on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = tab.get(f"{workload}:{cls}")
+    if not ent or ent.get("source_digest") != source_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def roofline(cls, avg_ms, launches_per_step, d, es, st, workload, R):
     """Algorithmic work per launch of the dominant class over its average duration."""
     sec = avg_ms * 1e-3
-    if cls in ("eig_step", "level_eig", "tail"):
-        # symmetric eigendecompositions with vectors: 9 E^3 flops each (textbook
-        # count); the class runs on ONE workgroup by design, so the whole-chip
-        # FP64 peak is the reference and the fraction shows the latency bound
+    peak_alu = FP64_PEAK_TFLOPS if es == 8 else FP32_PEAK_TFLOPS
+    traffic = measured_traffic(cls, workload)
+    common = {"kernel": cls, "traffic": traffic, "avg_launch_us": avg_ms * 1e3,
+              "launches_per_step": launches_per_step}
+    if cls == "eig_step":
+        # one launch = one truncated eigendecomposition (with vectors) of an
+        # E x E Gram in ONE workgroup; work = 9 E^3 flops (symmetric QR with
+        # vectors, the textbook count), averaged over the step's launches
+        Es = (eig_step_sizes(d, R, st["f"].ranks_host())
+              + eig_step_sizes(d + 1, 0, st["w"][0].ranks_host())
+              + eig_step_sizes(d, 0, st["z"].ranks_host()))
+        flops = sum(9.0 * E ** 3 for E in Es) / max(len(Es), 1)
+        ach = flops / sec / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": ach / peak_alu, **common,
+                "work_per_launch": f"9*E^3 flops averaged over E={Es} ({flops:.4g})"}
+    if cls in ("level_eig", "tail"):
         E = 64
         flops = 9.0 * E ** 3
         ach = flops / sec / 1e12
-        return {"bound": "alu", "kernel": cls, "achieved": ach, "peak": FP64_PEAK_TFLOPS if es == 8
-                else FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / (FP64_PEAK_TFLOPS if es == 8
-                else FP32_PEAK_TFLOPS), "traffic": None,
-                "avg_launch_us": avg_ms * 1e3, "launches_per_step": launches_per_step,
-                "work_per_launch": f"9*E^3 flops, E=64 ({flops:.3g})"}
+        return {"bound": "alu", "achieved": ach, "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": ach / peak_alu, **common,
+                "work_per_launch": f"9*E^3 flops per eigensolve, E=64 ({flops:.4g})"}
+    n = 1 << d
     if cls == "full_final":
-        n = 1 << d
         byts = n * es
-        ach = byts / sec / 1e9
-        return {"bound": "hbm", "kernel": cls, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_us": avg_ms * 1e3, "launches_per_step": launches_per_step,
-                "work_per_launch": f"2^d outputs written ({byts} B)"}
-    if cls in ("level_gram", "project"):
-        n = 1 << d
+        what = f"2^d outputs written ({byts} B)"
+    elif cls in ("level_gram", "project"):
         byts = n * es
-        ach = byts / sec / 1e9
-        return {"bound": "hbm", "kernel": cls, "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                "avg_launch_us": avg_ms * 1e3, "launches_per_step": launches_per_step,
-                "work_per_launch": f"2^d samples read ({byts} B)"}
-    return {"bound": "alu", "kernel": cls, "achieved": None, "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": None, "traffic": None, "avg_launch_us": avg_ms * 1e3,
-            "launches_per_step": launches_per_step}
+        what = f"2^d samples read ({byts} B)"
+    else:
+        return {"bound": "alu", "achieved": None, "peak": peak_alu, "unit": "TFLOP/s",
+                "frac": None, **common}
+    ach = byts / sec / 1e9
+    return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, **common, "work_per_launch": what}
 
 
 def cpu_baseline(noisy, B, eps, R, n, budget_s):

@@ -71,6 +71,18 @@ def _stream(device) -> ctypes.c_void_p:
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 
+_SIDE = {}
+
+
+def _side_stream(device) -> torch.cuda.Stream:
+    """A second stream per device (default priority) for independent stages."""
+    dev = torch.device(device)
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx not in _SIDE:
+        _SIDE[idx] = torch.cuda.Stream(device=idx)
+    return _SIDE[idx]
+
+
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
 
@@ -108,6 +120,10 @@ class QTT:
         return t
 
     # ----------------------------------------------------------- inspect
+    def record_stream(self, stream) -> None:
+        for t in (self.cores, self.ranks, self.status, *self._keep):
+            t.record_stream(stream)
+
     def ranks_host(self):
         return [int(v) for v in self.ranks.cpu()]
 
@@ -268,18 +284,26 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
     """
     if eps_w is None:
         eps_w = eps / 10.0
-    f = decompose(x, eps, max_rank)
     dt = x.dtype
-    if shape2d is None:
-        w = [kernel_sinc(f.d, float(B), eps_w, dt, x.device)]
-        am = [f.d]
-    else:
-        ny, nx = shape2d
-        dy, dx = ny.bit_length() - 1, nx.bit_length() - 1
-        bx, by = B
-        w = [kernel_sinc(dx, float(bx), eps_w, dt, x.device),
-             kernel_sinc(dy, float(by), eps_w, dt, x.device)]
-        am = [dx, dy]
+    # the kernel QTT does not depend on the samples: build it on a side
+    # stream while the signal is decomposed on the current one
+    main = torch.cuda.current_stream(x.device)
+    side = _side_stream(x.device)
+    side.wait_stream(main)
+    with torch.cuda.stream(side):
+        if shape2d is None:
+            w = [kernel_sinc(int(x.numel()).bit_length() - 1, float(B), eps_w, dt, x.device)]
+        else:
+            ny, nx = shape2d
+            dy, dx = ny.bit_length() - 1, nx.bit_length() - 1
+            bx, by = B
+            w = [kernel_sinc(dx, float(bx), eps_w, dt, x.device),
+                 kernel_sinc(dy, float(by), eps_w, dt, x.device)]
+    f = decompose(x, eps, max_rank)
+    main.wait_stream(side)
+    for t in w:
+        t.record_stream(main)
+    am = [f.d] if shape2d is None else [dx, dy]
     y = conv(f, w, am)
     z = round(y, eps, round_max_rank, round_method)
     out = full(z)
