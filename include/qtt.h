@@ -125,8 +125,9 @@ int qtt_query_decompose(int d, int max_rank, int dtype, int32_t* cap, size_t* ws
  *             doubles: row k-1 receives the singular values of unfolding k in
  *             non-increasing order, zero padded
  * Singular values and vectors come from FP64 Gram sums of the unfoldings
- * (wavefront-shuffle reductions) and a one-workgroup FP64 Jacobi
- * eigensolver, whatever `dtype` is.
+ * (wavefront-shuffle reductions) and a one-workgroup FP64 symmetric
+ * eigensolver (Householder tridiagonalisation, multisection, twisted
+ * factorisation), whatever `dtype` is.
  */
 int qtt_decompose(const void* x, int d, int dtype, double eps, int max_rank, qtt_tensor* out,
                   double* sv, void* ws, size_t ws_bytes, void* stream);
@@ -220,7 +221,7 @@ int qtt_full(const qtt_tensor* t, void* out, void* ws, size_t ws_bytes, void* st
 #define QTT_K_REDUCE 2       /* fixed-order sum of partial Gram matrices       */
 #define QTT_K_LEVEL_EIG 3    /* steps 1..6 from the level Gram                  */
 #define QTT_K_PROJECT 4      /* streaming projection + Gram of the remainder   */
-#define QTT_K_EIG_STEP 5     /* one truncated SVD step (Jacobi eigensolver)    */
+#define QTT_K_EIG_STEP 5     /* one truncated SVD step (FP64 eigensolver)      */
 #define QTT_K_TAIL 6         /* last steps of the sweep in one workgroup       */
 #define QTT_K_CONV 7         /* Toeplitz-operator x signal cores               */
 #define QTT_K_FULL_CHAIN 8   /* half-chain products of Full                    */

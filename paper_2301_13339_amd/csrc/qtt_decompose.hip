@@ -179,7 +179,7 @@ struct StepOut {
   int32_t* status;
   double* sv;  // may be null
   int lib_capped;
-  int32_t* dbg;  // Jacobi sweeps per step (workspace diagnostics)
+  int32_t* dbg;  // per-step diagnostics in the workspace (optional timings)
 };
 
 // Eigen-solve the Gram matrix in A (E x E), choose the rank, and leave the
@@ -726,7 +726,7 @@ int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p) {
   P.pstride = mcap * mcap;
   Arena ar(ws);
   P.scal = ar.take<double>(16);
-  // [0] non-finite flag, [16+k] Jacobi sweeps of step k, [80+4k..] optional timings
+  // [0] non-finite flag, [16+k] Gram order of step k, [80+5k..] optional timings
   P.iflags = ar.take<int32_t>(16 + 64 + 512);
   P.gram = ar.take<double>((size_t)mcap * mcap);
   P.umat = ar.take<double>((size_t)kMaxM * kMaxRank);

@@ -1,9 +1,10 @@
 // Internal declarations shared by the HIP translation units of libqtt.
 //
-// Device helpers: the one-workgroup FP64 Jacobi eigensolver used for every
-// truncated SVD (through the Gram matrix of the unfolding), the truncation
-// rule of Algorithm 1 with the max-rank modification (1), and a small host
-// arena that carves the caller's workspace.
+// Constants, the launch probe, the decomposition plan and a small host arena
+// that carves the caller's workspace.  Every truncated SVD goes through the
+// Gram matrix of the unfolding and the one-workgroup FP64 symmetric
+// eigensolver of qtt_syev.hpp; the truncation rule of Algorithm 1 with the
+// max-rank modification (1) is in qtt_eig.hpp.
 #pragma once
 
 #include <hip/hip_runtime.h>
