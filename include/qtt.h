@@ -207,6 +207,76 @@ int qtt_query_full(int d, const int32_t* cap, int dtype, size_t* ws_bytes);
  */
 int qtt_full(const qtt_tensor* t, void* out, void* ws, size_t ws_bytes, void* stream);
 
+/* --------------------------------------------------------------- adjoint */
+/*
+ * Building blocks of the backward of y = T(w) full(F) (the convolution (2.2)
+ * of the reconstruction of Algorithm 3 with the kernel generator w), at fixed
+ * ranks.  The paper gives no derivative; these follow from the chain rule.
+ */
+
+/* Workspace of qtt_toeplitz_apply for a signal of d modes and a generator
+ * with capacities w_cap[0..d+1]. */
+int qtt_query_toeplitz(int d, const int32_t* w_cap, int dtype, size_t* ws_bytes);
+
+/*
+ * Toeplitz product on full vectors of N = 2^(w->d - 1) elements (w->dtype):
+ *   transpose = 0:  y_j = sum_i w_{j-i+N} x_i      (y = T(w) x, eq. (2.2))
+ *   transpose = 1:  y_i = sum_j w_{j-i+N} x_j      (y = T(w)^T x, its adjoint)
+ * with w the QTT generator (d+1 modes, e.g. from qtt_kernel_sinc).  The
+ * operator is applied in its QTT-matrix form (the binary adder of qtt_conv)
+ * one mode per pass, so the cost is O(N d rho^2) for generator ranks rho.
+ * x and y are device arrays that must not overlap; ws holds two FP64 states
+ * of 2 max_k(w_cap[k]) N doubles (size from qtt_query_toeplitz): the
+ * intermediate sums stay in FP64 whatever the dtype.
+ * Errors: QTT_EINVAL (null pointers, w with fewer than 2 modes, a transpose
+ * flag other than 0/1, capacities above QTT_MAX_RANK), QTT_ENOSPC.
+ */
+int qtt_toeplitz_apply(const qtt_tensor* w, const void* x, void* y, int transpose, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Capacities (d+2 entries) and workspace for qtt_kernel_sinc_dB. */
+int qtt_query_kernel_sinc_dB(int d, int dtype, int32_t* cap, size_t* ws_bytes,
+                             size_t* core_elems);
+
+/*
+ * QTT (d+1 modes, uncapped, tolerance eps_w) of the derivative with respect
+ * to the bandwidth B of the normalised generator of qtt_kernel_sinc:
+ *   dw_u/dB = s'_m / S - s_m S' / S^2,  s_m = sinc(B x_m),
+ *   s'_m = (cos(pi B x_m) - s_m) / B  (0 at x_m = 0),  S = sum s, S' = sum s'
+ * (kernel (3.1) normalised as in (7.2) by the discrete sum).  S and S' are
+ * summed on the device; the samples are generated on the fly.
+ */
+int qtt_kernel_sinc_dB(int d, double B, double eps_w, int dtype, qtt_tensor* w_out, void* ws,
+                       size_t ws_bytes, void* stream);
+
+/* Workspace of qtt_full_adjoint (capacities of F, each <= QTT_MAX_RANK). */
+int qtt_query_full_adjoint(int d, const int32_t* cap, int dtype, size_t* ws_bytes);
+
+/*
+ * Adjoint of qtt_full: grad->cores[k] = d<g, full(f)>/d f_k for every core,
+ * at the ranks of f (written to grad->ranks).  g: 2^d elements of f->dtype.
+ * grad must have f's d, dtype and capacities.  The right interface matrices
+ * of f are recomputed, and g is contracted from the left mode by mode;
+ * every sum runs in FP64 in a fixed order (bit-reproducible).
+ */
+int qtt_full_adjoint(const qtt_tensor* f, const void* g, qtt_tensor* grad, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* Workspace of qtt_conv_full_backward (wdb_cap may be NULL). */
+int qtt_query_conv_full_backward(int d, const int32_t* f_cap, const int32_t* w_cap,
+                                 const int32_t* wdb_cap, int dtype, size_t* ws_bytes);
+
+/*
+ * Backward of y = T(w) full(f) for an upstream gradient grad_y (2^d
+ * elements): grad_f = qtt_full_adjoint(f, T(w)^T grad_y); if w_dB (from
+ * qtt_kernel_sinc_dB) is given, *grad_B (one device double) =
+ * <grad_y, T(w_dB) full(f)>.  full(f) is recomputed, not taken from the
+ * forward.  w_dB and grad_B are both NULL or both non-NULL.
+ */
+int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_tensor* w_dB,
+                           const void* grad_y, qtt_tensor* grad_f, double* grad_B, void* ws,
+                           size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------ measurement */
 /*
  * Kernel classes for the launch probe.  Between qtt_probe_start and
@@ -227,6 +297,7 @@ int qtt_full(const qtt_tensor* t, void* out, void* ws, size_t ws_bytes, void* st
 #define QTT_K_FULL_CHAIN 8   /* half-chain products of Full                    */
 #define QTT_K_FULL_FINAL 9   /* final product of Full (writes the 2^d outputs) */
 #define QTT_K_OTHER 10       /* bookkeeping kernels                            */
+#define QTT_K_ADJOINT 11     /* Toeplitz products on full vectors, adjoint of Full */
 
 int qtt_probe_start(int cls, int max_launches);
 int qtt_probe_stop(double* total_ms, int* launches);

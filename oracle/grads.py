@@ -48,11 +48,13 @@ def generator_dB(d: int, B: float) -> np.ndarray:
     return out
 
 
-def loss(cores, B: float, target) -> float:
-    """``L = ||T(w(B)) full(F) - t||^2`` with the exact generator ``w(B)``."""
+def loss(cores, B: float, target, w=None) -> float:
+    """``L = ||T(w) full(F) - t||^2``; ``w`` defaults to the exact generator ``w(B)``."""
     f = tt.tt_full(cores)
     d = tt.log2_exact(f.size)
-    y = conv.toeplitz_apply_fft(f, conv.toeplitz_generator(d, B))
+    if w is None:
+        w = conv.toeplitz_generator(d, B)
+    y = conv.toeplitz_apply_fft(f, w)
     r = y - np.asarray(target, dtype=np.float64)
     return float(r @ r)
 
@@ -86,12 +88,20 @@ def _right_interfaces(cores):
     return out
 
 
-def grads(cores, B: float, target):
-    """Return ``(L, [dL/dG_k], dL/dB, dL/dw, dL/df)`` by full-format contractions."""
+def grads(cores, B: float, target, w=None, dw=None):
+    """Return ``(L, [dL/dG_k], dL/dB, dL/dw, dL/df)`` by full-format contractions.
+
+    ``w`` (generator) and ``dw`` (its derivative in ``B``) default to the
+    exact ones; passing approximations (e.g. the full arrays of their QTTs)
+    gives the gradients of the loss with those in place, at fixed ranks.
+    """
     f = tt.tt_full(cores)
     n = f.size
     d = tt.log2_exact(n)
-    w = conv.toeplitz_generator(d, B)
+    if w is None:
+        w = conv.toeplitz_generator(d, B)
+    if dw is None:
+        dw = generator_dB(d, B)
     y = conv.toeplitz_apply_fft(f, w)
     r = y - np.asarray(target, dtype=np.float64)
     L = float(r @ r)
@@ -104,18 +114,26 @@ def grads(cores, B: float, target):
     gw = np.zeros(2 * n)
     u = np.arange(1, 2 * n)
     gw[1:] = c[(u - n) % m]
-    gB = float(gw @ generator_dB(d, B))
+    gB = float(gw @ dw)
+    gcores = full_adjoint(cores, gf)
+    return L, gcores, gB, gw, gf
+
+
+def full_adjoint(cores, g):
+    """``[d<g, full(F)>/dG_k]``: ``g`` contracted with the left and right
+    interfaces of every core (the products of the slices before and after it)."""
+    g = np.asarray(g, dtype=np.float64)
     Lf = _left_interfaces(cores)
     Rf = _right_interfaces(cores)
     gcores = []
     for k, G in enumerate(cores):
         Lk = Lf[k]                # 2**k x r_{k}   (bits 1..k)
         Rk = Rf[k + 1]            # r_{k+1} x 2**(K-k-1) (bits k+2..K)
-        g = np.zeros_like(G)
+        out = np.zeros_like(G)
         # position j = low + 2**k * i + 2**(k+1) * high
-        gf3 = gf.reshape((Rk.shape[1], 2, Lk.shape[0]))   # [high, i, low] (C order: low fastest)
+        g3 = g.reshape((Rk.shape[1], 2, Lk.shape[0]))   # [high, i, low] (C order: low fastest)
         for i in range(2):
-            M = gf3[:, i, :]                                # high x low
-            g[:, i, :] = Lk.T @ M.T @ Rk.T
-        gcores.append(g)
-    return L, gcores, gB, gw, gf
+            M = g3[:, i, :]                                 # high x low
+            out[:, i, :] = Lk.T @ M.T @ Rk.T
+        gcores.append(out)
+    return gcores

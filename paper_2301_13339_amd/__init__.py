@@ -10,6 +10,9 @@ raises.
     y   = conv(t, [w])                     # exact (2.2) in QTT format
     z   = round(y, eps)                    # TT-rounding
     out = full(z)                          # Algorithm 3
+
+Adjoint at fixed ranks: ``conv_full(t, B)`` is ``T(w(B)) full(t)`` as a
+torch.autograd.Function whose backward calls ``qtt_conv_full_backward``.
 """
 
 from __future__ import annotations
@@ -24,8 +27,9 @@ from ._lib import (QTT_F32, QTT_F64, QTT_MAX_RANK, QTT_MAXD, QTT_ROUND_EXACT,
                    QTT_STATUS_RANKCAP, QttError, lib, lib_path, qtt_tensor)
 
 __all__ = [
-    "QTT", "probe", "from_cores", "decompose", "kernel_sinc", "conv", "round", "full", "pipeline", "lib_path",
-    "QttError", "QTT_MAX_RANK",
+    "QTT", "probe", "from_cores", "decompose", "kernel_sinc", "conv", "round", "full", "pipeline",
+    "toeplitz_apply", "kernel_sinc_dB", "full_adjoint", "conv_full_backward", "ConvFull",
+    "conv_full", "lib_path", "QttError", "QTT_MAX_RANK",
 ]
 
 _DT = {torch.float32: QTT_F32, torch.float64: QTT_F64}
@@ -310,3 +314,137 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
     if shape2d is not None:
         out = out.reshape(shape2d)
     return out, dict(f=f, w=w, y=y, z=z)
+
+
+# ------------------------------------------------------------------ adjoint
+def toeplitz_apply(w: QTT, x: torch.Tensor, transpose: bool = False,
+                   out: torch.Tensor | None = None) -> torch.Tensor:
+    """``T(w) x`` (or ``T(w)^T x``) for a full vector ``x`` of ``2**(w.d-1)`` entries."""
+    d = w.d - 1
+    if x.dtype != _TORCH[w.dtype] or x.numel() != (1 << d) or not x.is_contiguous():
+        raise QttError(-1, "toeplitz_apply: x must be contiguous with 2^d entries of w's dtype")
+    cap = (ctypes.c_int32 * (w.d + 1))(*w.cap)
+    wsb = ctypes.c_size_t()
+    _check(lib().qtt_query_toeplitz(d, cap, w.dtype, ctypes.byref(wsb)), "qtt_query_toeplitz")
+    if out is None:
+        out = torch.empty_like(x)
+    ws = _workspace(wsb.value, x.device)
+    wc = w._c()
+    _check(lib().qtt_toeplitz_apply(ctypes.byref(wc), ctypes.c_void_p(x.data_ptr()),
+                                    ctypes.c_void_p(out.data_ptr()), int(bool(transpose)),
+                                    ctypes.c_void_p(ws.data_ptr()), wsb.value, _stream(x.device)),
+           "qtt_toeplitz_apply")
+    return out
+
+
+def kernel_sinc_dB(d: int, B: float, eps_w: float, dtype=torch.float64, device="cuda") -> QTT:
+    """QTT (``d+1`` modes) of the bandwidth derivative of the normalised generator."""
+    dt = _DT[dtype]
+    cap = (ctypes.c_int32 * (d + 2))()
+    ws = ctypes.c_size_t()
+    _check(lib().qtt_query_kernel_sinc_dB(int(d), dt, cap, ctypes.byref(ws), None),
+           "qtt_query_kernel_sinc_dB")
+    dev = torch.device(device)
+    out = _make(d + 1, dt, list(cap), dev)
+    w = _workspace(ws.value, dev)
+    t = out._c()
+    _check(lib().qtt_kernel_sinc_dB(int(d), float(B), float(eps_w), dt, ctypes.byref(t),
+                                    ctypes.c_void_p(w.data_ptr()), ws.value, _stream(dev)),
+           "qtt_kernel_sinc_dB")
+    out._keep = [w]
+    return out
+
+
+def _grad_like(f: QTT) -> QTT:
+    g = _make(f.d, f.dtype, f.cap, f.device)
+    g.cores.zero_()
+    return g
+
+
+def full_adjoint(f: QTT, g: torch.Tensor) -> QTT:
+    """Cores of ``d<g, full(f)>/d f_k`` (same ranks and capacities as ``f``)."""
+    cap = (ctypes.c_int32 * (f.d + 1))(*f.cap)
+    wsb = ctypes.c_size_t()
+    _check(lib().qtt_query_full_adjoint(f.d, cap, f.dtype, ctypes.byref(wsb)),
+           "qtt_query_full_adjoint")
+    gr = _grad_like(f)
+    ws = _workspace(wsb.value, f.device)
+    fc, gc = f._c(), gr._c()
+    _check(lib().qtt_full_adjoint(ctypes.byref(fc), ctypes.c_void_p(g.data_ptr()),
+                                  ctypes.byref(gc), ctypes.c_void_p(ws.data_ptr()), wsb.value,
+                                  _stream(f.device)), "qtt_full_adjoint")
+    return gr
+
+
+def conv_full_backward(f: QTT, w: QTT, w_dB: QTT | None, grad_y: torch.Tensor):
+    """``(grad_f, grad_B)`` of ``y = T(w) full(f)`` for the upstream gradient ``grad_y``."""
+    if grad_y.dtype != _TORCH[f.dtype] or grad_y.numel() != (1 << f.d):
+        raise QttError(-1, "conv_full_backward: grad_y must have 2^d entries of f's dtype")
+    grad_y = grad_y.contiguous()
+    fcap = (ctypes.c_int32 * (f.d + 1))(*f.cap)
+    wcap = (ctypes.c_int32 * (w.d + 1))(*w.cap)
+    bcap = (ctypes.c_int32 * (w_dB.d + 1))(*w_dB.cap) if w_dB is not None else None
+    wsb = ctypes.c_size_t()
+    _check(lib().qtt_query_conv_full_backward(f.d, fcap, wcap, bcap, f.dtype, ctypes.byref(wsb)),
+           "qtt_query_conv_full_backward")
+    gr = _grad_like(f)
+    gB = torch.zeros(1, dtype=torch.float64, device=f.device) if w_dB is not None else None
+    ws = _workspace(wsb.value, f.device)
+    fc, wc, gc = f._c(), w._c(), gr._c()
+    bc = w_dB._c() if w_dB is not None else None
+    _check(lib().qtt_conv_full_backward(
+        ctypes.byref(fc), ctypes.byref(wc), ctypes.byref(bc) if bc is not None else None,
+        ctypes.c_void_p(grad_y.data_ptr()), ctypes.byref(gc),
+        ctypes.c_void_p(gB.data_ptr()) if gB is not None else None,
+        ctypes.c_void_p(ws.data_ptr()), wsb.value, _stream(f.device)), "qtt_conv_full_backward")
+    return gr, gB
+
+
+def _with_cores(template: QTT, cores: torch.Tensor) -> QTT:
+    t = QTT.__new__(QTT)
+    t.d, t.dtype, t.cap, t.device = template.d, template.dtype, list(template.cap), template.device
+    t.cores = cores.detach()
+    t.ranks = template.ranks
+    t.status = template.status
+    t._keep = []
+    return t
+
+
+class ConvFull(torch.autograd.Function):
+    """``y = T(w(B)) full(F)`` at fixed ranks, differentiable in the cores and ``B``.
+
+    ``forward(cores, B, template, eps_w, eps_dB)``: ``cores`` is the flat
+    capacity-strided core array of ``template`` (a QTT whose ranks are kept);
+    ``B`` a one-element tensor.  The kernel QTT ``w(B)`` is built at
+    ``eps_w``; the backward builds the QTT of ``dw/dB`` at ``eps_dB`` and
+    recomputes ``full(F)`` instead of storing it.
+    """
+
+    @staticmethod
+    def forward(ctx, cores, B, template, eps_w, eps_dB):
+        f = _with_cores(template, cores)
+        dt = _TORCH[f.dtype]
+        w = kernel_sinc(f.d, float(B), eps_w, dt, f.device)
+        x = full(f)
+        y = toeplitz_apply(w, x)
+        ctx.save_for_backward(cores, B)
+        ctx.template, ctx.w, ctx.eps_dB = template, w, eps_dB
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        cores, B = ctx.saved_tensors
+        f = _with_cores(ctx.template, cores)
+        need_b = ctx.needs_input_grad[1]
+        wdb = kernel_sinc_dB(f.d, float(B), ctx.eps_dB, _TORCH[f.dtype], f.device) if need_b \
+            else None
+        gr, gB = conv_full_backward(f, ctx.w, wdb, gy.to(_TORCH[f.dtype]))
+        gcores = gr.cores if ctx.needs_input_grad[0] else None
+        gb = gB.to(device=B.device, dtype=B.dtype).reshape(B.shape) if need_b else None
+        return gcores, gb, None, None, None
+
+
+def conv_full(f: QTT, B: torch.Tensor, cores: torch.Tensor | None = None, eps_w: float = 1e-12,
+              eps_dB: float = 1e-12) -> torch.Tensor:
+    """Differentiable ``T(w(B)) full(F)``; ``cores`` defaults to ``f.cores``."""
+    return ConvFull.apply(f.cores if cores is None else cores, B, f, eps_w, eps_dB)

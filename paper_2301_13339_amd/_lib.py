@@ -25,13 +25,17 @@ EXPORTS = [
     "qtt_query_conv", "qtt_conv",
     "qtt_query_round", "qtt_round",
     "qtt_query_full", "qtt_full",
+    "qtt_query_toeplitz", "qtt_toeplitz_apply",
+    "qtt_query_kernel_sinc_dB", "qtt_kernel_sinc_dB",
+    "qtt_query_full_adjoint", "qtt_full_adjoint",
+    "qtt_query_conv_full_backward", "qtt_conv_full_backward",
     "qtt_probe_start", "qtt_probe_stop",
 ]
 
 # kernel classes of the launch probe (include/qtt.h)
 K_CLASSES = {
     "level_gram": 1, "reduce": 2, "level_eig": 3, "project": 4, "eig_step": 5, "tail": 6,
-    "conv": 7, "full_chain": 8, "full_final": 9, "other": 10,
+    "conv": 7, "full_chain": 8, "full_final": 9, "other": 10, "adjoint": 11,
 }
 
 
@@ -90,6 +94,24 @@ def _declare(L):
     L.qtt_query_full.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _SZP]
     L.qtt_full.restype = ctypes.c_int
     L.qtt_full.argtypes = [_TP, _VP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_query_toeplitz.restype = ctypes.c_int
+    L.qtt_query_toeplitz.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _SZP]
+    L.qtt_toeplitz_apply.restype = ctypes.c_int
+    L.qtt_toeplitz_apply.argtypes = [_TP, _VP, _VP, ctypes.c_int, _VP, ctypes.c_size_t, _VP]
+    L.qtt_query_kernel_sinc_dB.restype = ctypes.c_int
+    L.qtt_query_kernel_sinc_dB.argtypes = [ctypes.c_int, ctypes.c_int, _I32P, _SZP, _SZP]
+    L.qtt_kernel_sinc_dB.restype = ctypes.c_int
+    L.qtt_kernel_sinc_dB.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                     _TP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_query_full_adjoint.restype = ctypes.c_int
+    L.qtt_query_full_adjoint.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _SZP]
+    L.qtt_full_adjoint.restype = ctypes.c_int
+    L.qtt_full_adjoint.argtypes = [_TP, _VP, _TP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_query_conv_full_backward.restype = ctypes.c_int
+    L.qtt_query_conv_full_backward.argtypes = [ctypes.c_int, _I32P, _I32P, _I32P, ctypes.c_int,
+                                               _SZP]
+    L.qtt_conv_full_backward.restype = ctypes.c_int
+    L.qtt_conv_full_backward.argtypes = [_TP, _TP, _TP, _VP, _TP, _VP, _VP, ctypes.c_size_t, _VP]
     L.qtt_probe_start.restype = ctypes.c_int
     L.qtt_probe_start.argtypes = [ctypes.c_int, ctypes.c_int]
     L.qtt_probe_stop.restype = ctypes.c_int

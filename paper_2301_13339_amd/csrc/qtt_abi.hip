@@ -114,7 +114,7 @@ const char* qtt_strerror(int code) {
 const char* qtt_last_hip_error(void) { return g_hip_err; }
 
 int qtt_probe_start(int cls, int max_launches) {
-  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_OTHER || max_launches < 1 || max_launches > (1 << 20))
+  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_ADJOINT || max_launches < 1 || max_launches > (1 << 20))
     return QTT_EINVAL;
   probe_free();
   g_probe.ev = new hipEvent_t[2 * (size_t)max_launches];
@@ -349,6 +349,176 @@ int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_
   Source src{rp.yfull, 0, 0.0, 0};
   TensorDev zd = make_dev(z);
   return run_decompose(p, src, eps, zd, nullptr, st);
+}
+
+// --------------------------------------------------------------- adjoint
+static int wcap_ok(const int32_t* w_cap, int D) {
+  if (!w_cap || w_cap[0] != 1 || w_cap[D] != 1) return 0;
+  for (int k = 1; k < D; ++k)
+    if (w_cap[k] < 1 || w_cap[k] > QTT_MAX_RANK) return 0;
+  return 1;
+}
+
+int qtt_query_toeplitz(int d, const int32_t* w_cap, int dtype, size_t* ws_bytes) {
+  if (d < 1 || d > kMaxModes || !dtype_ok(dtype) || !wcap_ok(w_cap, d + 1)) return QTT_EINVAL;
+  if (ws_bytes) *ws_bytes = toeplitz_ws_elems(d, w_cap) * sizeof(double);
+  return QTT_OK;
+}
+
+int qtt_toeplitz_apply(const qtt_tensor* w, const void* x, void* y, int transpose, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (check_tensor_in(w) || w->d < 2 || !x || !y || (transpose != 0 && transpose != 1))
+    return QTT_EINVAL;
+  const int d = w->d - 1;
+  if (d > kMaxModes || !wcap_ok(w->cap, w->d)) return QTT_EINVAL;
+  const size_t need = toeplitz_ws_elems(d, w->cap) * sizeof(double);
+  if (!ws || ws_bytes < need) return ws ? QTT_ENOSPC : QTT_EINVAL;
+  TensorDev wd = make_dev(w);
+  return run_toeplitz(wd, w->dtype, x, y, transpose, ws, static_cast<hipStream_t>(stream));
+}
+
+int qtt_query_kernel_sinc_dB(int d, int dtype, int32_t* cap, size_t* ws_bytes,
+                             size_t* core_elems) {
+  if (d < 1 || d > kMaxModes) return QTT_EINVAL;
+  size_t b = 0;
+  const int rc = qtt_query_decompose(d + 1, 0, dtype, cap, &b, core_elems);
+  if (rc) return rc;
+  if (ws_bytes) *ws_bytes = b + sinc_sums_ws_bytes();
+  return QTT_OK;
+}
+
+int qtt_kernel_sinc_dB(int d, double B, double eps_w, int dtype, qtt_tensor* w_out, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (d < 1 || d > kMaxModes || !(B > 0.0) || !isfinite(B) || !ws) return QTT_EINVAL;
+  const size_t sb = sinc_sums_ws_bytes();
+  if (ws_bytes < sb) return QTT_ENOSPC;
+  // validate everything before the first launch
+  {
+    DecompPlan p;
+    if (d + 1 > kMaxModes + 1 || !dtype_ok(dtype) || !(eps_w >= 0.0) || !isfinite(eps_w))
+      return QTT_EINVAL;
+    plan_decompose(d + 1, eff_rank(0), dtype, nullptr, &p);
+    if (ws_bytes - sb < p.ws_bytes) return QTT_ENOSPC;
+    int32_t need[QTT_MAXD + 1];
+    caps_decompose(d + 1, eff_rank(0), need);
+    const int rc = check_tensor(w_out, d + 1, dtype, need);
+    if (rc) return rc;
+  }
+  double* consts = nullptr;
+  int rc = run_sinc_sums(B, d, ws, &consts, static_cast<hipStream_t>(stream));
+  if (rc) return rc;
+  Source src{consts, 2, B, d};
+  return decompose_common(src, d + 1, dtype, eps_w, 0, w_out, nullptr,
+                          static_cast<char*>(ws) + sb, ws_bytes - sb, stream);
+}
+
+int qtt_query_full_adjoint(int d, const int32_t* cap, int dtype, size_t* ws_bytes) {
+  if (d < 1 || d > kMaxModes || !cap || !dtype_ok(dtype)) return QTT_EINVAL;
+  for (int k = 0; k <= d; ++k)
+    if (cap[k] < 1 || cap[k] > QTT_MAX_RANK) return QTT_EINVAL;
+  if (ws_bytes) *ws_bytes = full_adjoint_ws_bytes(d, cap, dtype);
+  return QTT_OK;
+}
+
+static int grad_tensor_ok(const qtt_tensor* f, const qtt_tensor* g) {
+  if (!g || g->d != f->d || g->dtype != f->dtype || !g->ranks || !g->cores) return QTT_EINVAL;
+  for (int k = 0; k <= f->d; ++k)
+    if (g->cap[k] != f->cap[k]) return QTT_EINVAL;
+  return QTT_OK;
+}
+
+int qtt_full_adjoint(const qtt_tensor* f, const void* g, qtt_tensor* grad, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (check_tensor_in(f) || f->d > kMaxModes || !g || grad_tensor_ok(f, grad)) return QTT_EINVAL;
+  for (int k = 0; k <= f->d; ++k)
+    if (f->cap[k] > QTT_MAX_RANK) return QTT_ENOTSUP;
+  const size_t need = full_adjoint_ws_bytes(f->d, f->cap, f->dtype);
+  if (!ws || ws_bytes < need) return ws ? QTT_ENOSPC : QTT_EINVAL;
+  TensorDev fd = make_dev(f), gd = make_dev(grad);
+  return run_full_adjoint(fd, f->dtype, g, gd, ws, static_cast<hipStream_t>(stream));
+}
+
+struct BwdPlan {
+  void* ffull;
+  void* gf;
+  void* z;
+  void* toep_ws;
+  void* full_ws;
+  void* adj_ws;
+  double* dot_part;
+  size_t total;
+};
+
+static void plan_backward(int d, const int32_t* f_cap, const int32_t* w_cap,
+                          const int32_t* wdb_cap, int dtype, void* ws, BwdPlan* p) {
+  Arena ar(ws);
+  const size_t es = elem_size(dtype);
+  const size_t N = (size_t)1 << d;
+  p->ffull = ar.take<char>(N * es);
+  p->gf = ar.take<char>(N * es);
+  p->z = wdb_cap ? ar.take<char>(N * es) : nullptr;
+  size_t te = toeplitz_ws_elems(d, w_cap);
+  if (wdb_cap) {
+    const size_t t2 = toeplitz_ws_elems(d, wdb_cap);
+    if (t2 > te) te = t2;
+  }
+  p->toep_ws = ar.take<double>(te);
+  void* bufs[4];
+  size_t fb = 0;
+  plan_full(d, f_cap, dtype, nullptr, &fb, bufs);
+  p->full_ws = ar.take<char>(fb > 0 ? fb : 1);
+  p->adj_ws = ar.take<char>(full_adjoint_ws_bytes(d, f_cap, dtype));
+  p->dot_part = ar.take<double>(kDotPartials + 8);
+  p->total = ar.size();
+}
+
+int qtt_query_conv_full_backward(int d, const int32_t* f_cap, const int32_t* w_cap,
+                                 const int32_t* wdb_cap, int dtype, size_t* ws_bytes) {
+  if (d < 1 || d > kMaxModes || !f_cap || !dtype_ok(dtype) || !wcap_ok(w_cap, d + 1) ||
+      (wdb_cap && !wcap_ok(wdb_cap, d + 1)))
+    return QTT_EINVAL;
+  for (int k = 0; k <= d; ++k)
+    if (f_cap[k] < 1 || f_cap[k] > QTT_MAX_RANK) return QTT_EINVAL;
+  BwdPlan p;
+  plan_backward(d, f_cap, w_cap, wdb_cap, dtype, nullptr, &p);
+  if (ws_bytes) *ws_bytes = p.total;
+  return QTT_OK;
+}
+
+int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_tensor* w_dB,
+                           const void* grad_y, qtt_tensor* grad_f, double* grad_B, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (check_tensor_in(f) || f->d > kMaxModes || check_tensor_in(w) || !grad_y ||
+      grad_tensor_ok(f, grad_f))
+    return QTT_EINVAL;
+  const int d = f->d;
+  if (w->d != d + 1 || w->dtype != f->dtype || !wcap_ok(w->cap, d + 1)) return QTT_EINVAL;
+  if (w_dB && (check_tensor_in(w_dB) || w_dB->d != d + 1 || w_dB->dtype != f->dtype ||
+               !wcap_ok(w_dB->cap, d + 1)))
+    return QTT_EINVAL;
+  if ((w_dB == nullptr) != (grad_B == nullptr)) return QTT_EINVAL;
+  for (int k = 0; k <= d; ++k)
+    if (f->cap[k] > QTT_MAX_RANK) return QTT_ENOTSUP;
+  BwdPlan p;
+  plan_backward(d, f->cap, w->cap, w_dB ? w_dB->cap : nullptr, f->dtype, nullptr, &p);
+  if (!ws || ws_bytes < p.total) return ws ? QTT_ENOSPC : QTT_EINVAL;
+  plan_backward(d, f->cap, w->cap, w_dB ? w_dB->cap : nullptr, f->dtype, ws, &p);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  TensorDev fd = make_dev(f), wd = make_dev(w), gd = make_dev(grad_f);
+  // the core chain is recomputed here rather than kept from the forward
+  int rc = run_full(fd, f->dtype, p.ffull, p.full_ws, st);
+  if (rc) return rc;
+  rc = run_toeplitz(wd, f->dtype, grad_y, p.gf, 1, p.toep_ws, st);
+  if (rc) return rc;
+  rc = run_full_adjoint(fd, f->dtype, p.gf, gd, p.adj_ws, st);
+  if (rc) return rc;
+  if (w_dB) {
+    TensorDev bd = make_dev(w_dB);
+    rc = run_toeplitz(bd, f->dtype, p.ffull, p.z, 0, p.toep_ws, st);
+    if (rc) return rc;
+    rc = run_dot(f->dtype, grad_y, p.z, 1LL << d, p.dot_part, grad_B, st);
+  }
+  return rc;
 }
 
 }  // extern "C"

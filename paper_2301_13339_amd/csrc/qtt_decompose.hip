@@ -28,26 +28,26 @@
 
 #include "qtt_eig.hpp"
 #include "qtt_internal.hpp"
+#include "qtt_sinc.hpp"
 
 namespace qtt {
 
 // ------------------------------------------------------------ sample access
-// Generator of the sinc-kernel Toeplitz vector, unnormalised: for a kernel
-// grid of 2^nk samples x_m = -1/2 + m/2^nk, s_u = sinc(B x_{u - 2^(nk-1)}) for
-// 2^(nk-1) <= u < 3*2^(nk-1), else 0 (normalised later by the sample sum).
-__device__ __forceinline__ double sinc_gen(long long u, double B, int nk) {
-  const long long nn = 1LL << nk;
-  const long long m = u - (nn >> 1);
-  if (m < 0 || m >= nn) return 0.0;
-  const double x = -0.5 + (double)m / (double)nn;
-  const double t = B * x;
-  if (t == 0.0) return 1.0;
-  return sinpi(t) / (M_PI * t);
-}
-
+// GEN = 0: stored samples x[u].
+// GEN = 1: generator of the sinc-kernel Toeplitz vector, unnormalised (the
+//          last core is divided by the sample sum afterwards).
+// GEN = 2: derivative of the normalised generator with respect to the
+//          bandwidth, (s'_m - s_m S'/S) / S, with c = (1/S, S'/S) read from
+//          the device array passed in place of the samples.
 template <typename T, int GEN>
 __device__ __forceinline__ double sample(const T* x, long long u, double B, int nk) {
-  if (GEN) return sinc_gen(u, B, nk);
+  if (GEN == 1) return sinc_gen(u, B, nk);
+  if (GEN == 2) {
+    const double* c = reinterpret_cast<const double*>(x);
+    double sv, dv;
+    sinc_gen_pair(u, B, nk, &sv, &dv);
+    return (dv - sv * c[1]) * c[0];
+  }
   return (double)x[u];
 }
 
@@ -72,8 +72,8 @@ __global__ void k_single(const T* x, double B, int nk, T* cores, int32_t* ranks,
                          int32_t* status) {
   if (threadIdx.x == 0) {
     const double v0 = sample<T, GEN>(x, 0, B, nk), v1 = sample<T, GEN>(x, 1, B, nk);
-    double s = GEN ? v0 + v1 : 1.0;
-    if (GEN && s == 0.0) s = 1.0;
+    double s = (GEN == 1) ? v0 + v1 : 1.0;
+    if (s == 0.0) s = 1.0;
     cores[0] = (T)(v0 / s);
     cores[1] = (T)(v1 / s);
     ranks[0] = 1;
@@ -186,7 +186,7 @@ struct StepOut {
 // kept eigenvectors in the first r columns of V (descending eigenvalues):
 // lam[0..E) = eigenvalues in non-increasing order, perm[b] = b.  sx: scratch
 // of kEigScratch doubles.  Returns r.  Must be called by all threads.
-constexpr int kEigScratch = 7 * kMaxM + 16;
+constexpr int kEigScratch = 10 * kMaxM + 16;
 // one workgroup of 4 waves: a barrier costs ~40 cycles with 4 waves and
 // ~470 with 16 on gfx950, and every eigen step is barrier/latency bound
 constexpr int kEigThreads = 256;
@@ -272,7 +272,8 @@ __device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* 
 #ifdef QTT_EIG_TIMING
   tt[3] = wall_clock64();
 #endif
-  mgs_cols<NT>(V, E, lda, r);
+  // pv .. pv + 7 kMaxM (pv, e2, la and the arrays after) are free now
+  mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
 #ifdef QTT_EIG_TIMING
   tt[4] = wall_clock64();
 #endif
@@ -759,6 +760,8 @@ static void set_attrs() {
                       (int)lds_tail());
   hipFuncSetAttribute((const void*)k_tail<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
                       (int)lds_tail());
+  hipFuncSetAttribute((const void*)k_tail<T, GEN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                      (int)lds_tail());
   hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 1>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 2>,
@@ -846,7 +849,7 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
     {
       ProbeScope _ps(QTT_K_TAIL, stream);
       k_tail<T, GEN><<<1, kEigThreads, lds_tail(), stream>>>(x, src.B, src.nk, 1, D, eps, meta, cores,
-                                                     P.scal, src.gen, so, P.iflags);
+                                                     P.scal, src.gen == 1, so, P.iflags);
     }
     QTT_LAUNCH_CHECK();
     {
@@ -929,7 +932,7 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
                                                 P.iflags);
   }
   QTT_LAUNCH_CHECK();
-  if (src.gen) {
+  if (src.gen == 1) {
     {
       ProbeScope _ps(QTT_K_OTHER, stream);
       k_scale_last<T><<<1, 256, 0, stream>>>(cores, out.off[D - 1], out.ranks, D, P.scal);
@@ -947,9 +950,11 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
 int run_decompose(const DecompPlan& P, const Source& src, double eps, const TensorDev& out,
                   double* sv, hipStream_t stream) {
   if (P.dtype == QTT_F64) {
+    if (src.gen == 2) return run_decompose_t<double, 2>(P, src, eps, out, sv, stream);
     return src.gen ? run_decompose_t<double, 1>(P, src, eps, out, sv, stream)
                    : run_decompose_t<double, 0>(P, src, eps, out, sv, stream);
   }
+  if (src.gen == 2) return run_decompose_t<float, 2>(P, src, eps, out, sv, stream);
   return src.gen ? run_decompose_t<float, 1>(P, src, eps, out, sv, stream)
                  : run_decompose_t<float, 0>(P, src, eps, out, sv, stream);
 }

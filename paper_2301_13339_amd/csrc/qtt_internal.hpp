@@ -148,4 +148,17 @@ int run_full(const TensorDev& t, int dtype, void* out, void* ws, hipStream_t str
 int run_conv(const TensorDev& f, const TensorDev* w, int n_axes, const int32_t* axis_modes,
              const TensorDev& y, int dtype, hipStream_t stream);
 
+// ------------------------------------------------------------------ adjoint
+size_t toeplitz_ws_elems(int d, const int32_t* w_cap);
+int run_toeplitz(const TensorDev& w, int dtype, const void* x, void* y, int trans, void* ws,
+                 hipStream_t s);
+size_t full_adjoint_ws_bytes(int d, const int* cap, int dtype);
+int run_full_adjoint(const TensorDev& f, int dtype, const void* g, const TensorDev& gr, void* ws,
+                     hipStream_t s);
+constexpr int kDotPartials = 512;
+int run_dot(int dtype, const void* a, const void* b, long long n, double* part, double* out,
+            hipStream_t s);
+size_t sinc_sums_ws_bytes();
+int run_sinc_sums(double B, int nk, void* ws, double** consts, hipStream_t s);
+
 }  // namespace qtt

@@ -442,19 +442,145 @@ __device__ inline void tridiag_vec(const double* dg, const double* od, int E, do
   for (int i = 0; i < E; ++i) z[i * ldz] *= inv;
 }
 
+// Solve (T - mu I) y = b in place (b[i*ldb], i < E) by Gaussian elimination
+// with partial pivoting on the tridiagonal matrix (one lane).  Zero pivots
+// are replaced by `tiny` (inverse iteration only needs a direction).
+// w: 5E doubles of scratch.
+__device__ inline void tridiag_shift_solve(const double* dg, const double* od, int E, double mu,
+                                           double* b, int ldb, double* w, double tiny) {
+  double* dd = w;           // diagonal of U
+  double* du = w + E;       // first superdiagonal of U
+  double* du2 = w + 2 * E;  // second superdiagonal (fill-in from interchanges)
+  double* ml = w + 3 * E;   // multipliers
+  double* sw = w + 4 * E;   // 1 where rows i and i+1 were interchanged
+  for (int i = 0; i < E; ++i) {
+    dd[i] = dg[i] - mu;
+    du[i] = (i + 1 < E) ? od[i] : 0.0;
+    du2[i] = 0.0;
+  }
+  for (int i = 0; i + 1 < E; ++i) {
+    const double lo = od[i];  // subdiagonal entry below dd[i]
+    if (fabs(dd[i]) >= fabs(lo)) {
+      const double piv = (dd[i] != 0.0) ? dd[i] : tiny;
+      dd[i] = piv;
+      const double f = lo / piv;
+      ml[i] = f;
+      sw[i] = 0.0;
+      dd[i + 1] -= f * du[i];
+    } else {
+      // interchange rows i and i+1, then eliminate
+      const double f = dd[i] / lo;
+      dd[i] = lo;
+      ml[i] = f;
+      sw[i] = 1.0;
+      const double t = du[i];
+      du[i] = dd[i + 1];
+      dd[i + 1] = t - f * dd[i + 1];
+      if (i + 2 < E) {
+        du2[i] = du[i + 1];
+        du[i + 1] = -f * du[i + 1];
+      }
+    }
+  }
+  if (dd[E - 1] == 0.0) dd[E - 1] = tiny;
+  // forward: row interchanges and L
+  for (int i = 0; i + 1 < E; ++i) {
+    if (sw[i] == 0.0) {
+      b[(i + 1) * ldb] -= ml[i] * b[i * ldb];
+    } else {
+      const double t = b[i * ldb];
+      b[i * ldb] = b[(i + 1) * ldb];
+      b[(i + 1) * ldb] = t - ml[i] * b[i * ldb];
+    }
+  }
+  // backward: U
+  for (int i = E - 1; i >= 0; --i) {
+    double v = b[i * ldb];
+    if (i + 1 < E) v -= du[i] * b[(i + 1) * ldb];
+    if (i + 2 < E) v -= du2[i] * b[(i + 2) * ldb];
+    b[i * ldb] = v / dd[i];
+  }
+}
+
+// Classical Gram-Schmidt (applied twice) of column j of Z against columns
+// 0..j-1 (mutually orthogonal, squared norms cn[c]).  al: >= j doubles.
+template <int NT>
+__device__ void cgs2_col(double* Z, int E, int ldz, int j, const double* cn, double* al) {
+  const int tid = threadIdx.x;
+  const int l16 = tid & 15, g16 = tid >> 4;
+  constexpr int NG16 = NT / 16;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int c = g16; c < j; c += NG16) {
+      double dt = 0.0;
+      for (int i = l16; i < E; i += 16) dt = fma(Z[i * ldz + c], Z[i * ldz + j], dt);
+      dt = sum16(dt);
+      if (l16 == 0) al[c] = cn[c] > 0.0 ? dt / cn[c] : 0.0;
+    }
+    __syncthreads();
+    for (int i = tid; i < E; i += NT) {
+      double v = Z[i * ldz + j];
+      for (int c = 0; c < j; ++c) v = fma(-al[c], Z[i * ldz + c], v);
+      Z[i * ldz + j] = v;
+    }
+    __syncthreads();
+  }
+}
+
+// Squared norm of column j (identical in every 16-lane group).
+__device__ __forceinline__ double col_norm2(const double* Z, int E, int ldz, int j) {
+  const int l16 = threadIdx.x & 15;
+  double s = 0.0;
+  for (int i = l16; i < E; i += 16) s = fma(Z[i * ldz + j], Z[i * ldz + j], s);
+  return sum16(s);
+}
+
 // Modified Gram-Schmidt on columns 0..r-1 of Z (E rows, stride ldz), in
 // order.  Column c belongs to the 16-lane group c mod (NT/16), which alone
 // updates it; step j removes the (unnormalised) column j from every later
 // column, and all columns are normalised at the end.  One barrier per step.
+//
+// A column that loses most of its norm to the earlier ones came from a
+// (numerically) multiple eigenvalue: the twisted factorisation returns the
+// same vector for every copy.  It is replaced by inverse iteration with T
+// shifted just above lam[j], from a dense start vector kept orthogonal to the
+// earlier columns, so the replacement lies in the same eigenspace.  ms: >= kMaxRank + 6 kMaxM doubles.
 template <int NT>
-__device__ void mgs_cols(double* Z, int E, int ldz, int r) {
+__device__ void mgs_cols(double* Z, int E, int ldz, int r, const double* dg, const double* od,
+                         const double* lam, double* ms) {
   const int tid = threadIdx.x;
   const int l16 = tid & 15, g16 = tid >> 4;
   constexpr int NG16 = NT / 16;
-  for (int j = 0; j + 1 < r; ++j) {
-    double s = 0.0;
-    for (int i = l16; i < E; i += 16) s = fma(Z[i * ldz + j], Z[i * ldz + j], s);
-    s = sum16(s);
+  double* cn = ms;                     // kMaxRank: squared norms of the finished columns
+  double* al = ms + kMaxRank;          // kMaxM: projection coefficients / weights
+  double* lu = al + kMaxM;             // 5 kMaxM: solver scratch
+  double tnrm = 0.0;
+  for (int i = 0; i < E; ++i)
+    tnrm = fmax(tnrm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0));
+  for (int j = 0; j < r; ++j) {
+    double s = col_norm2(Z, E, ldz, j);
+    if (j > 0 && !(s >= 0.25)) {  // uniform: every group computed the same s
+      // dense deterministic start vector (an integer hash of (i, j)), so it
+      // has a component in every eigenspace
+      for (int i = tid; i < E; i += NT) {
+        const unsigned int h = (unsigned int)(i + 1) * 2654435761u ^ (unsigned int)(j + 7) * 40503u;
+        Z[i * ldz + j] = (double)(h >> 8) * (1.0 / 8388608.0) - 1.0;
+      }
+      __syncthreads();
+      const double mu = lam[j] + 1e-13 * tnrm;
+      for (int it = 0; it < 2; ++it) {
+        cgs2_col<NT>(Z, E, ldz, j, cn, al);
+        if (tid == 0) tridiag_shift_solve(dg, od, E, mu, Z + j, ldz, lu, 1e-300 + 1e-30 * tnrm);
+        __syncthreads();
+        const double t = col_norm2(Z, E, ldz, j);
+        const double inv = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+        __syncthreads();
+        for (int i = tid; i < E; i += NT) Z[i * ldz + j] *= inv;
+        __syncthreads();
+      }
+      cgs2_col<NT>(Z, E, ldz, j, cn, al);
+      s = col_norm2(Z, E, ldz, j);
+    }
+    if (tid == 0) cn[j] = s;
     const double inv = s > 0.0 ? 1.0 / s : 0.0;
     for (int c = j + 1 + ((g16 - (j + 1) % NG16 + NG16) % NG16); c < r; c += NG16) {
       double d = 0.0;

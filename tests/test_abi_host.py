@@ -133,3 +133,53 @@ def test_probe_arguments():
     so = L.lib()
     assert so.qtt_probe_start(0, 10) == -1
     assert so.qtt_probe_start(3, 0) == -1
+
+
+def test_adjoint_entry_points_validate():
+    L = _lib()
+    so = L.lib()
+    fake = ctypes.c_void_p(0x1000)
+    # generator capacities for d = 4 (5 modes)
+    wcap = (ctypes.c_int32 * 6)(1, 2, 4, 4, 2, 1)
+    ws = ctypes.c_size_t()
+    assert so.qtt_query_toeplitz(4, wcap, L.QTT_F64, ctypes.byref(ws)) == 0
+    assert ws.value == 2 * (2 * 4) * 16 * 8
+    bad = (ctypes.c_int32 * 6)(1, 2, 99, 4, 2, 1)
+    assert so.qtt_query_toeplitz(4, bad, L.QTT_F64, ctypes.byref(ws)) == -1
+    w = L.qtt_tensor()
+    w.d, w.dtype = 5, L.QTT_F64
+    for k in range(6):
+        w.cap[k] = wcap[k]
+    w.ranks = fake
+    w.cores = fake
+    # transpose flag must be 0 or 1; workspace must be large enough
+    assert so.qtt_toeplitz_apply(ctypes.byref(w), fake, fake, 2, fake, 1 << 20, None) == -1
+    assert so.qtt_toeplitz_apply(ctypes.byref(w), fake, fake, 0, fake, 8, None) == -2
+    # kernel derivative: bad bandwidth
+    assert so.qtt_kernel_sinc_dB(4, -1.0, 1e-8, L.QTT_F64, ctypes.byref(w), fake, 1 << 20,
+                                 None) == -1
+    cap = (ctypes.c_int32 * 6)()
+    assert so.qtt_query_kernel_sinc_dB(4, L.QTT_F64, cap, ctypes.byref(ws), None) == 0
+    assert list(cap) == [1, 2, 4, 4, 2, 1]
+    # backward: w_dB and grad_B come together; grad tensor must mirror f
+    f = L.qtt_tensor()
+    f.d, f.dtype = 4, L.QTT_F64
+    for k, c in enumerate([1, 2, 4, 2, 1]):
+        f.cap[k] = c
+    f.ranks = fake
+    f.cores = fake
+    g = L.qtt_tensor()
+    ctypes.pointer(g)[0] = f
+    assert so.qtt_conv_full_backward(ctypes.byref(f), ctypes.byref(w), ctypes.byref(w), fake,
+                                     ctypes.byref(g), None, fake, 1 << 30, None) == -1
+    g.cap[2] = 3
+    assert so.qtt_conv_full_backward(ctypes.byref(f), ctypes.byref(w), None, fake,
+                                     ctypes.byref(g), None, fake, 1 << 30, None) == -1
+    g.cap[2] = 4
+    assert so.qtt_conv_full_backward(ctypes.byref(f), ctypes.byref(w), None, fake,
+                                     ctypes.byref(g), None, fake, 16, None) == -2
+    fcap = (ctypes.c_int32 * 5)(1, 2, 4, 2, 1)
+    assert so.qtt_query_conv_full_backward(4, fcap, wcap, None, L.QTT_F64,
+                                           ctypes.byref(ws)) == 0
+    assert ws.value > 0
+    assert so.qtt_query_full_adjoint(4, fcap, L.QTT_F64, ctypes.byref(ws)) == 0

@@ -102,3 +102,21 @@ def test_grad_w_definition_small():
         for i in range(n):
             ref[j - i + n] += gy[j] * f[i]
     assert np.allclose(gw, ref, atol=1e-12)
+
+
+def test_full_adjoint_multilinear_identity():
+    """full is linear in each core, so <dG/dF_k, F_k> = G = <g, full(F)> for every k."""
+    d = 8
+    rng = np.random.default_rng(11)
+    cores = tt.tt_svd(rng.standard_normal(1 << d), 1e-2, 5)
+    g = rng.standard_normal(1 << d)
+    G = float(g @ tt.tt_full(cores))
+    gc = grads.full_adjoint(cores, g)
+    for k in range(d):
+        assert float(np.sum(gc[k] * cores[k])) == pytest.approx(G, rel=1e-12)
+
+
+def test_generator_dB_central_differences():
+    d, B, h = 7, 30.0, 1e-6
+    fd = (conv.toeplitz_generator(d, B + h) - conv.toeplitz_generator(d, B - h)) / (2 * h)
+    assert np.allclose(grads.generator_dB(d, B), fd, rtol=0, atol=1e-8)
