@@ -277,6 +277,64 @@ int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_t
                            const void* grad_y, qtt_tensor* grad_f, double* grad_B, void* ws,
                            size_t ws_bytes, void* stream);
 
+/* ---------------------------------------------------------------- batched */
+/*
+ * Many independent lines (e.g. SAR range lines) through the whole pipeline
+ * of qtt_decompose / qtt_kernel_sinc / exact convolution / rounding /
+ * qtt_full, each line with its own length 2^d[l] and bandwidth B[l], in a
+ * handful of launches over the whole batch that qtt_batch_run can capture
+ * in one hipGraph (replayed by later calls with the same pointers).
+ * Per line the result equals the single-signal pipeline with the same
+ * parameters: signal TT-SVD at eps with rank cap max_rank, kernel QTT at
+ * eps_w (rank cap w_max_rank, 0 = 24), y = T(w) full(F) exactly, rounding =
+ * TT-SVD of y at eps (cap round_max_rank, 0 = QTT_MAX_RANK), out = full.
+ */
+#define QTT_BATCH_MAXD 18       /* largest d of a line in a batch               */
+
+typedef struct qtt_batch qtt_batch;  /* host-side plan (line tables, graph) */
+
+/*
+ * Plan a batch: d[l] (1..QTT_BATCH_MAXD) and B[l] > 0 are host arrays of
+ * n_lines entries.  The lines are stored back to back (line l at offset
+ * sum_{j<l} 2^d[j]) in x and out.  *ws_bytes receives the workspace size
+ * (tables, cores, ranks, full vectors, the Toeplitz state of
+ * 2 w_max_rank 2^d[l] elements per line and per-workgroup scratch).  The
+ * plan is host memory owned by the library; free it with qtt_batch_destroy.
+ * Errors: QTT_EINVAL (bad sizes, eps, ranks or bandwidths), QTT_ENOTSUP
+ * (w_max_rank above 24).
+ */
+int qtt_batch_create(int n_lines, const int32_t* d, const double* B, int dtype, double eps,
+                     int max_rank, double eps_w, int w_max_rank, int round_max_rank,
+                     qtt_batch** plan, size_t* ws_bytes);
+
+int qtt_batch_destroy(qtt_batch* plan);
+
+/*
+ * Run the batch: x (input samples) and out (results) are device arrays of
+ * sum 2^d[l] elements of the plan's dtype; ws is the workspace.  The first
+ * call tunes the chunk width of the Toeplitz stage by timing the candidates
+ * (it synchronises the stream once) and uploads the line tables into ws;
+ * with use_graph = 1 the stage launches are captured in a hipGraph on the
+ * first call for these pointers and replayed afterwards.  Per-line status
+ * words (non-finite input, rank capacity reached) are in the workspace (see
+ * qtt_batch_status_offset): 3 per line (signal, kernel, rounding).
+ */
+int qtt_batch_run(qtt_batch* plan, const void* x, void* out, void* ws, size_t ws_bytes,
+                  int use_graph, void* stream);
+
+/*
+ * Where line `line`'s tensors live in the workspace: which = 0 signal cores
+ * F, 1 kernel cores W (d+1 modes), 2 rounded cores Z.  Byte offsets of its
+ * int32 ranks (d+1 or d+2 entries) and of its capacity-strided cores, the
+ * rank cap of that family and the element offset of the line's samples.
+ */
+int qtt_batch_info(const qtt_batch* plan, int line, int which, int64_t* rank_off_bytes,
+                   int64_t* core_off_bytes, int32_t* rank_cap, int64_t* sample_off);
+
+/* Byte offset of the 3 x n_lines status words and the tuned chunk width. */
+int qtt_batch_status_offset(const qtt_batch* plan, int64_t* status_off_bytes,
+                            int32_t* chunk_bits);
+
 /* ------------------------------------------------------------ measurement */
 /*
  * Kernel classes for the launch probe.  Between qtt_probe_start and
@@ -298,6 +356,7 @@ int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_t
 #define QTT_K_FULL_FINAL 9   /* final product of Full (writes the 2^d outputs) */
 #define QTT_K_OTHER 10       /* bookkeeping kernels                            */
 #define QTT_K_ADJOINT 11     /* Toeplitz products on full vectors, adjoint of Full */
+#define QTT_K_BATCH 12       /* batched (many-line) kernels                     */
 
 int qtt_probe_start(int cls, int max_launches);
 int qtt_probe_stop(double* total_ms, int* launches);

@@ -29,7 +29,7 @@ from ._lib import (QTT_F32, QTT_F64, QTT_MAX_RANK, QTT_MAXD, QTT_ROUND_EXACT,
 __all__ = [
     "QTT", "probe", "from_cores", "decompose", "kernel_sinc", "conv", "round", "full", "pipeline",
     "toeplitz_apply", "kernel_sinc_dB", "full_adjoint", "conv_full_backward", "ConvFull",
-    "conv_full", "lib_path", "QttError", "QTT_MAX_RANK",
+    "conv_full", "Batch", "lib_path", "QttError", "QTT_MAX_RANK",
 ]
 
 _DT = {torch.float32: QTT_F32, torch.float64: QTT_F64}
@@ -448,3 +448,104 @@ def conv_full(f: QTT, B: torch.Tensor, cores: torch.Tensor | None = None, eps_w:
               eps_dB: float = 1e-12) -> torch.Tensor:
     """Differentiable ``T(w(B)) full(F)``; ``cores`` defaults to ``f.cores``."""
     return ConvFull.apply(f.cores if cores is None else cores, B, f, eps_w, eps_dB)
+
+
+# ------------------------------------------------------------------ batched
+class Batch:
+    """Many independent lines through the whole pipeline (``qtt_batch_*``).
+
+    ``d`` and ``B`` give each line's length ``2**d[l]`` and kernel bandwidth;
+    the lines are stored back to back in the input and output vectors.  The
+    plan owns its workspace (a torch uint8 tensor on ``device``).
+    """
+
+    def __init__(self, d, B, dtype=torch.float32, eps: float = 1e-4, max_rank: int = 32,
+                 eps_w: float | None = None, w_max_rank: int = 0, round_max_rank: int = 0,
+                 device="cuda"):
+        self.d = [int(v) for v in d]
+        self.B = [float(v) for v in B]
+        if len(self.d) != len(self.B) or not self.d:
+            raise QttError(-1, "Batch: d and B must have the same non-zero length")
+        self.n = len(self.d)
+        self.dtype = dtype
+        self.device = torch.device(device)
+        self.eps_w = eps / 10.0 if eps_w is None else eps_w
+        n = self.n
+        dd = (ctypes.c_int32 * n)(*self.d)
+        bb = (ctypes.c_double * n)(*self.B)
+        plan = ctypes.c_void_p()
+        wsb = ctypes.c_size_t()
+        _check(lib().qtt_batch_create(n, dd, bb, _DT[dtype], float(eps), int(max_rank),
+                                      float(self.eps_w), int(w_max_rank), int(round_max_rank),
+                                      ctypes.byref(plan), ctypes.byref(wsb)), "qtt_batch_create")
+        self._plan = plan
+        self._lib = lib()
+        self.ws = torch.empty(max(wsb.value, 1), dtype=torch.uint8, device=self.device)
+        self.offsets = []
+        o = 0
+        for v in self.d:
+            self.offsets.append(o)
+            o += 1 << v
+        self.samples = o
+
+    def __del__(self):
+        plan = getattr(self, "_plan", None)
+        if plan is not None and plan.value:
+            self._lib.qtt_batch_destroy(plan)
+            self._plan = None
+
+    def run(self, x: torch.Tensor, out: torch.Tensor | None = None, graph: bool = True):
+        if x.dtype != self.dtype or x.numel() != self.samples or not x.is_contiguous():
+            raise QttError(-1, "Batch.run: x must be contiguous with sum 2^d entries")
+        if out is None:
+            out = torch.empty_like(x)
+        _check(self._lib.qtt_batch_run(self._plan, ctypes.c_void_p(x.data_ptr()),
+                                       ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                       int(bool(graph)), _stream(self.device)), "qtt_batch_run")
+        return out
+
+    def line(self, v: torch.Tensor, l: int) -> torch.Tensor:
+        o = self.offsets[l]
+        return v[o:o + (1 << self.d[l])]
+
+    def _info(self, l, which):
+        ro, co = ctypes.c_int64(), ctypes.c_int64()
+        cap = ctypes.c_int32()
+        so = ctypes.c_int64()
+        _check(self._lib.qtt_batch_info(self._plan, int(l), int(which), ctypes.byref(ro),
+                                        ctypes.byref(co), ctypes.byref(cap), ctypes.byref(so)),
+               "qtt_batch_info")
+        return ro.value, co.value, cap.value
+
+    def ranks(self, l: int, which: int = 2):
+        """Ranks of line ``l``: which = 0 signal, 1 kernel, 2 rounded."""
+        ro, _, _ = self._info(l, which)
+        D = self.d[l] + (1 if which == 1 else 0)
+        r = self.ws[ro:ro + 4 * (D + 1)].view(torch.int32)
+        return [int(v) for v in r.cpu()]
+
+    def cores(self, l: int, which: int = 2):
+        """Cores of line ``l`` as CPU float64 arrays ``(r_{k-1}, 2, r_k)``."""
+        ro, co, cap = self._info(l, which)
+        D = self.d[l] + (1 if which == 1 else 0)
+        r = self.ranks(l, which)
+        caps = [1] + [min(cap, 1 << k, 1 << (D - k)) for k in range(1, D)] + [1]
+        es = 8 if self.dtype == torch.float64 else 4
+        n = sum(caps[k] * 2 * caps[k + 1] for k in range(D))
+        flat = self.ws[co:co + es * n].view(self.dtype).double().cpu().numpy()
+        out, o = [], 0
+        for k in range(D):
+            m = r[k] * 2 * r[k + 1]
+            out.append(flat[o:o + m].reshape(r[k], 2, r[k + 1]).copy())
+            o += caps[k] * 2 * caps[k + 1]
+        return out
+
+    def status(self):
+        """(3, n) status words: signal, kernel and rounding decomposition."""
+        so = ctypes.c_int64()
+        cb = ctypes.c_int32()
+        _check(self._lib.qtt_batch_status_offset(self._plan, ctypes.byref(so), ctypes.byref(cb)),
+               "qtt_batch_status_offset")
+        self.chunk_bits = cb.value
+        return self.ws[so.value:so.value + 12 * self.n].view(torch.int32).reshape(3, self.n).cpu()

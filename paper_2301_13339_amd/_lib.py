@@ -14,6 +14,7 @@ QTT_STATUS_NONFINITE = 1
 QTT_STATUS_RANKCAP = 2
 QTT_MAXD = 48
 QTT_MAX_RANK = 64
+QTT_BATCH_MAXD = 18
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(HERE, "libqtt.so")
@@ -29,6 +30,8 @@ EXPORTS = [
     "qtt_query_kernel_sinc_dB", "qtt_kernel_sinc_dB",
     "qtt_query_full_adjoint", "qtt_full_adjoint",
     "qtt_query_conv_full_backward", "qtt_conv_full_backward",
+    "qtt_batch_create", "qtt_batch_destroy", "qtt_batch_run", "qtt_batch_info",
+    "qtt_batch_status_offset",
     "qtt_probe_start", "qtt_probe_stop",
 ]
 
@@ -36,6 +39,7 @@ EXPORTS = [
 K_CLASSES = {
     "level_gram": 1, "reduce": 2, "level_eig": 3, "project": 4, "eig_step": 5, "tail": 6,
     "conv": 7, "full_chain": 8, "full_final": 9, "other": 10, "adjoint": 11,
+    "batch": 12,
 }
 
 
@@ -112,6 +116,20 @@ def _declare(L):
                                                _SZP]
     L.qtt_conv_full_backward.restype = ctypes.c_int
     L.qtt_conv_full_backward.argtypes = [_TP, _TP, _TP, _VP, _TP, _VP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_batch_create.restype = ctypes.c_int
+    L.qtt_batch_create.argtypes = [ctypes.c_int, _I32P, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                                   ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p),
+                                   _SZP]
+    L.qtt_batch_destroy.restype = ctypes.c_int
+    L.qtt_batch_destroy.argtypes = [_VP]
+    L.qtt_batch_run.restype = ctypes.c_int
+    L.qtt_batch_run.argtypes = [_VP, _VP, _VP, _VP, ctypes.c_size_t, ctypes.c_int, _VP]
+    _I64P = ctypes.POINTER(ctypes.c_int64)
+    L.qtt_batch_info.restype = ctypes.c_int
+    L.qtt_batch_info.argtypes = [_VP, ctypes.c_int, ctypes.c_int, _I64P, _I64P, _I32P, _I64P]
+    L.qtt_batch_status_offset.restype = ctypes.c_int
+    L.qtt_batch_status_offset.argtypes = [_VP, _I64P, _I32P]
     L.qtt_probe_start.restype = ctypes.c_int
     L.qtt_probe_start.argtypes = [ctypes.c_int, ctypes.c_int]
     L.qtt_probe_stop.restype = ctypes.c_int

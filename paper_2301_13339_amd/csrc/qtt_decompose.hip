@@ -84,25 +84,25 @@ __global__ void k_single(const T* x, double B, int nk, T* cores, int32_t* ranks,
 }
 
 // ------------------------------------------------------------ level Gram
-// Partial Gram of the samples viewed as rows x 64 (row-major), 256 threads,
-// thread (ty, tx) owns the 4 x 4 tile rows 4ty.., cols 4tx.. .
+// Gram of the samples viewed as rows x 64 (row-major), 256 threads: thread
+// (ty, tx) accumulates the 4 x 4 tile rows 4ty.., cols 4tx.. over the 32-row
+// stages bid, bid + nblk, ... (st: 32 x 64 doubles of LDS).  Also the sum of
+// the samples (generator normalisation) and a finiteness flag.
 template <typename T, int GEN>
-__global__ void __launch_bounds__(256) k_level_gram(const T* x, double B, int nk, long long rows,
-                                                    double* partials, int pstride,
-                                                    double* gsum_part, int32_t* iflags) {
+__device__ __forceinline__ void level_gram_acc(const T* x, double B, int nk, long long rows,
+                                               long long bid, long long nblk, double* st,
+                                               double (&acc)[4][4], double& gsum, int& fin) {
   constexpr int W = 64, SR = 32;
-  __shared__ double st[SR * W];
   const int tid = threadIdx.x;
   const int ty = tid >> 4, tx = tid & 15;
-  double acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  double gsum = 0.0;
-  int fin = 1;
+  gsum = 0.0;
+  fin = 1;
   const long long nstage = (rows + SR - 1) / SR;
-  for (long long sidx = blockIdx.x; sidx < nstage; sidx += gridDim.x) {
+  for (long long sidx = bid; sidx < nstage; sidx += nblk) {
     const long long r0 = sidx * SR;
     const long long base = r0 * W;
     for (int e = tid; e < SR * W; e += 256) {
@@ -126,20 +126,43 @@ __global__ void __launch_bounds__(256) k_level_gram(const T* x, double B, int nk
     }
     __syncthreads();
   }
-  double* P = partials + (size_t)blockIdx.x * pstride;
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) P[(4 * ty + a) * W + 4 * tx + b] = acc[a][b];
-  // block sum of the samples (generator normalisation), fixed order
-  __shared__ double red[256];
-  red[tid] = gsum;
+}
+
+// fixed-order workgroup sum (red: 256 doubles of LDS); every thread gets it
+__device__ __forceinline__ double wg_sum256(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
   __syncthreads();
   for (int s = 128; s > 0; s >>= 1) {
     if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (tid == 0) gsum_part[blockIdx.x] = red[0];
+  const double t = red[0];
+  __syncthreads();
+  return t;
+}
+
+// Partial Grams over the stages of this block (one partial per block).
+template <typename T, int GEN>
+__global__ void __launch_bounds__(256) k_level_gram(const T* x, double B, int nk, long long rows,
+                                                    double* partials, int pstride,
+                                                    double* gsum_part, int32_t* iflags) {
+  constexpr int W = 64, SR = 32;
+  __shared__ double st[SR * W];
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[4][4];
+  double gsum;
+  int fin;
+  level_gram_acc<T, GEN>(x, B, nk, rows, blockIdx.x, gridDim.x, st, acc, gsum, fin);
+  double* P = partials + (size_t)blockIdx.x * pstride;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) P[(4 * ty + a) * W + 4 * tx + b] = acc[a][b];
+  const double tot = wg_sum256(gsum, red);
+  if (tid == 0) gsum_part[blockIdx.x] = tot;
   if (!fin) atomicOr(iflags, 1);
 }
 
@@ -296,14 +319,13 @@ __device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* 
 }
 
 // ------------------------------------------------------------- level eig
-// Steps 1..L from the Gram GZ (64 x 64) of the samples viewed as (N/64) x 64.
-// Writes cores 1..L, ranks 1..L, tau^2 (scal[1]) and Phi_L (64 x r_L) to umat.
+// Steps 1..L from the Gram GZ (64 x 64, at the start of smem) of the samples
+// viewed as (N/64) x 64.  Writes cores 1..L, ranks 0..L, tau^2 (scal[1]) and
+// Phi_L (64 x r_L) to umat.
 template <typename T>
-__global__ void __launch_bounds__(kEigThreads) k_level_eig(const double* gram, int L, int D, double eps,
-                                                    const Meta meta, T* cores, double* scal,
-                                                    double* umat, StepOut so) {
+__device__ void level_steps(double* smem, int L, int D, double eps, const Meta& meta, T* cores,
+                            double* scal, double* umat, const StepOut& so) {
   constexpr int NT = kEigThreads, W = 64, LDA = 65;
-  extern __shared__ double smem[];
   double* GZ = smem;                 // 64*64
   double* A = GZ + W * W;            // 65*65
   double* V = A + LDA * LDA;         // 65*65
@@ -314,7 +336,6 @@ __global__ void __launch_bounds__(kEigThreads) k_level_eig(const double* gram, i
   int* perm = (int*)(sx + kEigScratch);  // 72
   int* iscr = perm + 72;
   const int tid = threadIdx.x;
-  for (int e = tid; e < W * W; e += NT) GZ[e] = gram[e];
   if (tid == 0) {
     Phi[0] = 1.0;
     so.ranks[0] = 1;
@@ -388,37 +409,44 @@ __global__ void __launch_bounds__(kEigThreads) k_level_eig(const double* gram, i
   }
 }
 
-// --------------------------------------------------------- project + Gram
-// Y = A U for A (rowsA x WA, row-major) and U (WA x r); Y is written to X
-// (row-major, r columns) and is the next remainder; X_next rows pair two Y
-// rows.  Partial Gram (2r x 2r, square stride mstride) per block when
-// do_gram.  WA is either fixed (wa_fixed > 0) or 2*ranks[kin-1].
-template <typename T, int GEN, int TS>
-__global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, int nk,
-                                                      long long rowsA, int wa_fixed,
-                                                      const int32_t* ranks, int kin,
-                                                      const double* U, T* Xout, int do_gram,
-                                                      double* partials, int pstride,
-                                                      int mstride) {
-  constexpr int SR = 32;
+template <typename T>
+__global__ void __launch_bounds__(kEigThreads) k_level_eig(const double* gram, int L, int D,
+                                                           double eps, const Meta meta,
+                                                           T* cores, double* scal, double* umat,
+                                                           StepOut so) {
   extern __shared__ double smem[];
+  for (int e = threadIdx.x; e < 64 * 64; e += kEigThreads) smem[e] = gram[e];
+  __syncthreads();
+  level_steps<T>(smem, L, D, eps, meta, cores, scal, umat, so);
+}
+
+
+// --------------------------------------------------------- project + Gram
+// Y = A U for A (rowsA x WA, row-major) and U (WA x r); Y is written to Xout
+// (row-major, r columns) and is the next remainder, whose rows pair two Y
+// rows.  With do_gram, thread (ty, tx) accumulates the TS x TS tile of the
+// Gram of the next remainder (2r x 2r) over the 32-row stages bid, bid +
+// nblk, ...  smem: WA*r + 32*WA + 32*r doubles.
+template <typename T, int GEN, int TS>
+__device__ __forceinline__ void project_gram_acc(const T* Ain, double B, int nk, long long rowsA,
+                                                 int WA, int r, const double* U, T* Xout,
+                                                 int do_gram, long long bid, long long nblk,
+                                                 double* smem, double (&acc)[TS][TS]) {
+  constexpr int SR = 32;
   const int tid = threadIdx.x;
-  const int WA = wa_fixed > 0 ? wa_fixed : 2 * ranks[kin - 1];
-  const int r = ranks[kin];
   const int M = 2 * r;
   double* Us = smem;              // WA*r
   double* As = Us + WA * r;       // SR*WA
   double* Ys = As + SR * WA;      // SR*r
   for (int e = tid; e < WA * r; e += 256) Us[e] = U[e];
   const int ty = tid >> 4, tx = tid & 15;
-  double acc[TS][TS];
 #pragma unroll
   for (int a = 0; a < TS; ++a)
 #pragma unroll
     for (int b = 0; b < TS; ++b) acc[a][b] = 0.0;
   __syncthreads();
   const long long nstage = (rowsA + SR - 1) / SR;
-  for (long long sidx = blockIdx.x; sidx < nstage; sidx += gridDim.x) {
+  for (long long sidx = bid; sidx < nstage; sidx += nblk) {
     const long long r0 = sidx * SR;
     const int nr = (int)((rowsA - r0) < SR ? (rowsA - r0) : SR);
     for (int e = tid; e < nr * WA; e += 256) As[e] = sample<T, GEN>(Ain, r0 * WA + e, B, nk);
@@ -454,7 +482,25 @@ __global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, in
     }
     __syncthreads();
   }
+}
+
+// WA is either fixed (wa_fixed > 0) or 2*ranks[kin-1]; one partial Gram
+// (square stride mstride) per block.
+template <typename T, int GEN, int TS>
+__global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, int nk,
+                                                      long long rowsA, int wa_fixed,
+                                                      const int32_t* ranks, int kin,
+                                                      const double* U, T* Xout, int do_gram,
+                                                      double* partials, int pstride,
+                                                      int mstride) {
+  extern __shared__ double smem[];
+  const int WA = wa_fixed > 0 ? wa_fixed : 2 * ranks[kin - 1];
+  const int r = ranks[kin];
+  double acc[TS][TS];
+  project_gram_acc<T, GEN, TS>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, blockIdx.x, gridDim.x,
+                               smem, acc);
   if (do_gram) {
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
     double* P = partials + (size_t)blockIdx.x * pstride;
 #pragma unroll
     for (int a = 0; a < TS; ++a)
@@ -467,41 +513,15 @@ __global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, in
 }
 
 // --------------------------------------------------------------- eig step
-// Step k from the reduced Gram (M x M, stride mstride), M = 2 r_{k-1}.
-// Writes core k, ranks[k] and U_k (M x r_k, row-major) to umat.
+// Step k from the Gram already in A (M x M, stride lda), M = 2 r_{k-1}: the
+// truncated eigendecomposition, core k, and U_k (M x r_k, row-major) in umat.
 template <typename T>
-__global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, int mstride, int k,
-                                                   const double* scal, int cap_k, T* cores,
-                                                   long long off_k, double* umat,
-                                                   double* gA, double* gV, StepOut so) {
+__device__ int eig_step_solve(double* A, double* V, int lda, double* lam, double* sx, int* perm,
+                              int* iscr, int M, int k, double tau2, int cap_k, T* cores,
+                              long long off_k, double* umat, const StepOut& so) {
   constexpr int NT = kEigThreads;
-  extern __shared__ double smem[];
   const int tid = threadIdx.x;
-  const int rp = so.ranks[k - 1];
-  const int M = 2 * rp;
-  double *A, *V;
-  int lda;
-  double* lam;
-  if (M <= kEigLds) {
-    lda = kEigLds + 1;
-    A = smem;
-    V = A + lda * lda;
-    lam = V + lda * lda;
-  } else {
-    lda = kMaxM + 1;
-    A = gA;
-    V = gV;
-    lam = smem;
-  }
-  double* sx = lam + kMaxM + 8;
-  int* perm = (int*)(sx + kEigScratch);
-  int* iscr = perm + kMaxM + 8;
-  for (int e = tid; e < M * M; e += NT) {
-    const int i = e / M, j = e - i * M;
-    A[i * lda + j] = gram[i * mstride + j];
-  }
-  __syncthreads();
-  const double tau2 = scal[1];
+  const int rp = M / 2;
   const int r =
       solve_and_truncate<NT, true>(A, V, M, lda, sx, iscr, lam, perm, tau2, cap_k, k, so);
   for (int e = tid; e < M * r; e += NT) {
@@ -514,6 +534,50 @@ __global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, in
     const int i = ai & 1, a = ai >> 1;
     cores[off_k + e] = (T)V[(a + rp * i) * lda + perm[b]];
   }
+  return r;
+}
+
+// LDS layout of an eig step: A and V in LDS for M <= kEigLds, else in gA/gV
+struct EigLayout {
+  double *A, *V, *lam, *sx;
+  int *perm, *iscr;
+  int lda;
+};
+
+__device__ __forceinline__ EigLayout eig_layout(double* smem, int M, double* gA, double* gV) {
+  EigLayout L;
+  if (M <= kEigLds) {
+    L.lda = kEigLds + 1;
+    L.A = smem;
+    L.V = L.A + L.lda * L.lda;
+    L.lam = L.V + L.lda * L.lda;
+  } else {
+    L.lda = kMaxM + 1;
+    L.A = gA;
+    L.V = gV;
+    L.lam = smem;
+  }
+  L.sx = L.lam + kMaxM + 8;
+  L.perm = (int*)(L.sx + kEigScratch);
+  L.iscr = L.perm + kMaxM + 8;
+  return L;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, int mstride, int k,
+                                                   const double* scal, int cap_k, T* cores,
+                                                   long long off_k, double* umat,
+                                                   double* gA, double* gV, StepOut so) {
+  extern __shared__ double smem[];
+  const int M = 2 * so.ranks[k - 1];
+  const EigLayout L = eig_layout(smem, M, gA, gV);
+  for (int e = threadIdx.x; e < M * M; e += kEigThreads) {
+    const int i = e / M, j = e - i * M;
+    L.A[i * L.lda + j] = gram[i * mstride + j];
+  }
+  __syncthreads();
+  eig_step_solve<T>(L.A, L.V, L.lda, L.lam, L.sx, L.perm, L.iscr, M, k, scal[1], cap_k, cores,
+                    off_k, umat, so);
 }
 
 // -------------------------------------------------------------------- tail
@@ -522,12 +586,10 @@ __global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, in
 // and tau^2 are computed here; otherwise scal[1] holds tau^2.  gen_scale:
 // divide the last core by scal[2] (generator normalisation).
 template <typename T, int GEN>
-__global__ void __launch_bounds__(kEigThreads) k_tail(const T* Xin, double B, int nk, int k0, int D,
-                                               double eps, const Meta meta, T* cores,
-                                               double* scal, int gen_scale, StepOut so,
-                                               int32_t* iflags) {
+__device__ void tail_steps(double* smem, const T* Xin, double B, int nk, int k0, int D,
+                           double eps, const Meta& meta, T* cores, double* scal, int gen_scale,
+                           const StepOut& so, int32_t* iflags) {
   constexpr int NT = kEigThreads, LDA = kEigLds + 1;
-  extern __shared__ double smem[];
   double* X = smem;                   // kTailElems
   double* A = X + kTailElems;         // LDA*LDA  (also Y after the eigen solve)
   double* V = A + LDA * LDA;          // LDA*LDA
@@ -664,6 +726,15 @@ __global__ void __launch_bounds__(kEigThreads) k_tail(const T* Xin, double B, in
   if (tid == 0) so.ranks[D] = 1;
 }
 
+template <typename T, int GEN>
+__global__ void __launch_bounds__(kEigThreads) k_tail(const T* Xin, double B, int nk, int k0,
+                                                      int D, double eps, const Meta meta,
+                                                      T* cores, double* scal, int gen_scale,
+                                                      StepOut so, int32_t* iflags) {
+  extern __shared__ double smem[];
+  tail_steps<T, GEN>(smem, Xin, B, nk, k0, D, eps, meta, cores, scal, gen_scale, so, iflags);
+}
+
 // ----------------------------------------------------------- final scaling
 // Scale the last core by 1/scal[2] (used when the tail did not run the
 // generator itself).
@@ -677,6 +748,184 @@ __global__ void k_scale_last(T* cores, long long off, const int32_t* ranks, int 
 
 __global__ void k_flag_status(const int32_t* iflags, int32_t* status) {
   if (threadIdx.x == 0 && status && iflags[0]) atomicOr(status, QTT_STATUS_NONFINITE);
+}
+
+// ================================================================ batched
+// Many independent decompositions (lines) in one launch.  Persistent
+// workgroups take the tasks (sorted by decreasing size on the host) from an
+// atomic counter and run the whole sweep of a task in one workgroup, with
+// the same steps as the single-signal schedule: level Gram in LDS, steps
+// 1..6, projections + Grams of the remainders, eig steps, the tail.  Each
+// workgroup owns a slice of global scratch (scal, U, A/V for orders > 64 and
+// two remainder buffers of nmax elements).
+__device__ __forceinline__ void wg_sync_global() {
+  __threadfence();
+  __syncthreads();
+}
+
+template <typename T, int GEN, int TS>
+__device__ __noinline__ void batch_project(const T* Ain, double B, int nk, long long rowsA, int WA, int r,
+                              const double* U, T* Xout, int do_gram, double* smem, int M,
+                              const EigLayout& Ly) {
+  double acc[TS][TS];
+  project_gram_acc<T, GEN, TS>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, 0, 1, smem, acc);
+  if (do_gram) {
+    // the projection's LDS is free after its last barrier; A may overlap it
+    const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+#pragma unroll
+    for (int a = 0; a < TS; ++a)
+#pragma unroll
+      for (int c = 0; c < TS; ++c) {
+        const int i = ty * TS + a, j = tx * TS + c;
+        if (i < M && j < M) Ly.A[i * Ly.lda + j] = acc[a][c];
+      }
+  }
+  wg_sync_global();
+}
+
+template <typename T, int GEN>
+__device__ void batch_project_any(int Mcap, const T* Ain, double B, int nk, long long rowsA,
+                                  int WA, int r, const double* U, T* Xout, int do_gram,
+                                  double* smem, int M, const EigLayout& Ly) {
+  if (Mcap <= 16)
+    batch_project<T, GEN, 1>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+  else if (Mcap <= 32)
+    batch_project<T, GEN, 2>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+  else if (Mcap <= 64)
+    batch_project<T, GEN, 4>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+  else
+    batch_project<T, GEN, 8>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+}
+
+template <typename T, int GEN>
+__device__ __noinline__ void batch_line(const BatchTask& tk, const T* x, T* cores, int32_t* ranks,
+                           int32_t* status, double* smem, Meta& meta, double* wscr, T* xb0,
+                           T* xb1) {
+  const int tid = threadIdx.x;
+  const int D = tk.D;
+  double* scal = wscr;
+  double* umat = scal + 16;
+  double* gA = umat + kMaxM * kMaxRank;
+  double* gV = gA + (kMaxM + 1) * (kMaxM + 1);
+  // capacities and (absolute) core offsets of this task
+  if (tid == 0) {
+    long long off = tk.core_off;
+    for (int k = 0; k <= D; ++k) {
+      int c = tk.rcap;
+      if (k < 30 && (1 << k) < c) c = 1 << k;
+      if (D - k < 30 && (1 << (D - k)) < c) c = 1 << (D - k);
+      meta.caps[k] = (k == 0 || k == D) ? 1 : c;
+    }
+    for (int k = 0; k < D; ++k) {
+      meta.offs[k] = off;
+      const int c1 = (k + 1 == D) ? 1 : meta.caps[k + 1];
+      off += (long long)meta.caps[k] * 2 * c1;
+    }
+    meta.offs[D] = off;
+  }
+  __syncthreads();
+  StepOut so;
+  so.ranks = ranks + tk.rank_off;
+  so.status = status + tk.status_idx;
+  so.sv = nullptr;
+  so.lib_capped = tk.rcap >= kMaxRank ? 1 : 0;
+  so.dbg = nullptr;
+  int32_t* flag = status + tk.status_idx;  // non-finite input sets bit 1 here directly
+  const T* xl = GEN ? x : x + tk.x_off;
+  const long long N = 1LL << D;
+  if (D == 1) {
+    if (tid == 0) {
+      const double v0 = sample<T, GEN>(xl, 0, tk.B, tk.nk), v1 = sample<T, GEN>(xl, 1, tk.B, tk.nk);
+      double sm = (GEN == 1) ? v0 + v1 : 1.0;
+      if (sm == 0.0) sm = 1.0;
+      cores[meta.offs[0]] = (T)(v0 / sm);
+      cores[meta.offs[0] + 1] = (T)(v1 / sm);
+      so.ranks[0] = 1;
+      so.ranks[1] = 1;
+      if (!(finite_d(v0) && finite_d(v1))) atomicOr(flag, QTT_STATUS_NONFINITE);
+    }
+    return;
+  }
+  if (N <= kTailElems) {
+    tail_steps<T, GEN>(smem, xl, tk.B, tk.nk, 1, D, tk.eps, meta, cores, scal, GEN == 1, so, flag);
+    return;
+  }
+  // level Gram of the samples viewed as (N/64) x 64, straight into LDS
+  const int L = kLevel;
+  {
+    double acc[4][4];
+    double gsum;
+    int fin;
+    level_gram_acc<T, GEN>(xl, tk.B, tk.nk, N >> L, 0, 1, smem, acc, gsum, fin);
+    const double tot = wg_sum256(gsum, smem + 64 * 64);
+    const int ty = tid >> 4, tx = tid & 15;
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) smem[(4 * ty + a) * 64 + 4 * tx + b] = acc[a][b];
+    if (!fin) atomicOr(flag, QTT_STATUS_NONFINITE);
+    if (tid == 0) scal[2] = tot;
+    __syncthreads();
+  }
+  level_steps<T>(smem, L, D, tk.eps, meta, cores, scal, umat, so);
+  wg_sync_global();
+  int tail_k = L + 1;
+  while (tail_k < D && !((1LL << (D - tail_k)) * 2LL * meta.caps[tail_k - 1] <= kTailElems))
+    ++tail_k;
+  int k = L + 1;
+  T* xb[2] = {xb0, xb1};
+  int cur = 0;
+  {
+    const int r = so.ranks[L];
+    const int M = 2 * r;
+    const EigLayout Ly = eig_layout(smem, M, gA, gV);
+    batch_project_any<T, GEN>(2 * meta.caps[L], xl, tk.B, tk.nk, N >> L, 1 << L, r, umat, xb[cur],
+                              k < tail_k ? 1 : 0, smem, M, Ly);
+  }
+  while (k < tail_k) {
+    const int rp = so.ranks[k - 1];
+    const int M = 2 * rp;
+    const EigLayout Ly = eig_layout(smem, M, gA, gV);
+    const int r = eig_step_solve<T>(Ly.A, Ly.V, Ly.lda, Ly.lam, Ly.sx, Ly.perm, Ly.iscr, M, k,
+                                    scal[1], meta.caps[k], cores, meta.offs[k - 1], umat, so);
+    wg_sync_global();
+    const int M2 = 2 * r;
+    const EigLayout Ly2 = eig_layout(smem, M2, gA, gV);
+    batch_project_any<T, 0>(2 * meta.caps[k], xb[cur], tk.B, tk.nk, 1LL << (D - k), M, r, umat,
+                            xb[cur ^ 1], (k + 1 < tail_k) ? 1 : 0, smem, M2, Ly2);
+    cur ^= 1;
+    ++k;
+  }
+  tail_steps<T, 0>(smem, xb[cur], tk.B, tk.nk, k, D, tk.eps, meta, cores, scal, 0, so, flag);
+  if (GEN == 1) {
+    wg_sync_global();
+    const int rp = so.ranks[D - 1];
+    const double sc = scal[2] != 0.0 ? 1.0 / scal[2] : 1.0;
+    T* last = cores + meta.offs[D - 1];
+    for (int e = tid; e < 2 * rp; e += kEigThreads) last[e] = (T)((double)last[e] * sc);
+  }
+}
+
+template <typename T, int GEN>
+__global__ void __launch_bounds__(kEigThreads) k_batch_decompose(
+    const T* x, const BatchTask* tasks, int ntasks, int32_t* counter, T* cores, int32_t* ranks,
+    int32_t* status, char* wscr, long long wstride, long long nmax) {
+  extern __shared__ double smem[];
+  __shared__ int s_task;
+  __shared__ Meta s_meta;
+  double* my = reinterpret_cast<double*>(wscr + (long long)blockIdx.x * wstride);
+  T* xb0 = reinterpret_cast<T*>(my + batch_wg_doubles());
+  T* xb1 = xb0 + nmax;
+  for (;;) {
+    if (threadIdx.x == 0) s_task = atomicAdd(counter, 1);
+    __syncthreads();
+    const int t = s_task;
+    __syncthreads();
+    if (t >= ntasks) break;  // every wave leaves on the same value
+    const BatchTask tk = tasks[t];
+    batch_line<T, GEN>(tk, x, cores, ranks, status, smem, s_meta, my, xb0, xb1);
+    wg_sync_global();
+  }
 }
 
 // =================================================================== host
@@ -957,6 +1206,59 @@ int run_decompose(const DecompPlan& P, const Source& src, double eps, const Tens
   if (src.gen == 2) return run_decompose_t<float, 2>(P, src, eps, out, sv, stream);
   return src.gen ? run_decompose_t<float, 1>(P, src, eps, out, sv, stream)
                  : run_decompose_t<float, 0>(P, src, eps, out, sv, stream);
+}
+
+}  // namespace qtt
+
+// ------------------------------------------------------------ batched host
+namespace qtt {
+
+size_t batch_decompose_lds() {
+  size_t m = lds_level_eig();
+  if (lds_tail() > m) m = lds_tail();
+  if (lds_eig_step() > m) m = lds_eig_step();
+  const size_t pj = lds_project(kMaxM, kMaxRank);
+  if (pj > m) m = pj;
+  return m;
+}
+
+template <typename T, int GEN>
+static int batch_decompose_t(const T* x, const BatchTask* tasks, int ntasks, int32_t* counter,
+                             T* cores, int32_t* ranks, int32_t* status, char* wscr,
+                             long long wstride, long long nmax, int nwg, hipStream_t s) {
+  static bool attrs = false;
+  if (!attrs) {
+    QTT_HIP_CHECK(hipFuncSetAttribute((const void*)k_batch_decompose<T, GEN>,
+                                      hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)batch_decompose_lds()));
+    attrs = true;
+  }
+  ProbeScope _ps(QTT_K_BATCH, s);
+  k_batch_decompose<T, GEN><<<nwg, kEigThreads, batch_decompose_lds(), s>>>(
+      x, tasks, ntasks, counter, cores, ranks, status, wscr, wstride, nmax);
+  QTT_LAUNCH_CHECK();
+  return QTT_OK;
+}
+
+int run_batch_decompose(int dtype, int gen, const void* x, const BatchTask* tasks, int ntasks,
+                        int32_t* counter, void* cores, int32_t* ranks, int32_t* status,
+                        char* wscr, long long wstride, long long nmax, int nwg, hipStream_t s) {
+  if (dtype == QTT_F64) {
+    if (gen)
+      return batch_decompose_t<double, 1>(static_cast<const double*>(x), tasks, ntasks, counter,
+                                          static_cast<double*>(cores), ranks, status, wscr,
+                                          wstride, nmax, nwg, s);
+    return batch_decompose_t<double, 0>(static_cast<const double*>(x), tasks, ntasks, counter,
+                                        static_cast<double*>(cores), ranks, status, wscr, wstride,
+                                        nmax, nwg, s);
+  }
+  if (gen)
+    return batch_decompose_t<float, 1>(static_cast<const float*>(x), tasks, ntasks, counter,
+                                       static_cast<float*>(cores), ranks, status, wscr, wstride,
+                                       nmax, nwg, s);
+  return batch_decompose_t<float, 0>(static_cast<const float*>(x), tasks, ntasks, counter,
+                                     static_cast<float*>(cores), ranks, status, wscr, wstride,
+                                     nmax, nwg, s);
 }
 
 }  // namespace qtt

@@ -141,6 +141,31 @@ int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p);
 int run_decompose(const DecompPlan& p, const Source& src, double eps, const TensorDev& out,
                   double* sv, hipStream_t stream);
 
+// ----------------------------------------------------------------- batched
+// One independent decomposition of a batch (see k_batch_decompose).
+struct BatchTask {
+  long long x_off;     // offset of the samples (stored samples only)
+  long long core_off;  // element offset of the task's cores (capacity strided)
+  int rank_off;        // offset of its D+1 ranks
+  int status_idx;      // its status word
+  int D;               // binary modes
+  int rcap;            // rank capacity, 1..kMaxRank
+  int nk;              // generator: log2 of the kernel grid
+  int pad;
+  double B;            // generator bandwidth
+  double eps;          // tolerance
+};
+
+// doubles of per-workgroup scratch ahead of the two remainder buffers
+constexpr long long batch_wg_doubles() {
+  return 16 + (long long)kMaxM * kMaxRank + 2LL * (kMaxM + 1) * (kMaxM + 1);
+}
+
+int run_batch_decompose(int dtype, int gen, const void* x, const BatchTask* tasks, int ntasks,
+                        int32_t* counter, void* cores, int32_t* ranks, int32_t* status,
+                        char* wscr, long long wstride, long long nmax, int nwg, hipStream_t s);
+size_t batch_decompose_lds();
+
 // --------------------------------------------------------------- other ops
 int plan_full(int d, const int32_t* cap, int dtype, void* ws, size_t* ws_bytes, void** bufs);
 int run_full(const TensorDev& t, int dtype, void* out, void* ws, hipStream_t stream);
