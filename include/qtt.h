@@ -286,7 +286,7 @@ int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_t
  * in one hipGraph (replayed by later calls with the same pointers).
  * Per line the result equals the single-signal pipeline with the same
  * parameters: signal TT-SVD at eps with rank cap max_rank, kernel QTT at
- * eps_w (rank cap w_max_rank, 0 = 24), y = T(w) full(F) exactly, rounding =
+ * eps_w (rank cap w_max_rank, 0 = 16), y = T(w) full(F) exactly, rounding =
  * TT-SVD of y at eps (cap round_max_rank, 0 = QTT_MAX_RANK), out = full.
  */
 #define QTT_BATCH_MAXD 18       /* largest d of a line in a batch               */

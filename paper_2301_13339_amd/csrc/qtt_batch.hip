@@ -177,8 +177,8 @@ __global__ void __launch_bounds__(256) k_batch_full(const T* cores, const int32_
 }
 
 // ==================================================== batched Toeplitz
-// One launch per chunk q of CB bits (bits q*CB .. q*CB+cb-1, 0-based).  A
-// workgroup takes one line and one value of the other bits; the state of
+// One launch per chunk q of at most CB bits (chunk_of).  A workgroup takes
+// one line and one value of the other bits; the state of
 // the 2^cb positions for every bond (2 rho x 2^cb doubles) lives in LDS
 // (double-buffered) across the cb steps, with the step rule of the
 // single-signal Toeplitz product (binary adder with carry).  Between chunks
@@ -187,31 +187,46 @@ __global__ void __launch_bounds__(256) k_batch_full(const T* cores, const int32_
 // them, and workgroups own disjoint positions).
 constexpr int kToepMaxBond = 48;  // 2 x the generator rank cap of the batch
 constexpr int kToepMaxCB = 7;
+constexpr int kToepPerWG = 32;    // values of the other bits per workgroup
+
+// The d bits of a line split into nq = ceil(d / CB) chunks of nearly equal
+// width (never narrower than d / nq), chunk q starting at bit b0.
+__host__ __device__ inline bool chunk_of(int d, int CB, int q, int* b0, int* cb) {
+  const int nq = (d + CB - 1) / CB;
+  if (q >= nq) return false;
+  const int base = d / nq, rem = d % nq;
+  *cb = base + (q < rem ? 1 : 0);
+  *b0 = q * base + (q < rem ? q : rem);
+  return true;
+}
 
 template <typename T>
-__global__ void __launch_bounds__(256) k_batch_toep(const T* wcores, const int32_t* ranks,
-                                                    const BatchLine* lines, const long long* wg0,
-                                                    int nlines, int wcap, int q, int CB,
-                                                    const T* f, T* state, T* y) {
+__global__ void __launch_bounds__(64) k_batch_toep(const T* wcores, const int32_t* ranks,
+                                                   const BatchLine* lines, const long long* wg0,
+                                                   int nlines, int wcap, int q, int CB,
+                                                   int pmax, const T* f, T* state, T* y) {
   extern __shared__ double sm[];
-  const int tid = threadIdx.x;
+  const int lane = threadIdx.x;
   const int l = find_line(wg0, nlines, blockIdx.x);
   const BatchLine ln = lines[l];
   const int d = ln.d;
-  const int b0 = q * CB;
-  if (b0 >= d) return;  // uniform: this line has no chunk q (not launched)
-  const int cb = (d - b0) < CB ? (d - b0) : CB;
+  int b0, cb;
+  if (!chunk_of(d, CB, q, &b0, &cb)) return;  // uniform: the line has no chunk q
   const int P = 1 << cb;
   const long long N = 1LL << d;
-  const long long o = (long long)blockIdx.x - wg0[l];  // value of the other d - cb bits
-  const long long lo = o & ((1LL << b0) - 1), hi = o >> b0;
   const int32_t* wr = ranks + ln.w_rank;
   const T* W = wcores + ln.w_core;
   double* S0 = sm;
-  double* S1 = sm + kToepMaxBond * (1 << kToepMaxCB);
+  double* S1 = sm + 2 * wcap * pmax;
+  // this workgroup takes kToepPerWG consecutive values of the other d - cb bits
+  const long long nout = 1LL << (d - cb);
+  const long long o_beg = ((long long)blockIdx.x - wg0[l]) * kToepPerWG;
+  const long long o_end = (o_beg + kToepPerWG) < nout ? (o_beg + kToepPerWG) : nout;
+  for (long long o = o_beg; o < o_end; ++o) {
+  const long long lo = o & ((1LL << b0) - 1), hi = o >> b0;
   // load the state at bond b0 (the input vector when q == 0)
   const int rin0 = (q == 0) ? 1 : wr[b0];
-  for (int e = tid; e < 2 * rin0 * P; e += 256) {
+  for (int e = lane; e < 2 * rin0 * P; e += 64) {
     const int b = e / P, p = e - b * P;
     const long long pos = lo | ((long long)p << b0) | (hi << (b0 + cb));
     double v;
@@ -224,43 +239,70 @@ __global__ void __launch_bounds__(256) k_batch_toep(const T* wcores, const int32
   __syncthreads();
   double* cur = S0;
   double* nxt = S1;
+  // One step: a work item is a pair of positions (p0, p1) that differ in the
+  // step's bit (they share their inputs) and a group of 8 output bonds; per
+  // item 4 rin loads of the state and ~32 rin FMAs.
   for (int j = 0; j < cb; ++j) {
     const int k = b0 + j + 1;  // 1-based bit
     const int rin = (k == 1) ? 1 : wr[k - 1];
     const int rout = wr[k];
     const T* Wk = W + core_off_dev(d + 1, wcap, k - 1);
     const int half = 1 << j;
-    for (int e = tid; e < 2 * rout * P; e += 256) {
-      const int bo = e / P, p = e - bo * P;
-      const int a1 = bo >> 1, c1 = bo & 1;
-      const int ob = (p >> j) & 1;
-      const int p0 = p & ~half, p1 = p | half;
-      double acc = 0.0;
+    const int npair = P >> 1;
+    const int ngroup = (2 * rout + 7) >> 3;
+    for (int it = lane; it < npair * ngroup; it += 64) {
+      const int g = it / npair, pr = it - g * npair;
+      const int p0 = ((pr >> j) << (j + 1)) | (pr & (half - 1));
+      const int p1 = p0 | half;
+      double acc[8][2];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) acc[t][0] = acc[t][1] = 0.0;
       for (int a = 0; a < rin; ++a) {
+        double w[4][2];  // W_k[a, u, a1] for the group's 4 values of a1
+#pragma unroll
+        for (int t2 = 0; t2 < 4; ++t2) {
+          const int a1 = g * 4 + t2;
+          w[t2][0] = a1 < rout ? (double)Wk[(a * 2) * rout + a1] : 0.0;
+          w[t2][1] = a1 < rout ? (double)Wk[(a * 2 + 1) * rout + a1] : 0.0;
+        }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
           const double x0 = cur[(2 * a + c) * P + p0], x1 = cur[(2 * a + c) * P + p1];
 #pragma unroll
-          for (int n = 0; n < 2; ++n) {
-            // forward product: output bit j = ob, input bit i = n
-            const int v = ob + (1 - n) + c;
-            if ((v >> 1) == c1) acc = fma((double)Wk[(a * 2 + (v & 1)) * rout + a1], n ? x1 : x0, acc);
+          for (int t = 0; t < 8; ++t) {
+            const int c1 = t & 1;
+#pragma unroll
+            for (int ob = 0; ob < 2; ++ob) {
+#pragma unroll
+              for (int n = 0; n < 2; ++n) {
+                // forward product: output bit ob, input bit n
+                const int v = ob + (1 - n) + c;
+                if ((v >> 1) == c1) acc[t][ob] = fma(w[t >> 1][v & 1], n ? x1 : x0, acc[t][ob]);
+              }
+            }
           }
         }
       }
-      nxt[bo * P + p] = acc;
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int bo = g * 8 + t;
+        if (bo < 2 * rout) {
+          nxt[bo * P + p0] = acc[t][0];
+          nxt[bo * P + p1] = acc[t][1];
+        }
+      }
     }
     __syncthreads();
-    double* t = cur;
+    double* tmp = cur;
     cur = nxt;
-    nxt = t;
+    nxt = tmp;
   }
   const int kend = b0 + cb;
   if (kend == d) {
     // contract the top carry with W_{d+1}: y = sum_{a,c} S[(a,c)] W_{d+1}[a, c, 0]
     const int rl = wr[d];
     const T* Wl = W + core_off_dev(d + 1, wcap, d);
-    for (int p = tid; p < P; p += 256) {
+    for (int p = lane; p < P; p += 64) {
       double s = 0.0;
       for (int b = 0; b < 2 * rl; ++b) s = fma(cur[b * P + p], (double)Wl[b], s);
       const long long pos = lo | ((long long)p << b0) | (hi << (b0 + cb));
@@ -268,11 +310,13 @@ __global__ void __launch_bounds__(256) k_batch_toep(const T* wcores, const int32
     }
   } else {
     const int rout = wr[kend];
-    for (int e = tid; e < 2 * rout * P; e += 256) {
+    for (int e = lane; e < 2 * rout * P; e += 64) {
       const int b = e / P, p = e - b * P;
       const long long pos = lo | ((long long)p << b0) | (hi << (b0 + cb));
       state[ln.st_off + (long long)b * N + pos] = (T)cur[b * P + p];
     }
+  }
+  __syncthreads();  // the LDS state is reused by the next value of the other bits
   }
 }
 
@@ -298,6 +342,7 @@ struct qtt_batch {
   std::vector<long long> full_wg0;                  // per line, for the Full tiles
   std::vector<std::vector<long long>> toep_wg0;     // per chunk
   std::vector<long long> toep_total;
+  std::vector<int> toep_cbmax;                      // widest chunk of each pass
   long long full_total = 0;
   long long samples = 0, nmax = 0;
   int cb = 6, full_c = 7, full_hb = 6;
@@ -436,15 +481,15 @@ static void batch_grids(qtt_batch* p) {
   const int nq = (maxd + p->cb - 1) / p->cb;
   p->toep_wg0.assign(nq, std::vector<long long>(n));
   p->toep_total.assign(nq, 0);
+  p->toep_cbmax.assign(nq, 0);
   for (int qi = 0; qi < nq; ++qi) {
     long long a = 0;
     for (int l = 0; l < n; ++l) {
       p->toep_wg0[qi][l] = a;
-      const int d = p->d[l];
-      const int b0 = qi * p->cb;
-      if (b0 < d) {
-        const int cbl = std::min(d - b0, p->cb);
-        a += 1LL << (d - cbl);
+      int b0, cbl;
+      if (chunk_of(p->d[l], p->cb, qi, &b0, &cbl)) {
+        a += ((1LL << (p->d[l] - cbl)) + kToepPerWG - 1) / kToepPerWG;
+        p->toep_cbmax[qi] = std::max(p->toep_cbmax[qi], cbl);
       }
     }
     p->toep_total[qi] = a;
@@ -545,17 +590,21 @@ static int batch_stages(qtt_batch* p, const T* x, T* out, char* ws, hipStream_t 
     k_batch_full<T><<<(unsigned)p->full_total, 256, 0, s>>>(fc, fr, lines, fwg, n, 0, p->f_rcap,
                                                              p->full_c, p->full_hb, f);
     QTT_LAUNCH_CHECK();
-    const size_t lds = sizeof(double) * 2 * kToepMaxBond * (1 << kToepMaxCB);
+    const size_t lds_max = sizeof(double) * 2 * kToepMaxBond * (1 << kToepMaxCB);
     static bool attr = false;
     if (!attr) {
       QTT_HIP_CHECK(hipFuncSetAttribute((const void*)k_batch_toep<T>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+                                        hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds_max));
       attr = true;
     }
     for (size_t qi = 0; qi < p->toep_wg0.size(); ++qi) {
+      if (p->toep_total[qi] > 0xFFFFFFFFLL / 64) return QTT_ENOTSUP;  // grid limit
       const long long* twg = reinterpret_cast<const long long*>(ws + p->o_twg) + (size_t)n * qi;
-      k_batch_toep<T><<<(unsigned)p->toep_total[qi], 256, lds, s>>>(
-          wc, wr, lines, twg, n, p->w_rcap, (int)qi, p->cb, f, st, y);
+      const int pmax = 1 << p->toep_cbmax[qi];
+      const size_t lds = sizeof(double) * 2 * (2 * p->w_rcap) * pmax;
+      k_batch_toep<T><<<(unsigned)p->toep_total[qi], 64, lds, s>>>(
+          wc, wr, lines, twg, n, p->w_rcap, (int)qi, p->cb, pmax, f, st, y);
       QTT_LAUNCH_CHECK();
     }
   }
@@ -630,7 +679,7 @@ int qtt_batch_create(int n_lines, const int32_t* d, const double* B, int dtype, 
       max_rank > QTT_MAX_RANK || w_max_rank < 0 || round_max_rank < 0 ||
       round_max_rank > QTT_MAX_RANK)
     return QTT_EINVAL;
-  const int wr = w_max_rank == 0 ? kToepMaxBond / 2 : w_max_rank;
+  const int wr = w_max_rank == 0 ? 16 : w_max_rank;
   if (wr > kToepMaxBond / 2) return QTT_ENOTSUP;
   for (int l = 0; l < n_lines; ++l) {
     if (d[l] < 1 || d[l] > QTT_BATCH_MAXD) return QTT_EINVAL;
