@@ -24,7 +24,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import conv, tt
+from . import conv, rsvd, tt
 
 
 def relative_error(a, ref) -> float:
@@ -39,12 +39,15 @@ def _toeplitz(f, w, fft):
 
 
 def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None = None,
-                round_max_rank: int = 0, fft: bool | None = None):
+                round_max_rank: int = 0, fft: bool | None = None, sketch_ell: int = 0,
+                sketch_seed: int = 0):
     """Run the composed pipeline on a 1-D signal of length ``2**d``.
 
     ``fft`` selects the DFT route for the exact convolution (default: on for
-    ``d > 14``); both routes compute the same sum.  Returns a dict with the
-    cores, the intermediate full arrays, ranks and the output.
+    ``d > 14``); both routes compute the same sum.  ``sketch_ell > 0`` takes
+    the rounding's truncated SVDs from Algorithms 4 and 5 (``ell`` columns,
+    ``sketch_seed``).  Returns a dict with the cores, the intermediate full
+    arrays, ranks and the output.
     """
     x = np.asarray(x, dtype=np.float64).ravel()
     d = tt.log2_exact(x.size)
@@ -58,7 +61,11 @@ def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None 
     W, winfo = tt.tt_svd(w, eps_w, 0, return_info=True)
     w_t = tt.tt_full(W)
     y = _toeplitz(f_t, w_t, fft)
-    Z, zinfo = tt.tt_svd(y, eps, round_max_rank, return_info=True)
+    if sketch_ell > 0:
+        Z, zinfo = rsvd.tt_svd_sketch(y, eps, round_max_rank, sketch_ell, sketch_seed,
+                                      return_info=True)
+    else:
+        Z, zinfo = tt.tt_svd(y, eps, round_max_rank, return_info=True)
     out = tt.tt_full(Z)
     return dict(F=F, W=W, Z=Z, f_tilde=f_t, w=w, w_tilde=w_t, y=y, out=out,
                 F_ranks=finfo["ranks"], W_ranks=winfo["ranks"], Z_ranks=zinfo["ranks"],

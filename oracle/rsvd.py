@@ -1,0 +1,120 @@
+"""Randomized range finder and RSVD (Algorithms 4 and 5 of Appendix A) and the
+TT-SVD sweep that takes every truncated SVD from them, in float64 numpy.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The Gaussian test matrix is bit-defined so that an independent GPU
+implementation draws the same one: entry ``Omega[row, col]`` of sweep step
+``step`` comes from one call of the counter-based generator Philox-4x32-10
+(Salmon, Moraes, Dror and Shaw, "Parallel random numbers: as easy as 1, 2,
+3", SC 2011) with counter ``(row, col, step, 0)`` and key ``(seed mod 2^32,
+seed >> 32)``; its first two output words ``x0, x1`` give the uniforms
+``u = (x + 1/2) 2^-32`` in (0, 1) and the Box-Muller transform
+``sqrt(-2 ln u1) cos(2 pi u2)`` gives one standard normal.
+
+Readings: Algorithm 4 is applied to the unfolding ``A`` (``m x n``) of each
+step with ``ell = k + p`` columns; with ``ell >= m`` the reduced QR of ``Y``
+gives an orthogonal ``m x m`` basis and the step is the exact SVD.  The rank
+of each step is then chosen from the singular values of ``B = Q^T A`` by the
+rule of Algorithm 1 (tolerance and cap), as in the plain sweep.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import tt
+
+_M0 = 0xD2511F53
+_M1 = 0xCD9E8D57
+_W0 = 0x9E3779B9
+_W1 = 0xBB67AE85
+_MASK = 0xFFFFFFFF
+
+
+def philox4x32_10(ctr, key):
+    """Philox-4x32 with 10 rounds on uint64 numpy arrays holding 32-bit words.
+
+    ``ctr`` is a sequence of 4 arrays (or ints), ``key`` of 2; returns the 4
+    output words.  Each round multiplies words 0 and 2 by the two constants,
+    mixes the high halves with the other words and the key, and the key is
+    advanced by the two Weyl constants between rounds.
+    """
+    c = [np.asarray(v, dtype=np.uint64) & _MASK for v in ctr]
+    k0 = np.asarray(key[0], dtype=np.uint64) & _MASK
+    k1 = np.asarray(key[1], dtype=np.uint64) & _MASK
+    for r in range(10):
+        if r > 0:
+            k0 = (k0 + _W0) & _MASK
+            k1 = (k1 + _W1) & _MASK
+        p0 = c[0] * np.uint64(_M0)
+        p1 = c[2] * np.uint64(_M1)
+        hi0, lo0 = p0 >> np.uint64(32), p0 & _MASK
+        hi1, lo1 = p1 >> np.uint64(32), p1 & _MASK
+        c = [hi1 ^ c[1] ^ k0, lo1, hi0 ^ c[3] ^ k1, lo0]
+    return c
+
+
+def gaussian_matrix(nrows: int, ncols: int, step: int, seed: int) -> np.ndarray:
+    """``Omega`` (``nrows x ncols``) of one sweep step, as described above."""
+    row = np.repeat(np.arange(nrows, dtype=np.uint64), ncols)
+    col = np.tile(np.arange(ncols, dtype=np.uint64), nrows)
+    zero = np.zeros_like(row)
+    x = philox4x32_10([row, col, zero + np.uint64(step), zero],
+                      [seed & _MASK, (seed >> 32) & _MASK])
+    u1 = (x[0].astype(np.float64) + 0.5) * 2.0 ** -32
+    u2 = (x[1].astype(np.float64) + 0.5) * 2.0 ** -32
+    z = np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)
+    return z.reshape(nrows, ncols)
+
+
+def range_finder(A, omega) -> np.ndarray:
+    """Algorithm 4: ``Y = A Omega``, ``Q R = Y``; returns ``Q``."""
+    Y = np.asarray(A, dtype=np.float64) @ omega
+    Q, _ = np.linalg.qr(Y, mode="reduced")
+    return Q
+
+
+def rsvd(A, Q):
+    """Algorithm 5: ``B = Q^T A``, ``U~ S V^T = B``, ``U = Q U~``."""
+    B = Q.T @ np.asarray(A, dtype=np.float64)
+    Ut, s, Vt = np.linalg.svd(B, full_matrices=False)
+    return Q @ Ut, s, Vt
+
+
+def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0,
+                  return_info: bool = False):
+    """Algorithm 1 with every truncated SVD taken by Algorithms 4 and 5.
+
+    Same conventions as :func:`oracle.tt.tt_svd`; step ``k`` (1-based) draws
+    ``Omega`` of ``n_k x ell`` entries with ``step = k``.
+    """
+    v = np.asarray(a, dtype=np.float64).ravel()
+    K = tt.log2_exact(v.size)
+    norm = float(np.linalg.norm(v))
+    info = {"norm": norm, "ranks": [1], "sv": []}
+    if K == 1:
+        cores = [v.reshape(1, 2, 1).copy()]
+        info["ranks"].append(1)
+        return (cores, info) if return_info else cores
+    tau = eps * norm / math.sqrt(K - 1)
+    cores = []
+    r_prev = 1
+    rem = v.reshape((1, -1), order="F")
+    for k in range(1, K):
+        A = rem.reshape((2 * r_prev, -1), order="F")
+        omega = gaussian_matrix(A.shape[1], ell, k, seed)
+        Q = range_finder(A, omega)
+        U, s, Vt = rsvd(A, Q)
+        r = tt.truncation_rank(s, tau, max_rank)
+        info["sv"].append(s.copy())
+        U, Vt = tt._gauge(U[:, :r].copy(), Vt[:r, :].copy())
+        cores.append(U.reshape((r_prev, 2, r), order="F"))
+        rem = s[:r, None] * Vt
+        info["ranks"].append(r)
+        r_prev = r
+    cores.append(rem.reshape((r_prev, 2, 1), order="F"))
+    info["ranks"].append(1)
+    return (cores, info) if return_info else cores

@@ -1,0 +1,81 @@
+"""Pins of the randomized forms (Algorithms 4 and 5, Appendix A) and of the
+counter-based generator that defines their Gaussian test matrices."""
+
+import numpy as np
+import pytest
+
+from oracle import rsvd, tt
+
+
+# Known-answer vectors of Philox-4x32-10 published with the generator
+# (Salmon et al. 2011, Random123 test vectors): (counter, key) -> output.
+KAT = [
+    ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+    ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+    ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+     (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+]
+
+
+@pytest.mark.parametrize("ctr,key,want", KAT)
+def test_philox_known_answers(ctr, key, want):
+    got = rsvd.philox4x32_10(list(ctr), list(key))
+    assert [int(v) for v in got] == list(want)
+
+
+def test_gaussian_matrix_moments_and_determinism():
+    om = rsvd.gaussian_matrix(2000, 50, step=3, seed=12345)
+    assert abs(om.mean()) < 0.02 and abs(om.var() - 1.0) < 0.03
+    assert np.array_equal(om, rsvd.gaussian_matrix(2000, 50, step=3, seed=12345))
+    assert not np.array_equal(om, rsvd.gaussian_matrix(2000, 50, step=4, seed=12345))
+    # one entry recomputed from its own counter
+    x = rsvd.philox4x32_10([17, 9, 3, 0], [12345, 0])
+    u1 = (float(x[0]) + 0.5) * 2.0 ** -32
+    u2 = (float(x[1]) + 0.5) * 2.0 ** -32
+    assert om[17, 9] == pytest.approx(np.sqrt(-2 * np.log(u1)) * np.cos(2 * np.pi * u2), rel=1e-15)
+
+
+def test_rsvd_exact_when_sketch_covers_the_rank():
+    """rank(A) <= ell: Q spans range(A) and Algorithm 5 returns the SVD."""
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((40, 6)) @ rng.standard_normal((6, 300))
+    Q = rsvd.range_finder(A, rsvd.gaussian_matrix(300, 10, 1, 7))
+    U, s, Vt = rsvd.rsvd(A, Q)
+    s_ref = np.linalg.svd(A, compute_uv=False)
+    assert np.allclose(s[:6], s_ref[:6], rtol=1e-12)
+    assert np.allclose((U * s) @ Vt, A, atol=1e-10 * np.linalg.norm(A))
+
+
+def test_rsvd_error_bound_a1():
+    """(A.1): ||A - Q Q^T A|| <= (1 + 11 sqrt(k+p) sqrt(min(m,n))) sigma_{k+1}."""
+    rng = np.random.default_rng(1)
+    m, n, k, p = 60, 400, 8, 6
+    Uo, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    Vo, _ = np.linalg.qr(rng.standard_normal((n, m)))
+    sig = np.concatenate([np.geomspace(10.0, 1.0, k), 1e-3 * np.ones(m - k)])
+    A = (Uo * sig) @ Vo.T
+    for seed in range(5):
+        Q = rsvd.range_finder(A, rsvd.gaussian_matrix(n, k + p, 1, seed))
+        err = np.linalg.norm(A - Q @ (Q.T @ A), 2)
+        assert err <= (1 + 11 * np.sqrt(k + p) * np.sqrt(min(m, n))) * sig[k]
+
+
+def test_sketched_ttsvd_equals_ttsvd_when_ell_covers_unfoldings():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal(1 << 10)
+    a, ia = tt.tt_svd(x, 1e-2, 0, return_info=True)
+    b, ib = rsvd.tt_svd_sketch(x, 1e-2, 0, ell=64, seed=3, return_info=True)
+    assert ia["ranks"] == ib["ranks"]
+    assert np.allclose(tt.tt_full(a), tt.tt_full(b), atol=1e-12 * np.linalg.norm(x))
+
+
+def test_sketched_ttsvd_near_optimal_on_smooth_data():
+    """With ell below some unfoldings' row count the sweep is approximate but
+    stays within the tolerance on a fast-decaying spectrum."""
+    n = 1 << 12
+    t = np.arange(n) / n
+    x = np.exp(-((t - 0.3) ** 2) / 0.01) + 0.5 * np.sin(40 * t) * t
+    eps = 1e-6
+    b = rsvd.tt_svd_sketch(x, eps, 0, ell=12, seed=5)
+    err = np.linalg.norm(tt.tt_full(b) - x) / np.linalg.norm(x)
+    assert err <= 2 * eps
