@@ -65,9 +65,11 @@ extern "C" {
 
 /* rounding methods for qtt_round */
 #define QTT_ROUND_EXACT 0       /* TT-SVD of the represented tensor, FP64 sums  */
-#define QTT_ROUND_SKETCH_F32 1  /* randomized range finder, FP32 sketch GEMMs   */
-#define QTT_ROUND_SKETCH_BF16 2 /* randomized range finder, BF16 MFMA sketches  */
+#define QTT_ROUND_SKETCH_F32 1  /* randomized range finder, FP32 sketch GEMM    */
+#define QTT_ROUND_SKETCH_BF16 2 /* randomized range finder, BF16-operand sketch */
 
+#define QTT_SKETCH_ELL 32       /* sketch width of qtt_round's sketch methods   */
+#define QTT_SKETCH_MAX_ELL 64   /* largest sketch width                         */
 #define QTT_MAXD 48             /* largest number of binary modes               */
 #define QTT_MAX_RANK 64         /* largest TT-rank a decomposition can produce  */
 
@@ -187,14 +189,33 @@ int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int me
  *          truncation rule and threshold with ||y||_F) of the represented
  *          tensor; it is computed by reconstructing the tensor into the
  *          workspace (Algorithm 3) and running the qtt_decompose sweep.
- *   method QTT_ROUND_SKETCH_*: randomized rounding (range finder of
- *          Algorithm 4 on every unfolding, one sketch per mode against a
- *          random Gaussian TT drawn from `seed` with Philox-4x32-10) followed
- *          by the exact truncation of the sketched tensor.
+ *   method QTT_ROUND_SKETCH_F32 / _BF16: the same sweep with every
+ *          truncated SVD taken by Algorithms 4 and 5 (qtt_round_sketch with
+ *          ell = QTT_SKETCH_ELL and the given seed).
  *   z      output tensor with capacities from qtt_query_round
  */
 int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_t seed,
               qtt_tensor* z, void* ws, size_t ws_bytes, void* stream);
+
+/* Capacities and workspace of qtt_round_sketch (1 <= ell <= QTT_SKETCH_MAX_ELL). */
+int qtt_query_round_sketch(int d, const int32_t* y_cap, int max_rank, int dtype, int ell,
+                           int32_t* z_cap, size_t* ws_bytes, size_t* core_elems);
+
+/*
+ * Randomised rounding (Algorithms 4 and 5 of Appendix A inside the TT-SVD
+ * sweep of the represented tensor): at every step the unfolding A (m x n)
+ * is sketched as Y = A Omega (m x ell, Omega Gaussian from Philox-4x32-10,
+ * counter (row, col, step, 0), key = seed, Box-Muller of the first two
+ * words), Q = qr(Y) and B = Q^T A give the truncated SVD, whose rank follows
+ * the rule of Algorithm 1 at eps (cap max_rank).  The sketch GEMM runs in
+ * FP32 (bf16 = 0) or with operands rounded to bfloat16 (bf16 = 1), with FP32
+ * accumulation and an FP64 combine of the partial sums; QR, the small
+ * eigenproblem and the Gram of A stay in FP64.  With ell >= m a step is the
+ * exact SVD.  qtt_round's QTT_ROUND_SKETCH_* methods are this call with
+ * ell = QTT_SKETCH_ELL.
+ */
+int qtt_round_sketch(const qtt_tensor* y, double eps, int max_rank, int ell, int bf16,
+                     uint64_t seed, qtt_tensor* z, void* ws, size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------ full */
 /* Workspace for qtt_full of a tensor with capacities cap[0..d]. */
@@ -357,6 +378,7 @@ int qtt_batch_status_offset(const qtt_batch* plan, int64_t* status_off_bytes,
 #define QTT_K_OTHER 10       /* bookkeeping kernels                            */
 #define QTT_K_ADJOINT 11     /* Toeplitz products on full vectors, adjoint of Full */
 #define QTT_K_BATCH 12       /* batched (many-line) kernels                     */
+#define QTT_K_SKETCH 13      /* randomised rounding (sketch passes and steps)   */
 
 int qtt_probe_start(int cls, int max_launches);
 int qtt_probe_stop(double* total_ms, int* launches);

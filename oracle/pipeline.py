@@ -73,8 +73,10 @@ def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None 
 
 
 def pipeline_2d(img, Bx: float, By: float, eps: float, max_rank: int = 0,
-                eps_w: float | None = None, round_max_rank: int = 0, fft: bool = True):
-    """Run the composed pipeline on a row-major ``2**dy x 2**dx`` image."""
+                eps_w: float | None = None, round_max_rank: int = 0, fft: bool = True,
+                sketch_ell: int = 0, sketch_seed: int = 0):
+    """Run the composed pipeline on a row-major ``2**dy x 2**dx`` image
+    (``sketch_ell`` as in :func:`pipeline_1d`)."""
     img = np.asarray(img, dtype=np.float64)
     ny, nx = img.shape
     dy, dx = tt.log2_exact(ny), tt.log2_exact(nx)
@@ -88,7 +90,11 @@ def pipeline_2d(img, Bx: float, By: float, eps: float, max_rank: int = 0,
     Wy, wyinfo = tt.tt_svd(wy, eps_w, 0, return_info=True)
     wx_t, wy_t = tt.tt_full(Wx), tt.tt_full(Wy)
     y = conv.toeplitz_apply_2d(f_t, wy_t, wx_t, fft=fft)
-    Z, zinfo = tt.tt_svd(y.ravel(), eps, round_max_rank, return_info=True)
+    if sketch_ell > 0:
+        Z, zinfo = rsvd.tt_svd_sketch(y.ravel(), eps, round_max_rank, sketch_ell, sketch_seed,
+                                      return_info=True)
+    else:
+        Z, zinfo = tt.tt_svd(y.ravel(), eps, round_max_rank, return_info=True)
     out = tt.tt_full(Z).reshape(ny, nx)
     return dict(F=F, Wx=Wx, Wy=Wy, Z=Z, f_tilde=f_t, wx_tilde=wx_t, wy_tilde=wy_t, y=y,
                 out=out, F_ranks=finfo["ranks"], Wx_ranks=wxinfo["ranks"],

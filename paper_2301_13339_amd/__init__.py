@@ -245,20 +245,36 @@ _METHODS = {"exact": QTT_ROUND_EXACT, "sketch_f32": QTT_ROUND_SKETCH_F32,
             "sketch_bf16": QTT_ROUND_SKETCH_BF16}
 
 
-def round(y: QTT, eps: float, max_rank: int = 0, method: str = "exact", seed: int = 0) -> QTT:  # noqa: A001
-    """TT-rounding of ``y`` at tolerance ``eps``."""
+def round(y: QTT, eps: float, max_rank: int = 0, method: str = "exact", seed: int = 0,  # noqa: A001
+          ell: int | None = None) -> QTT:
+    """TT-rounding of ``y`` at tolerance ``eps``.
+
+    ``method``: ``"exact"``, ``"sketch_f32"`` or ``"sketch_bf16"`` (the
+    randomised form; ``ell`` columns, default ``QTT_SKETCH_ELL``).
+    """
     m = _METHODS[method]
     ycap = (ctypes.c_int32 * (y.d + 1))(*y.cap)
     zcap = (ctypes.c_int32 * (y.d + 1))()
     wsb = ctypes.c_size_t()
-    _check(lib().qtt_query_round(y.d, ycap, int(max_rank), y.dtype, m, zcap, ctypes.byref(wsb),
-                                 None), "qtt_query_round")
+    if m == QTT_ROUND_EXACT or ell is None:
+        _check(lib().qtt_query_round(y.d, ycap, int(max_rank), y.dtype, m, zcap,
+                                     ctypes.byref(wsb), None), "qtt_query_round")
+    else:
+        _check(lib().qtt_query_round_sketch(y.d, ycap, int(max_rank), y.dtype, int(ell), zcap,
+                                            ctypes.byref(wsb), None), "qtt_query_round_sketch")
     z = _make(y.d, y.dtype, list(zcap), y.device)
     w = _workspace(wsb.value, y.device)
     yc, zc = y._c(), z._c()
-    _check(lib().qtt_round(ctypes.byref(yc), float(eps), int(max_rank), m, ctypes.c_uint64(seed),
-                           ctypes.byref(zc), ctypes.c_void_p(w.data_ptr()), wsb.value,
-                           _stream(y.device)), "qtt_round")
+    if m == QTT_ROUND_EXACT or ell is None:
+        _check(lib().qtt_round(ctypes.byref(yc), float(eps), int(max_rank), m,
+                               ctypes.c_uint64(seed), ctypes.byref(zc),
+                               ctypes.c_void_p(w.data_ptr()), wsb.value, _stream(y.device)),
+               "qtt_round")
+    else:
+        _check(lib().qtt_round_sketch(ctypes.byref(yc), float(eps), int(max_rank), int(ell),
+                                      int(m == QTT_ROUND_SKETCH_BF16), ctypes.c_uint64(seed),
+                                      ctypes.byref(zc), ctypes.c_void_p(w.data_ptr()), wsb.value,
+                                      _stream(y.device)), "qtt_round_sketch")
     z._keep = [w, y]
     return z
 
@@ -280,7 +296,8 @@ def full(t: QTT, out: torch.Tensor | None = None) -> torch.Tensor:
 
 
 def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | None = None,
-             round_method: str = "exact", round_max_rank: int = 0, shape2d=None):
+             round_method: str = "exact", round_max_rank: int = 0, shape2d=None,
+             sketch_ell: int | None = None, sketch_seed: int = 0):
     """Decompose, build the kernel QTT, convolve, round and reconstruct.
 
     ``B`` is one bandwidth (signal) or ``(Bx, By)`` with ``shape2d = (ny, nx)``
@@ -309,7 +326,7 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
         t.record_stream(main)
     am = [f.d] if shape2d is None else [dx, dy]
     y = conv(f, w, am)
-    z = round(y, eps, round_max_rank, round_method)
+    z = round(y, eps, round_max_rank, round_method, sketch_seed, sketch_ell)
     out = full(z)
     if shape2d is not None:
         out = out.reshape(shape2d)

@@ -24,7 +24,7 @@ EXPORTS = [
     "qtt_core_elems", "qtt_strerror", "qtt_last_hip_error",
     "qtt_query_decompose", "qtt_decompose", "qtt_kernel_sinc",
     "qtt_query_conv", "qtt_conv",
-    "qtt_query_round", "qtt_round",
+    "qtt_query_round", "qtt_round", "qtt_query_round_sketch", "qtt_round_sketch",
     "qtt_query_full", "qtt_full",
     "qtt_query_toeplitz", "qtt_toeplitz_apply",
     "qtt_query_kernel_sinc_dB", "qtt_kernel_sinc_dB",
@@ -39,7 +39,7 @@ EXPORTS = [
 K_CLASSES = {
     "level_gram": 1, "reduce": 2, "level_eig": 3, "project": 4, "eig_step": 5, "tail": 6,
     "conv": 7, "full_chain": 8, "full_final": 9, "other": 10, "adjoint": 11,
-    "batch": 12,
+    "batch": 12, "sketch": 13,
 }
 
 
@@ -94,6 +94,12 @@ def _declare(L):
     L.qtt_round.restype = ctypes.c_int
     L.qtt_round.argtypes = [_TP, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
                             _TP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_query_round_sketch.restype = ctypes.c_int
+    L.qtt_query_round_sketch.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, ctypes.c_int,
+                                         ctypes.c_int, _I32P, _SZP, _SZP]
+    L.qtt_round_sketch.restype = ctypes.c_int
+    L.qtt_round_sketch.argtypes = [_TP, ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                   ctypes.c_uint64, _TP, _VP, ctypes.c_size_t, _VP]
     L.qtt_query_full.restype = ctypes.c_int
     L.qtt_query_full.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _SZP]
     L.qtt_full.restype = ctypes.c_int

@@ -114,7 +114,7 @@ const char* qtt_strerror(int code) {
 const char* qtt_last_hip_error(void) { return g_hip_err; }
 
 int qtt_probe_start(int cls, int max_launches) {
-  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_BATCH || max_launches < 1 || max_launches > (1 << 20))
+  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_SKETCH || max_launches < 1 || max_launches > (1 << 20))
     return QTT_EINVAL;
   probe_free();
   g_probe.ev = new hipEvent_t[2 * (size_t)max_launches];
@@ -291,7 +291,7 @@ struct RoundPlan {
   size_t total;
 };
 
-static void plan_round(int d, const int32_t* y_cap, int rcap, int dtype, void* ws,
+static void plan_round(int d, const int32_t* y_cap, int rcap, int dtype, int ell, void* ws,
                        RoundPlan* rp) {
   Arena ar(ws);
   const size_t es = elem_size(dtype);
@@ -301,20 +301,25 @@ static void plan_round(int d, const int32_t* y_cap, int rcap, int dtype, void* w
   plan_full(d, y_cap, dtype, nullptr, &fb, bufs);
   rp->full_ws = ar.take<char>(fb);
   rp->full_bytes = fb;
-  DecompPlan p;
-  plan_decompose(d, rcap, dtype, nullptr, &p);
-  rp->dec_ws = ar.take<char>(p.ws_bytes);
-  rp->dec_bytes = p.ws_bytes;
+  size_t db;
+  if (ell > 0) {
+    db = sketch_ws_bytes(d, dtype, ell);
+  } else {
+    DecompPlan p;
+    plan_decompose(d, rcap, dtype, nullptr, &p);
+    db = p.ws_bytes;
+  }
+  rp->dec_ws = ar.take<char>(db);
+  rp->dec_bytes = db;
   rp->total = ar.size();
 }
 
-int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int method,
-                    int32_t* z_cap, size_t* ws_bytes, size_t* core_elems) {
+// ell = 0: exact rounding; otherwise the sketch width
+static int query_round_common(int d, const int32_t* y_cap, int max_rank, int dtype, int ell,
+                              int32_t* z_cap, size_t* ws_bytes, size_t* core_elems) {
   if (d < 1 || d > kMaxModes || !y_cap || !dtype_ok(dtype) || max_rank < 0) return QTT_EINVAL;
-  if (method < QTT_ROUND_EXACT || method > QTT_ROUND_SKETCH_BF16) return QTT_EINVAL;
-  if (method != QTT_ROUND_EXACT) return QTT_ENOTSUP;
   RoundPlan rp;
-  plan_round(d, y_cap, eff_rank(max_rank), dtype, nullptr, &rp);
+  plan_round(d, y_cap, eff_rank(max_rank), dtype, ell, nullptr, &rp);
   int32_t zc[QTT_MAXD + 1];
   caps_decompose(d, eff_rank(max_rank), zc);
   if (z_cap) memcpy(z_cap, zc, sizeof(int32_t) * (d + 1));
@@ -323,32 +328,63 @@ int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int me
   return QTT_OK;
 }
 
-int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_t seed,
-              qtt_tensor* z, void* ws, size_t ws_bytes, void* stream) {
-  (void)seed;
+int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int method,
+                    int32_t* z_cap, size_t* ws_bytes, size_t* core_elems) {
+  if (method < QTT_ROUND_EXACT || method > QTT_ROUND_SKETCH_BF16) return QTT_EINVAL;
+  return query_round_common(d, y_cap, max_rank, dtype,
+                            method == QTT_ROUND_EXACT ? 0 : QTT_SKETCH_ELL, z_cap, ws_bytes,
+                            core_elems);
+}
+
+int qtt_query_round_sketch(int d, const int32_t* y_cap, int max_rank, int dtype, int ell,
+                           int32_t* z_cap, size_t* ws_bytes, size_t* core_elems) {
+  if (ell < 1 || ell > QTT_SKETCH_MAX_ELL) return QTT_EINVAL;
+  return query_round_common(d, y_cap, max_rank, dtype, ell, z_cap, ws_bytes, core_elems);
+}
+
+static int round_common(const qtt_tensor* y, double eps, int max_rank, int ell, int bf16,
+                        uint64_t seed, qtt_tensor* z, void* ws, size_t ws_bytes, void* stream) {
   if (check_tensor_in(y) || y->d > kMaxModes || !(eps >= 0.0) || !isfinite(eps) || max_rank < 0 ||
       !ws)
     return QTT_EINVAL;
-  if (method < QTT_ROUND_EXACT || method > QTT_ROUND_SKETCH_BF16) return QTT_EINVAL;
-  if (method != QTT_ROUND_EXACT) return QTT_ENOTSUP;
   const int d = y->d;
+  if (d < 2) ell = 0;  // one mode: nothing to truncate, the exact path copies
   RoundPlan rp;
-  plan_round(d, y->cap, eff_rank(max_rank), y->dtype, nullptr, &rp);
+  plan_round(d, y->cap, eff_rank(max_rank), y->dtype, ell, nullptr, &rp);
   if (ws_bytes < rp.total) return QTT_ENOSPC;
   int32_t zc[QTT_MAXD + 1];
   caps_decompose(d, eff_rank(max_rank), zc);
   int rc = check_tensor(z, d, y->dtype, zc);
   if (rc) return rc;
-  plan_round(d, y->cap, eff_rank(max_rank), y->dtype, ws, &rp);
+  plan_round(d, y->cap, eff_rank(max_rank), y->dtype, ell, ws, &rp);
   hipStream_t st = static_cast<hipStream_t>(stream);
   TensorDev yd = make_dev(y);
   rc = run_full(yd, y->dtype, rp.yfull, rp.full_ws, st);
   if (rc) return rc;
+  TensorDev zd = make_dev(z);
+  if (ell > 0) {
+    int capi[QTT_MAXD + 1];
+    for (int k = 0; k <= d; ++k) capi[k] = zc[k];
+    return run_round_sketch(y->dtype, bf16, rp.yfull, d, eps, capi, ell, seed, zd, rp.dec_ws, st);
+  }
   DecompPlan p;
   plan_decompose(d, eff_rank(max_rank), y->dtype, rp.dec_ws, &p);
   Source src{rp.yfull, 0, 0.0, 0};
-  TensorDev zd = make_dev(z);
   return run_decompose(p, src, eps, zd, nullptr, st);
+}
+
+int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_t seed,
+              qtt_tensor* z, void* ws, size_t ws_bytes, void* stream) {
+  if (method < QTT_ROUND_EXACT || method > QTT_ROUND_SKETCH_BF16) return QTT_EINVAL;
+  const int ell = method == QTT_ROUND_EXACT ? 0 : QTT_SKETCH_ELL;
+  return round_common(y, eps, max_rank, ell, method == QTT_ROUND_SKETCH_BF16, seed, z, ws,
+                      ws_bytes, stream);
+}
+
+int qtt_round_sketch(const qtt_tensor* y, double eps, int max_rank, int ell, int bf16,
+                     uint64_t seed, qtt_tensor* z, void* ws, size_t ws_bytes, void* stream) {
+  if (ell < 1 || ell > QTT_SKETCH_MAX_ELL || (bf16 != 0 && bf16 != 1)) return QTT_EINVAL;
+  return round_common(y, eps, max_rank, ell, bf16, seed, z, ws, ws_bytes, stream);
 }
 
 // --------------------------------------------------------------- adjoint

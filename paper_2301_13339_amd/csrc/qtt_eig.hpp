@@ -1,6 +1,7 @@
-// Truncation rule of Algorithm 1 (with the max-rank modification (1)) on the
-// eigenvalues of the Gram matrix of an unfolding; the eigensolver itself is
-// in qtt_syev.hpp.
+// One truncated SVD step of the sweep on the Gram matrix of an unfolding:
+// the truncation rule of Algorithm 1 (with the max-rank modification (1)) on
+// its eigenvalues, and solve_and_truncate, which runs the eigensolver of
+// qtt_syev.hpp, picks the rank and leaves the kept eigenvectors.
 #pragma once
 
 #include "qtt_internal.hpp"
@@ -28,6 +29,134 @@ __device__ inline int truncation_rank_dev(const double* lam, int E, double tau2,
   if (r < 1) r = 1;
   *over = r > cap;
   return r < cap ? r : cap;
+}
+
+// ----------------------------------------------------- step bookkeeping
+// capacities and core offsets, passed by value to the kernels
+struct Meta {
+  int caps[QTT_MAXD + 1];
+  long long offs[QTT_MAXD + 1];
+};
+
+struct StepOut {
+  int32_t* ranks;
+  int32_t* status;
+  double* sv;  // may be null
+  int lib_capped;
+  int32_t* dbg;  // per-step diagnostics in the workspace (optional timings)
+};
+
+// Eigen-solve the Gram matrix in A (E x E), choose the rank, and leave the
+// kept eigenvectors in the first r columns of V (descending eigenvalues):
+// lam[0..E) = eigenvalues in non-increasing order, perm[b] = b.  sx: scratch
+// of kEigScratch doubles.  Returns r.  Must be called by all threads.
+constexpr int kEigScratch = 10 * kMaxM + 16;
+// one workgroup of 4 waves: a barrier costs ~40 cycles with 4 waves and
+// ~470 with 16 on gfx950, and every eigen step is barrier/latency bound
+constexpr int kEigThreads = 256;
+
+template <int NT, bool BIG = false>
+__device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* sx, int* iscr,
+                                  double* lam, int* perm, double tau2, int cap, int k,
+                                  const StepOut& so) {
+  const int tid = threadIdx.x;
+  double* dg = sx;
+  double* od = dg + kMaxM;
+  double* bt = od + kMaxM;
+  double* pv = bt + kMaxM;
+  double* e2 = pv + kMaxM;
+  double* la = e2 + kMaxM;  // ascending eigenvalues
+  // the tridiagonalisation takes pv .. pv + 4 kMaxM (over e2 and la, which are
+  // used only after it) for its column and p buffers
+  // finiteness of the Gram (NaN/Inf input)
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < E; ++i) tr += A[i * lda + i];
+    iscr[1] = isfinite(tr) ? 1 : 0;
+  }
+  __syncthreads();
+  const int finite = iscr[1];
+#ifdef QTT_EIG_TIMING
+  long long tt[6];
+  tt[0] = wall_clock64();
+#endif
+  if (finite) {
+    if (BIG && E > 64)
+      sy_tridiag<NT, BIG ? 8 : 4>(A, E, lda, dg, od, bt, pv);
+    else
+      sy_tridiag<NT, 4>(A, E, lda, dg, od, bt, pv);
+#ifdef QTT_EIG_TIMING
+    tt[1] = wall_clock64();
+#endif
+    tridiag_eigvals<NT>(dg, od, E, la, e2, pv);
+  }
+#ifdef QTT_EIG_TIMING
+  tt[2] = wall_clock64();
+#endif
+  for (int i = tid; i < E; i += NT) {
+    lam[i] = finite ? la[E - 1 - i] : 0.0;
+    perm[i] = i;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int over = 0;
+    const int r = truncation_rank_dev(lam, E, tau2, cap, &over);
+    iscr[2] = r;
+    so.ranks[k] = r;
+    if (so.status) {
+      if (!finite) atomicOr(so.status, QTT_STATUS_NONFINITE);
+      if (over && so.lib_capped) atomicOr(so.status, QTT_STATUS_RANKCAP);
+    }
+  }
+  if (so.sv) {
+    for (int i = tid; i < kSvStride; i += NT) {
+      const double l = (i < E) ? lam[i] : 0.0;
+      so.sv[(size_t)(k - 1) * kSvStride + i] = l > 0.0 ? sqrt(l) : 0.0;
+    }
+  }
+  __syncthreads();
+  const int r = iscr[2];
+  if (!finite) {
+    for (int idx = tid; idx < E * E; idx += NT) {
+      const int a = idx / E, c = idx - a * E;
+      V[a * lda + c] = (a == c) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    return r;
+  }
+  // eigenvectors of T for the kept eigenvalues, one lane per vector
+  {
+    double nrm = 0.0;
+    for (int i = 0; i < E; ++i)
+      nrm = fmax(nrm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0));
+    const double tiny = 1e-300 + 1e-30 * nrm;
+    for (int b = tid; b < r; b += NT) tridiag_vec(dg, od, E, lam[b], V + b, lda, tiny);
+  }
+  __syncthreads();
+#ifdef QTT_EIG_TIMING
+  tt[3] = wall_clock64();
+#endif
+  // pv .. pv + 7 kMaxM (pv, e2, la and the arrays after) are free now
+  mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
+#ifdef QTT_EIG_TIMING
+  tt[4] = wall_clock64();
+#endif
+  back_transform<NT>(A, bt, E, lda, V, lda, r);
+#ifdef QTT_EIG_TIMING
+  tt[5] = wall_clock64();
+  if (tid == 0 && so.dbg) {
+    so.dbg[k] = E;
+    int* tm = so.dbg + 64 + 4 * k;
+    (void)tm;
+    int* t5 = so.dbg + 64 + 5 * k;
+    t5[0] = (int)(tt[1] - tt[0]);
+    t5[1] = (int)(tt[2] - tt[1]);
+    t5[2] = (int)(tt[3] - tt[2]);
+    t5[3] = (int)(tt[4] - tt[3]);
+    t5[4] = (int)(tt[5] - tt[4]);
+  }
+#endif
+  return r;
 }
 
 }  // namespace qtt

@@ -173,6 +173,11 @@ int run_full(const TensorDev& t, int dtype, void* out, void* ws, hipStream_t str
 int run_conv(const TensorDev& f, const TensorDev* w, int n_axes, const int32_t* axis_modes,
              const TensorDev& y, int dtype, hipStream_t stream);
 
+// ------------------------------------------------------------------- sketch
+size_t sketch_ws_bytes(int D, int dtype, int ell);
+int run_round_sketch(int dtype, int bf16, const void* y, int D, double eps, const int* cap,
+                     int ell, uint64_t seed, const TensorDev& out, void* ws, hipStream_t s);
+
 // ------------------------------------------------------------------ adjoint
 size_t toeplitz_ws_elems(int d, const int32_t* w_cap);
 int run_toeplitz(const TensorDev& w, int dtype, const void* x, void* y, int trans, void* ws,
