@@ -100,3 +100,21 @@ def test_sketch_image_bf16(q):
     out, st = q.pipeline(x.reshape(-1), (60.0, 60.0), eps, R, shape2d=noisy.shape,
                          round_method="sketch_bf16", sketch_ell=ell, sketch_seed=seed)
     assert rel(out.cpu().numpy(), ref["out"]) <= max(2 * eps, 3e-3)
+
+
+def test_image_4096_precision_form(q):
+    """The 4096 x 4096 image at full size (FP32 data, BF16-operand sketch,
+    ell = 64): against the FP64 exact pipeline on the same input (the oracle's
+    exact-SVD sweep at this size is beyond a test's time), within
+    max(2 eps, 3e-3); ranks within the capacities; no status bits."""
+    noisy, _ = G.sar_image_2d(12, 12, seed=3)
+    print("image 4096", flush=True)
+    eps, R = 1e-3, 32
+    x32 = torch.tensor(noisy, dtype=torch.float32, device=DEV)
+    x64 = torch.tensor(noisy, dtype=torch.float64, device=DEV)
+    out, st = q.pipeline(x32, (1000.0, 1000.0), eps, R, shape2d=noisy.shape,
+                         round_method="sketch_bf16", sketch_ell=64, sketch_seed=1)
+    ref, st64 = q.pipeline(x64, (1000.0, 1000.0), eps, R, shape2d=noisy.shape)
+    assert rel(out.cpu().numpy(), ref.cpu().numpy()) <= max(2 * eps, 3e-3)
+    assert st["z"].status_host() == 0 and st["f"].status_host() == 0
+    assert max(st["f"].ranks_host()) <= R
