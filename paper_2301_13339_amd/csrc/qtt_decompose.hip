@@ -249,7 +249,8 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
     }
     __syncthreads();
     const int r =
-        solve_and_truncate<NT>(A, V, m, LDA, sx, iscr, lam, perm, tau2, meta.caps[k], k, so);
+        solve_and_truncate<NT>(lds(A), lds(V), m, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
+                               tau2, meta.caps[k], k, so);
     // core k = V[:, perm[:r]]
     {
       const int total = rp * 2 * r;
@@ -387,10 +388,10 @@ __global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, in
 // --------------------------------------------------------------- eig step
 // Step k from the Gram already in A (M x M, stride lda), M = 2 r_{k-1}: the
 // truncated eigendecomposition, core k, and U_k (M x r_k, row-major) in umat.
-template <typename T>
-__device__ int eig_step_solve(double* A, double* V, int lda, double* lam, double* sx, int* perm,
-                              int* iscr, int M, int k, double tau2, int cap_k, T* cores,
-                              long long off_k, double* umat, const StepOut& so) {
+template <typename T, class MP>
+__device__ int eig_step_solve(MP A, MP V, int lda, ldsd lam, ldsd sx, ldsi perm, ldsi iscr, int M,
+                              int k, double tau2, int cap_k, T* cores, long long off_k,
+                              double* umat, const StepOut& so) {
   constexpr int NT = kEigThreads;
   const int tid = threadIdx.x;
   const int rp = M / 2;
@@ -435,6 +436,17 @@ __device__ __forceinline__ EigLayout eig_layout(double* smem, int M, double* gA,
   return L;
 }
 
+// eig_step_solve on a layout: A and V as LDS pointers when they live there
+template <typename T>
+__device__ int eig_step_solve_at(const EigLayout& L, int M, int k, double tau2, int cap_k,
+                                 T* cores, long long off_k, double* umat, const StepOut& so) {
+  if (M <= kEigLds)
+    return eig_step_solve<T>(lds(L.A), lds(L.V), L.lda, lds(L.lam), lds(L.sx), lds(L.perm),
+                             lds(L.iscr), M, k, tau2, cap_k, cores, off_k, umat, so);
+  return eig_step_solve<T>(L.A, L.V, L.lda, lds(L.lam), lds(L.sx), lds(L.perm), lds(L.iscr), M,
+                           k, tau2, cap_k, cores, off_k, umat, so);
+}
+
 template <typename T>
 __global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, int mstride, int k,
                                                    const double* scal, int cap_k, T* cores,
@@ -448,8 +460,7 @@ __global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, in
     L.A[i * L.lda + j] = gram[i * mstride + j];
   }
   __syncthreads();
-  eig_step_solve<T>(L.A, L.V, L.lda, L.lam, L.sx, L.perm, L.iscr, M, k, scal[1], cap_k, cores,
-                    off_k, umat, so);
+  eig_step_solve_at<T>(L, M, k, scal[1], cap_k, cores, off_k, umat, so);
 }
 
 // -------------------------------------------------------------------- tail
@@ -531,7 +542,8 @@ __device__ void tail_steps(double* smem, const T* Xin, double B, int nk, int k0,
     }
     __syncthreads();
     const int r =
-        solve_and_truncate<NT>(A, V, E, LDA, sx, iscr, lam, perm, tau2, meta.caps[k], k, so);
+        solve_and_truncate<NT>(lds(A), lds(V), E, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
+                               tau2, meta.caps[k], k, so);
     const long long off = meta.offs[k - 1];
     const int total = rp * 2 * r;
     double yv[kPer];
@@ -637,8 +649,10 @@ __device__ __forceinline__ void wg_sync_global() {
 
 template <typename T, int GEN, int TS>
 __device__ __noinline__ void batch_project(const T* Ain, double B, int nk, long long rowsA, int WA, int r,
-                              const double* U, T* Xout, int do_gram, double* smem, int M,
+                              const double* U, T* Xout, int do_gram, ldsd smem_l, int M,
                               const EigLayout& Ly) {
+  // generic view of the LDS pointer: its accesses still compile to ds_*
+  double* smem = (double*)smem_l;
   double acc[TS][TS];
   project_gram_acc<T, GEN, TS>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, 0, 1, smem, acc);
   if (do_gram) {
@@ -660,19 +674,20 @@ __device__ void batch_project_any(int Mcap, const T* Ain, double B, int nk, long
                                   int WA, int r, const double* U, T* Xout, int do_gram,
                                   double* smem, int M, const EigLayout& Ly) {
   if (Mcap <= 16)
-    batch_project<T, GEN, 1>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+    batch_project<T, GEN, 1>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, lds(smem), M, Ly);
   else if (Mcap <= 32)
-    batch_project<T, GEN, 2>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+    batch_project<T, GEN, 2>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, lds(smem), M, Ly);
   else if (Mcap <= 64)
-    batch_project<T, GEN, 4>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+    batch_project<T, GEN, 4>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, lds(smem), M, Ly);
   else
-    batch_project<T, GEN, 8>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, smem, M, Ly);
+    batch_project<T, GEN, 8>(Ain, B, nk, rowsA, WA, r, U, Xout, do_gram, lds(smem), M, Ly);
 }
 
 template <typename T, int GEN>
 __device__ __noinline__ void batch_line(const BatchTask& tk, const T* x, T* cores, int32_t* ranks,
-                           int32_t* status, double* smem, Meta& meta, double* wscr, T* xb0,
+                           int32_t* status, ldsd smem_l, Meta& meta, double* wscr, T* xb0,
                            T* xb1) {
+  double* smem = (double*)smem_l;  // LDS (accesses compile to ds_*)
   const int tid = threadIdx.x;
   const int D = tk.D;
   double* scal = wscr;
@@ -758,8 +773,8 @@ __device__ __noinline__ void batch_line(const BatchTask& tk, const T* x, T* core
     const int rp = so.ranks[k - 1];
     const int M = 2 * rp;
     const EigLayout Ly = eig_layout(smem, M, gA, gV);
-    const int r = eig_step_solve<T>(Ly.A, Ly.V, Ly.lda, Ly.lam, Ly.sx, Ly.perm, Ly.iscr, M, k,
-                                    scal[1], meta.caps[k], cores, meta.offs[k - 1], umat, so);
+    const int r = eig_step_solve_at<T>(Ly, M, k, scal[1], meta.caps[k], cores, meta.offs[k - 1],
+                                       umat, so);
     wg_sync_global();
     const int M2 = 2 * r;
     const EigLayout Ly2 = eig_layout(smem, M2, gA, gV);
@@ -795,7 +810,7 @@ __global__ void __launch_bounds__(kEigThreads) k_batch_decompose(
     __syncthreads();
     if (t >= ntasks) break;  // every wave leaves on the same value
     const BatchTask tk = tasks[t];
-    batch_line<T, GEN>(tk, x, cores, ranks, status, smem, s_meta, my, xb0, xb1);
+    batch_line<T, GEN>(tk, x, cores, ranks, status, lds(smem), s_meta, my, xb0, xb1);
     wg_sync_global();
   }
 }

@@ -12,7 +12,7 @@ namespace qtt {
 // Algorithm 1's rule on the sorted eigenvalues of the Gram matrix: smallest
 // r >= 1 with sum_{i >= r} lam_i <= tau2 (tails summed from the small end),
 // then min(r, cap).  *over is set when the eps-rank exceeded cap.
-__device__ inline int truncation_rank_dev(const double* lam, int E, double tau2, int cap,
+__device__ inline int truncation_rank_dev(lds_ptr<const double> lam, int E, double tau2, int cap,
                                           int* over) {
   double tail = 0.0;
   int r = E;
@@ -55,17 +55,17 @@ constexpr int kEigScratch = 10 * kMaxM + 16;
 // ~470 with 16 on gfx950, and every eigen step is barrier/latency bound
 constexpr int kEigThreads = 256;
 
-template <int NT, bool BIG = false>
-__device__ int solve_and_truncate(double* A, double* V, int E, int lda, double* sx, int* iscr,
-                                  double* lam, int* perm, double tau2, int cap, int k,
+template <int NT, bool BIG = false, class MP>
+__device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr, ldsd lam,
+                                  ldsi perm, double tau2, int cap, int k,
                                   const StepOut& so) {
   const int tid = threadIdx.x;
-  double* dg = sx;
-  double* od = dg + kMaxM;
-  double* bt = od + kMaxM;
-  double* pv = bt + kMaxM;
-  double* e2 = pv + kMaxM;
-  double* la = e2 + kMaxM;  // ascending eigenvalues
+  ldsd dg = sx;
+  ldsd od = dg + kMaxM;
+  ldsd bt = od + kMaxM;
+  ldsd pv = bt + kMaxM;
+  ldsd e2 = pv + kMaxM;
+  ldsd la = e2 + kMaxM;  // ascending eigenvalues
   // the tridiagonalisation takes pv .. pv + 4 kMaxM (over e2 and la, which are
   // used only after it) for its column and p buffers
   // finiteness of the Gram (NaN/Inf input)

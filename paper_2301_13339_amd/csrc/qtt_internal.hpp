@@ -24,6 +24,21 @@ constexpr int kEigLds = 64;                  // eigen problems up to this size l
 constexpr int kMaxPartials = 128;            // partial Gram matrices per streaming pass
 constexpr int kSvStride = 2 * kMaxRank;      // row stride of the optional singular-value output
 
+// ------------------------------------------------------------ LDS pointers
+// A plain pointer argument of a device function that is not inlined is a
+// generic address, and every access through it is a flat instruction (the
+// latency of a global access and a wait on both memory counters) even when
+// it points into LDS.  The eigensolver passes its LDS arrays as pointers in
+// address space 3 instead, so that they compile to ds_* instructions.
+template <class T>
+using lds_ptr = __attribute__((address_space(3))) T*;
+using ldsd = lds_ptr<double>;
+using ldsi = lds_ptr<int>;
+template <class T>
+__device__ __forceinline__ lds_ptr<T> lds(T* p) {
+  return (lds_ptr<T>)p;
+}
+
 // -------------------------------------------------------------- host arena
 struct Arena {
   char* base;

@@ -280,7 +280,8 @@ __global__ void __launch_bounds__(kEigThreads) k_sketch_step(
     }
   }
   __syncthreads();
-  const int r = solve_and_truncate<NT>(A, V, el, LDA, sx, iscr, lam, perm, tau2, cap_k, k, so);
+  const int r = solve_and_truncate<NT>(lds(A), lds(V), el, LDA, lds(sx), lds(iscr), lds(lam),
+                                       lds(perm), tau2, cap_k, k, so);
   // U = Q V_r (m x r)
   for (int e = tid; e < m * r; e += NT) {
     const int i = e / r, b = e - i * r;

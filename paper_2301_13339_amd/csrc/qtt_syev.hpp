@@ -77,9 +77,8 @@ __device__ __forceinline__ double rcp_acc(double x) {
 // v vanishes there and A is already reduced there.  v_j is left in
 // A[j+1.., j] (LDS) and beta_j in bt[j].  buf: >= 4*kMaxM doubles (double-
 // buffered column and p vectors, so two barriers per step suffice).
-template <int NT, int BS>
-__device__ void sy_tridiag(double* A, int E, int lda, double* dg, double* od, double* bt,
-                           double* buf) {
+template <int NT, int BS, class MP>
+__device__ void sy_tridiag(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd buf) {
   static_assert(NT == 256, "16 x 16 thread grid");
   const int tid = threadIdx.x;
   const int br = tid >> 4, bc = tid & 15;
@@ -96,8 +95,8 @@ __device__ void sy_tridiag(double* A, int E, int lda, double* dg, double* od, do
     }
   __syncthreads();  // A (LDS) now only receives reflectors
   for (int j = 0; j + 2 < E; ++j) {
-    double* colb = buf + (j & 1) * (2 * kMaxM);
-    double* pb = colb + kMaxM;
+    ldsd colb = buf + (j & 1) * (2 * kMaxM);
+    ldsd pb = colb + kMaxM;
     // 1. publish column j
     if (bc == j / BS) {
       const int jc = j - c0;
@@ -248,7 +247,7 @@ __device__ __forceinline__ int sign_change(double a, double b) {
 }
 
 template <int NC>
-__device__ __forceinline__ void sturm_counts(const double* dn, const double* e2n, int E,
+__device__ __forceinline__ void sturm_counts(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E,
                                              const double* x, int* c) {
   double pm[NC], pc[NC];
 #pragma unroll
@@ -287,8 +286,8 @@ __device__ __forceinline__ void sturm_counts(const double* dn, const double* e2n
 // Multisection over NC chains per lane: a 16-lane group brackets the
 // eigenvalues k = g, g + NT/16, ... and shrinks each bracket 17x per pass.
 template <int NT, int NC>
-__device__ void multisect(const double* dn, const double* e2n, int E, double lo, double hi,
-                          double width_stop, double scale, double* lam) {
+__device__ void multisect(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E, double lo,
+                          double hi, double width_stop, double scale, ldsd lam) {
   const int tid = threadIdx.x;
   const int l16 = tid & 15, g16 = tid >> 4;
   constexpr int NG16 = NT / 16;
@@ -332,8 +331,8 @@ __device__ void multisect(const double* dn, const double* e2n, int E, double lo,
 // All eigenvalues of T in ascending order into lam[0..E), to an absolute
 // accuracy of about 1e-15 ||T||.  e2, dn: >= E doubles of scratch each.
 template <int NT>
-__device__ void tridiag_eigvals(const double* dg, const double* od, int E, double* lam,
-                                double* e2, double* dn) {
+__device__ void tridiag_eigvals(lds_ptr<const double> dg, lds_ptr<const double> od, int E, ldsd lam,
+                                ldsd e2, ldsd dn) {
   const int tid = threadIdx.x;
   // Gershgorin scale (every thread)
   double nrm = 0.0;
@@ -372,8 +371,9 @@ __device__ void tridiag_eigvals(const double* dg, const double* od, int E, doubl
 
 // Eigenvector of T for eigenvalue lam by a twisted factorisation; written
 // (normalised) to z[i*ldz] for i < E.  One lane per vector.
-__device__ inline void tridiag_vec(const double* dg, const double* od, int E, double lam,
-                                   double* z, int ldz, double tiny) {
+template <class MP>
+__device__ inline void tridiag_vec(lds_ptr<const double> dg, lds_ptr<const double> od, int E,
+                                   double lam, MP z, int ldz, double tiny) {
   if (E == 1) {
     z[0] = 1.0;
     return;
@@ -446,13 +446,14 @@ __device__ inline void tridiag_vec(const double* dg, const double* od, int E, do
 // with partial pivoting on the tridiagonal matrix (one lane).  Zero pivots
 // are replaced by `tiny` (inverse iteration only needs a direction).
 // w: 5E doubles of scratch.
-__device__ inline void tridiag_shift_solve(const double* dg, const double* od, int E, double mu,
-                                           double* b, int ldb, double* w, double tiny) {
-  double* dd = w;           // diagonal of U
-  double* du = w + E;       // first superdiagonal of U
-  double* du2 = w + 2 * E;  // second superdiagonal (fill-in from interchanges)
-  double* ml = w + 3 * E;   // multipliers
-  double* sw = w + 4 * E;   // 1 where rows i and i+1 were interchanged
+template <class MP>
+__device__ inline void tridiag_shift_solve(lds_ptr<const double> dg, lds_ptr<const double> od,
+                                           int E, double mu, MP b, int ldb, ldsd w, double tiny) {
+  ldsd dd = w;           // diagonal of U
+  ldsd du = w + E;       // first superdiagonal of U
+  ldsd du2 = w + 2 * E;  // second superdiagonal (fill-in from interchanges)
+  ldsd ml = w + 3 * E;   // multipliers
+  ldsd sw = w + 4 * E;   // 1 where rows i and i+1 were interchanged
   for (int i = 0; i < E; ++i) {
     dd[i] = dg[i] - mu;
     du[i] = (i + 1 < E) ? od[i] : 0.0;
@@ -504,8 +505,8 @@ __device__ inline void tridiag_shift_solve(const double* dg, const double* od, i
 
 // Classical Gram-Schmidt (applied twice) of column j of Z against columns
 // 0..j-1 (mutually orthogonal, squared norms cn[c]).  al: >= j doubles.
-template <int NT>
-__device__ void cgs2_col(double* Z, int E, int ldz, int j, const double* cn, double* al) {
+template <int NT, class MP>
+__device__ void cgs2_col(MP Z, int E, int ldz, int j, lds_ptr<const double> cn, ldsd al) {
   const int tid = threadIdx.x;
   const int l16 = tid & 15, g16 = tid >> 4;
   constexpr int NG16 = NT / 16;
@@ -527,7 +528,8 @@ __device__ void cgs2_col(double* Z, int E, int ldz, int j, const double* cn, dou
 }
 
 // Squared norm of column j (identical in every 16-lane group).
-__device__ __forceinline__ double col_norm2(const double* Z, int E, int ldz, int j) {
+template <class MP>
+__device__ __forceinline__ double col_norm2(MP Z, int E, int ldz, int j) {
   const int l16 = threadIdx.x & 15;
   double s = 0.0;
   for (int i = l16; i < E; i += 16) s = fma(Z[i * ldz + j], Z[i * ldz + j], s);
@@ -544,15 +546,15 @@ __device__ __forceinline__ double col_norm2(const double* Z, int E, int ldz, int
 // same vector for every copy.  It is replaced by inverse iteration with T
 // shifted just above lam[j], from a dense start vector kept orthogonal to the
 // earlier columns, so the replacement lies in the same eigenspace.  ms: >= kMaxRank + 6 kMaxM doubles.
-template <int NT>
-__device__ void mgs_cols(double* Z, int E, int ldz, int r, const double* dg, const double* od,
-                         const double* lam, double* ms) {
+template <int NT, class MP>
+__device__ void mgs_cols(MP Z, int E, int ldz, int r, lds_ptr<const double> dg,
+                         lds_ptr<const double> od, lds_ptr<const double> lam, ldsd ms) {
   const int tid = threadIdx.x;
   const int l16 = tid & 15, g16 = tid >> 4;
   constexpr int NG16 = NT / 16;
-  double* cn = ms;                     // kMaxRank: squared norms of the finished columns
-  double* al = ms + kMaxRank;          // kMaxM: projection coefficients / weights
-  double* lu = al + kMaxM;             // 5 kMaxM: solver scratch
+  ldsd cn = ms;                     // kMaxRank: squared norms of the finished columns
+  ldsd al = ms + kMaxRank;          // kMaxM: projection coefficients / weights
+  ldsd lu = al + kMaxM;             // 5 kMaxM: solver scratch
   double tnrm = 0.0;
   for (int i = 0; i < E; ++i)
     tnrm = fmax(tnrm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0));
@@ -603,8 +605,8 @@ __device__ void mgs_cols(double* Z, int E, int ldz, int r, const double* dg, con
 // Z <- Q Z for the r columns of Z, Q = H_0 H_1 ... H_{E-3} (reflectors in A).
 // A 16-lane group owns columns g, g + NT/16, ...; it applies every reflector
 // to them in turn (no barrier between reflectors).
-template <int NT>
-__device__ void back_transform(const double* A, const double* bt, int E, int lda, double* Z,
+template <int NT, class MP>
+__device__ void back_transform(MP A, lds_ptr<const double> bt, int E, int lda, MP Z,
                                int ldz, int r) {
   const int tid = threadIdx.x;
   const int l16 = tid & 15, g16 = tid >> 4;
@@ -613,7 +615,7 @@ __device__ void back_transform(const double* A, const double* bt, int E, int lda
     const double beta = bt[j];
     if (beta == 0.0) continue;  // uniform
     const int m = E - 1 - j;
-    const double* v = A + (j + 1) * lda + j;  // v[i*lda], rows j+1..
+    const MP v = A + (j + 1) * lda + j;  // v[i*lda], rows j+1..
     for (int c = g16; c < r; c += NG16) {
       double d = 0.0;
       for (int i = l16; i < m; i += 16) d = fma(v[i * lda], Z[(j + 1 + i) * ldz + c], d);
