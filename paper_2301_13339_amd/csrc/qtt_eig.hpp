@@ -81,10 +81,14 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   tt[0] = wall_clock64();
 #endif
   if (finite) {
-    if (BIG && E > 64)
-      sy_tridiag<NT, BIG ? 8 : 4>(A, E, lda, dg, od, bt, pv);
-    else
-      sy_tridiag<NT, 4>(A, E, lda, dg, od, bt, pv);
+    if constexpr (BIG) {
+      if (E > 64)
+        sy_tridiag<NT, 8>(A, E, lda, dg, od, bt, pv);
+      else
+        sy_tridiag64(A, E, lda, dg, od, bt, pv);
+    } else {
+      sy_tridiag64(A, E, lda, dg, od, bt, pv);
+    }
 #ifdef QTT_EIG_TIMING
     tt[1] = wall_clock64();
 #endif
@@ -137,11 +141,23 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   tt[3] = wall_clock64();
 #endif
   // pv .. pv + 7 kMaxM (pv, e2, la and the arrays after) are free now
-  mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
+  if (E <= 64) {
+    // reflectors are rows of A (sy_tridiag64)
+    const bool done = mgs_backtr64(A, bt, E, lda, V, lda, r, pv, iscr + 3);
 #ifdef QTT_EIG_TIMING
-  tt[4] = wall_clock64();
+    tt[4] = wall_clock64();
 #endif
-  back_transform<NT>(A, bt, E, lda, V, lda, r);
+    if (!done) {
+      mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
+      back_transform64(A, bt, E, lda, V, lda, r);
+    }
+  } else {
+    mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
+#ifdef QTT_EIG_TIMING
+    tt[4] = wall_clock64();
+#endif
+    back_transform<NT>(A, bt, E, lda, V, lda, r);
+  }
 #ifdef QTT_EIG_TIMING
   tt[5] = wall_clock64();
   if (tid == 0 && so.dbg) {

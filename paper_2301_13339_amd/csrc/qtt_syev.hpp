@@ -28,11 +28,6 @@ __device__ __forceinline__ double dpp_d(double x) {
   const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
-__device__ __forceinline__ double swz16_d(double x) {
-  const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(x), 0x401F);
-  const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(x), 0x401F);
-  return __hiloint2double(hi, lo);
-}
 // sum over the 16 lanes of a DPP row (all lanes of the row get the sum)
 __device__ __forceinline__ double sum16(double v) {
   v += dpp_d<0xB1>(v);   // quad_perm [1,0,3,2]
@@ -41,21 +36,24 @@ __device__ __forceinline__ double sum16(double v) {
   v += dpp_d<0x140>(v);  // row_mirror
   return v;
 }
+// x[l % 32] + x[l % 32 + 32] in every lane l (the two half waves swap)
+__device__ __forceinline__ double sum_halves(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const auto a = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
+// x + (x of the neighbouring DPP row): rows 0+1 and 2+3 paired
+__device__ __forceinline__ double sum_row_pairs(double x) {
+  const int lo = __double2loint(x), hi = __double2hiint(x);
+  const auto a = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  return __hiloint2double(b[0], a[0]) + __hiloint2double(b[1], a[1]);
+}
 // sum over the 32 lanes of a half wave
-__device__ __forceinline__ double sum32(double v) {
-  const double s = sum16(v);
-  return s + swz16_d(s);
-}
-// sum over the whole wave (uniform result)
-__device__ __forceinline__ double sum64(double v) {
-  v = sum16(v);
-  v += swz16_d(v);
-  const double a = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 0),
-                                    __builtin_amdgcn_readlane(__double2loint(v), 0));
-  const double b = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 32),
-                                    __builtin_amdgcn_readlane(__double2loint(v), 32));
-  return a + b;
-}
+__device__ __forceinline__ double sum32(double v) { return sum_row_pairs(sum16(v)); }
+// sum over the whole wave (every lane gets the sum)
+__device__ __forceinline__ double sum64(double v) { return sum_halves(sum_row_pairs(sum16(v))); }
 
 // 1/x to FP64 accuracy from the hardware estimate (two Newton steps)
 __device__ __forceinline__ double rcp_acc(double x) {
@@ -232,6 +230,275 @@ __device__ void sy_tridiag(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd
   __syncthreads();
 }
 
+// Tridiagonalisation for E <= 64, four waves.  Wave q holds rows
+// 16q..16q+15 of A in registers, lane c column c, so the product A v needs no
+// exchange inside a wave (each wave multiplies its 16 rows; the four partial
+// vectors meet in LDS), and the step loop is unrolled by 16 so that row j,
+// published at step j, is a register with a compile-time index.  Same
+// reflectors as sy_tridiag (H_j = I - beta_j v v^T, v_{j+1} = x0 + sign(x0)
+// alpha); reflector j is stored as row j of A (entries 0..j zero, v in
+// j+1..63), beta_j in bt[j].  A: >= 64 rows allocated, lda >= 64.
+// buf: >= 704 doubles.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+template <class MP>
+__device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd buf) {
+  const int tid = threadIdx.x;
+  const int q = tid >> 6, c = tid & 63;
+  ldsd part = buf + 128;         // 4 x 64: partial A v of each wave
+  ldsd wb = buf + 384 + 64 * q;  // 64 per wave (wave-private): w
+  ldsd last = buf + 576;         // 2 x 64: rows E-2 and E-1 at the end
+  double a[16];
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int r = 16 * q + ii;
+    const double t = A[r * lda + c];  // r, c < 64 <= lda: in bounds
+    a[ii] = (r < E && c < E) ? t : 0.0;
+  }
+  __syncthreads();  // A (LDS) now only receives reflector rows
+  bool done = false;
+  for (int jb = 0; jb < 4 && !done; ++jb) {
+#pragma unroll
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * jb + jj;
+      if (j + 2 >= E) {  // uniform
+        done = true;
+        break;
+      }
+      // the published row is double-buffered: a wave that skips the second
+      // barrier of a step may publish the next row while others still read
+      ldsd colb = buf + 64 * (jj & 1);
+      if (q == jb) colb[c] = a[jj];  // row j = column j
+      __syncthreads();
+      const double col = colb[c];
+      const double x0 = colb[j + 1];
+      const double dj = colb[j];
+      const double t = (c > j + 1) ? col : 0.0;
+      const double xs2 = sum64(t * t);
+      if (xs2 <= 1e-300 + 1e-32 * (xs2 + x0 * x0)) {  // already reduced (uniform)
+        if (tid == 0) {
+          bt[j] = 0.0;
+          od[j] = x0;
+          dg[j] = dj;
+        }
+        continue;
+      }
+      const double alpha = sqrt(xs2 + x0 * x0);
+      const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+      const double v0 = x0 + sg * alpha;
+      const double beta = 2.0 / (xs2 + v0 * v0);
+      const double vc = (c == j + 1) ? v0 : t;
+      // v on the own rows (zero on rows <= j): waves below jb hold no active row
+      double vi[16];
+      double pp = 0.0;
+      if (q >= jb) {
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) vi[ii] = colb[16 * q + ii];
+        if (q == jb) {
+#pragma unroll
+          for (int ii = 0; ii <= jj; ++ii) vi[ii] = 0.0;
+          if (jj < 15) vi[(jj + 1) & 15] = v0;
+        } else if (jj == 15 && q == jb + 1) {
+          vi[0] = v0;
+        }
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 16; ii += 4) {
+          s0 = fma(a[ii], vi[ii], s0);
+          s1 = fma(a[ii + 1], vi[ii + 1], s1);
+          s2 = fma(a[ii + 2], vi[ii + 2], s2);
+          s3 = fma(a[ii + 3], vi[ii + 3], s3);
+        }
+        pp = (s0 + s1) + (s2 + s3);
+      }
+      part[q * 64 + c] = pp;
+      if (q == 3) A[j * lda + c] = vc;  // reflector row j (vc = 0 for c <= j)
+      if (tid == 0) {
+        dg[j] = dj;
+        od[j] = -sg * alpha;
+        bt[j] = beta;
+      }
+      __syncthreads();
+      if (q >= jb) {
+        const double p =
+            beta * ((part[c] + part[64 + c]) + (part[128 + c] + part[192 + c]));
+        const double K = 0.5 * beta * sum64(p * vc);
+        const double w = p - K * vc;
+        wb[c] = w;
+        wave_lds_sync();
+        double wi[16];
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) wi[ii] = wb[16 * q + ii];
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) a[ii] = fma(-vi[ii], w, fma(-wi[ii], vc, a[ii]));
+        wave_lds_sync();  // wb is rewritten next step
+      }
+    }
+  }
+  // trailing 2 x 2 block (rows E-2, E-1)
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int r = 16 * q + ii;
+    if (r >= E - 2 && r < E) last[(r - (E - 2)) * 64 + c] = a[ii];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (E >= 2) {
+      dg[E - 2] = last[E - 2];
+      od[E - 2] = last[64 + E - 2];
+      bt[E - 2] = 0.0;
+    }
+    dg[E - 1] = last[64 + E - 1];
+    bt[E - 1] = 0.0;
+  }
+  __syncthreads();
+}
+
+// Z <- Q Z for the r <= 64 columns of Z, Q = H_0 ... H_{E-3} with reflector
+// j stored as row j of A (sy_tridiag64).  Lane b of wave 0 holds column b in
+// registers and applies every reflector in turn; blocks of 16 entries that
+// lie in the zero part (entries <= j) of a reflector are skipped.
+template <class MP>
+__device__ void back_transform64(MP A, lds_ptr<const double> bt, int E, int lda, MP Z, int ldz,
+                                 int r) {
+  if (threadIdx.x < 64) {
+    const int b = threadIdx.x;
+    double z[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) z[i] = (i < E && b < r) ? Z[i * ldz + b] : 0.0;
+    for (int j = E - 3; j >= 0; --j) {
+      const double beta = bt[j];
+      if (beta == 0.0) continue;  // uniform
+      const MP row = A + j * lda;
+      double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (16 * k + 15 > j) {
+#pragma unroll
+          for (int ii = 0; ii < 16; ii += 4) {
+            d0 = fma(row[16 * k + ii], z[16 * k + ii], d0);
+            d1 = fma(row[16 * k + ii + 1], z[16 * k + ii + 1], d1);
+            d2 = fma(row[16 * k + ii + 2], z[16 * k + ii + 2], d2);
+            d3 = fma(row[16 * k + ii + 3], z[16 * k + ii + 3], d3);
+          }
+        }
+      }
+      const double d = beta * ((d0 + d1) + (d2 + d3));
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        if (16 * k + 15 > j) {
+#pragma unroll
+          for (int ii = 0; ii < 16; ++ii) z[16 * k + ii] = fma(-d, row[16 * k + ii], z[16 * k + ii]);
+        }
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 64; ++i)
+      if (i < E && b < r) Z[i * ldz + b] = z[i];
+  }
+  __syncthreads();
+}
+
+// Modified Gram-Schmidt of the r kept eigenvectors of T (columns 0..r-1 of
+// Z, E <= 64 rows, r <= 64) followed by Z <- Q Z with the reflector rows of
+// sy_tridiag64, all in registers.  Column b lives in wave b / 32: lane b % 32
+// holds rows 0..31 and lane b % 32 + 32 rows 32..63, so a dot product is a
+// per-lane sum plus one swap of the half waves.  Step j normalises column j,
+// publishes it in pub (64 doubles of LDS) and removes it from the later
+// columns.  A column that keeps less than a quarter of its norm (a repeated
+// eigenvalue: the twisted factorisation returned the same vector twice)
+// stops the routine, which then returns false with Z untouched, and the
+// caller takes mgs_cols, whose inverse iteration replaces such columns.
+template <class MP>
+__device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP Z, int ldz, int r,
+                             ldsd pub, ldsi flag) {
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, h = l >> 5;
+  const int b = 32 * w + (l & 31);
+  const bool own = b < r;  // r <= 64: only waves 0 and 1 own columns
+  const int bl = own ? b : 0;
+  double z[32];
+#pragma unroll
+  for (int ii = 0; ii < 32; ++ii) {
+    const int i = 32 * h + ii;
+    const double t = Z[i * ldz + bl];  // i < 64 rows, bl < 64 <= ldz: in bounds
+    z[ii] = (own && i < E) ? t : 0.0;
+  }
+  if (tid == 0) flag[0] = 0;
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    if (w == (j >> 5)) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 32; ii += 4) {
+        s0 = fma(z[ii], z[ii], s0);
+        s1 = fma(z[ii + 1], z[ii + 1], s1);
+        s2 = fma(z[ii + 2], z[ii + 2], s2);
+        s3 = fma(z[ii + 3], z[ii + 3], s3);
+      }
+      const double s = sum_halves((s0 + s1) + (s2 + s3));
+      if ((l & 31) == (j & 31)) {
+        if (j > 0 && !(s >= 0.25)) flag[0] = 1;
+        const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 32; ++ii) {
+          z[ii] *= inv;
+          pub[32 * h + ii] = z[ii];
+        }
+      }
+    }
+    __syncthreads();
+    if (flag[0]) return false;  // uniform
+    double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+    double pj[32];
+#pragma unroll
+    for (int ii = 0; ii < 32; ++ii) pj[ii] = pub[32 * h + ii];
+#pragma unroll
+    for (int ii = 0; ii < 32; ii += 4) {
+      p0 = fma(pj[ii], z[ii], p0);
+      p1 = fma(pj[ii + 1], z[ii + 1], p1);
+      p2 = fma(pj[ii + 2], z[ii + 2], p2);
+      p3 = fma(pj[ii + 3], z[ii + 3], p3);
+    }
+    const double d = sum_halves((p0 + p1) + (p2 + p3));
+    if (own && b > j) {
+#pragma unroll
+      for (int ii = 0; ii < 32; ++ii) z[ii] = fma(-d, pj[ii], z[ii]);
+    }
+    __syncthreads();  // pub is rewritten by the next step
+  }
+  if (w < 2) {
+    for (int j = E - 3; j >= 0; --j) {
+      const double beta = bt[j];
+      if (beta == 0.0) continue;  // uniform
+      double rw[32];
+#pragma unroll
+      for (int ii = 0; ii < 32; ++ii) rw[ii] = A[j * lda + 32 * h + ii];
+      double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 32; ii += 4) {
+        d0 = fma(rw[ii], z[ii], d0);
+        d1 = fma(rw[ii + 1], z[ii + 1], d1);
+        d2 = fma(rw[ii + 2], z[ii + 2], d2);
+        d3 = fma(rw[ii + 3], z[ii + 3], d3);
+      }
+      const double d = beta * sum_halves((d0 + d1) + (d2 + d3));
+#pragma unroll
+      for (int ii = 0; ii < 32; ++ii) z[ii] = fma(-d, rw[ii], z[ii]);
+    }
+#pragma unroll
+    for (int ii = 0; ii < 32; ++ii) {
+      const int i = 32 * h + ii;
+      if (own && i < E) Z[i * ldz + b] = z[ii];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 // Sturm counts (number of eigenvalues below x[t]) for NC shifts at once, on
 // T scaled to ||T|| ~ 1 (diagonal dn, squared off-diagonal e2n).  Three-term
 // recurrence of the leading principal minors
@@ -328,6 +595,36 @@ __device__ void multisect(lds_ptr<const double> dn, lds_ptr<const double> e2n, i
     if (t < nk && l16 == 0) lam[g16 + t * NG16] = 0.5 * (l[t] + u[t]) * scale;
 }
 
+// Multisection for E <= 64 with one quad of lanes per eigenvalue: lanes
+// 4k..4k+3 of the workgroup bracket eigenvalue k (ascending) and narrow the
+// bracket 5x per pass with one Sturm count each.  All brackets start equal
+// and shrink by the same factor, so the pass count is fixed up front.
+template <int NT>
+__device__ void multisect4(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E, double lo,
+                           double hi, double width_stop, double scale, ldsd lam) {
+  static_assert(NT == 256, "64 quads");
+  const int tid = threadIdx.x;
+  const int k = tid >> 2, l4 = tid & 3;
+  const int qshift = tid & 60;  // first lane of the quad within the wave
+  const double frac = (double)(l4 + 1) * 0.2;
+  const int passes = (int)ceil(log((hi - lo) / width_stop) / log(5.0));
+  double l = lo, u = hi;
+  for (int it = 0; it < passes; ++it) {
+    const double x = l + (u - l) * frac;
+    int c;
+    sturm_counts<1>(dn, e2n, E, &x, &c);
+    const unsigned long long bal = __ballot(c > k);
+    const unsigned int qb = (unsigned int)((bal >> qshift) & 0xFull);
+    const int first = qb ? __builtin_ctz(qb) : 4;
+    const double w = (u - l) * 0.2;
+    const double nl = (first == 0) ? l : l + w * (double)first;
+    const double nu = (first == 4) ? u : l + w * (double)(first + 1);
+    l = nl;
+    u = nu;
+  }
+  if (l4 == 0 && k < E) lam[k] = 0.5 * (l + u) * scale;
+}
+
 // All eigenvalues of T in ascending order into lam[0..E), to an absolute
 // accuracy of about 1e-15 ||T||.  e2, dn: >= E doubles of scratch each.
 template <int NT>
@@ -358,7 +655,11 @@ __device__ void tridiag_eigvals(lds_ptr<const double> dg, lds_ptr<const double> 
   const double ws = 1e-15;
   constexpr int NG16 = NT / 16;
   const int nkmax = (E + NG16 - 1) / NG16;
-  if (nkmax <= 1)
+  // (5x per pass: stop at 2e-16, below the 17x scheme's last width, since the
+  // eigenvector error of the twisted factorisation follows the eigenvalue's)
+  if (NT == 256 && E <= 64)
+    multisect4<NT>(dn, e2, E, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
+  else if (nkmax <= 1)
     multisect<NT, 1>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
   else if (nkmax <= 2)
     multisect<NT, 2>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
