@@ -134,7 +134,11 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
     for (int i = 0; i < E; ++i)
       nrm = fmax(nrm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0));
     const double tiny = 1e-300 + 1e-30 * nrm;
-    for (int b = tid; b < r; b += NT) tridiag_vec(dg, od, E, lam[b], V + b, lda, tiny);
+    if (E <= 64 && r <= 32) {
+      if (tid < 64) tridiag_vec_pair(dg, od, E, lam, V, lda, r, tiny);
+    } else {
+      for (int b = tid; b < r; b += NT) tridiag_vec(dg, od, E, lam[b], V + b, lda, tiny);
+    }
   }
   __syncthreads();
 #ifdef QTT_EIG_TIMING

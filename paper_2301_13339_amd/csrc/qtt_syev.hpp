@@ -256,7 +256,7 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
   for (int ii = 0; ii < 16; ++ii) {
     const int r = 16 * q + ii;
     const double t = A[r * lda + c];  // r, c < 64 <= lda: in bounds
-    a[ii] = (r < E && c < E) ? t : 0.0;
+    a[ii] = ((r < E) & (c < E)) ? t : 0.0;  // no && here: a branch would serialise the loads
   }
   __syncthreads();  // A (LDS) now only receives reflector rows
   bool done = false;
@@ -368,7 +368,9 @@ __device__ void back_transform64(MP A, lds_ptr<const double> bt, int E, int lda,
     const int b = threadIdx.x;
     double z[64];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) z[i] = (i < E && b < r) ? Z[i * ldz + b] : 0.0;
+    for (int i = 0; i < 64; ++i) z[i] = Z[i * ldz + b];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) z[i] = (i < E) ? z[i] : 0.0;
     for (int j = E - 3; j >= 0; --j) {
       const double beta = bt[j];
       if (beta == 0.0) continue;  // uniform
@@ -402,96 +404,109 @@ __device__ void back_transform64(MP A, lds_ptr<const double> bt, int E, int lda,
   __syncthreads();
 }
 
+// x summed over the four DPP rows at the same position, in every lane
+__device__ __forceinline__ double sum_rows4(double x) { return sum_halves(sum_row_pairs(x)); }
+
+// 1/sqrt(x) to FP64 accuracy from the hardware estimate (two Newton steps)
+__device__ __forceinline__ double rsq_acc(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 // Modified Gram-Schmidt of the r kept eigenvectors of T (columns 0..r-1 of
 // Z, E <= 64 rows, r <= 64) followed by Z <- Q Z with the reflector rows of
-// sy_tridiag64, all in registers.  Column b lives in wave b / 32: lane b % 32
-// holds rows 0..31 and lane b % 32 + 32 rows 32..63, so a dot product is a
-// per-lane sum plus one swap of the half waves.  Step j normalises column j,
-// publishes it in pub (64 doubles of LDS) and removes it from the later
-// columns.  A column that keeps less than a quarter of its norm (a repeated
-// eigenvalue: the twisted factorisation returned the same vector twice)
-// stops the routine, which then returns false with Z untouched, and the
-// caller takes mgs_cols, whose inverse iteration replaces such columns.
+// sy_tridiag64, all in registers.  Column b lives in wave b / 16, in the
+// lanes at position b % 16 of the four DPP rows, row q holding entries
+// 16q..16q+15; a dot product is a per-lane sum plus two lane swaps.  Step j
+// normalises column j, publishes it in pub (64 doubles of LDS) and removes
+// it from the later columns.  A column that keeps less than a quarter of its
+// norm (a repeated eigenvalue: the twisted factorisation returned the same
+// vector twice) stops the routine, which then returns false with Z
+// untouched, and the caller takes mgs_cols, whose inverse iteration replaces
+// such columns.
 template <class MP>
 __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP Z, int ldz, int r,
                              ldsd pub, ldsi flag) {
   const int tid = threadIdx.x;
-  const int w = tid >> 6, l = tid & 63, h = l >> 5;
-  const int b = 32 * w + (l & 31);
-  const bool own = b < r;  // r <= 64: only waves 0 and 1 own columns
+  const int w = tid >> 6, l = tid & 63, q = l >> 4;
+  const int b = 16 * w + (l & 15);
+  const bool own = b < r;
   const int bl = own ? b : 0;
-  double z[32];
+  double z[16];
 #pragma unroll
-  for (int ii = 0; ii < 32; ++ii) {
-    const int i = 32 * h + ii;
+  for (int ii = 0; ii < 16; ++ii) {
+    const int i = 16 * q + ii;
     const double t = Z[i * ldz + bl];  // i < 64 rows, bl < 64 <= ldz: in bounds
-    z[ii] = (own && i < E) ? t : 0.0;
+    z[ii] = (i < E) ? t : 0.0;         // other lanes' values are never stored
   }
   if (tid == 0) flag[0] = 0;
   __syncthreads();
   for (int j = 0; j < r; ++j) {
-    if (w == (j >> 5)) {
+    if (w == (j >> 4)) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int ii = 0; ii < 32; ii += 4) {
+      for (int ii = 0; ii < 16; ii += 4) {
         s0 = fma(z[ii], z[ii], s0);
         s1 = fma(z[ii + 1], z[ii + 1], s1);
         s2 = fma(z[ii + 2], z[ii + 2], s2);
         s3 = fma(z[ii + 3], z[ii + 3], s3);
       }
-      const double s = sum_halves((s0 + s1) + (s2 + s3));
-      if ((l & 31) == (j & 31)) {
+      const double s = sum_rows4((s0 + s1) + (s2 + s3));
+      if ((l & 15) == (j & 15)) {
         if (j > 0 && !(s >= 0.25)) flag[0] = 1;
-        const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+        const double inv = s > 0.0 ? rsq_acc(s) : 0.0;
 #pragma unroll
-        for (int ii = 0; ii < 32; ++ii) {
+        for (int ii = 0; ii < 16; ++ii) {
           z[ii] *= inv;
-          pub[32 * h + ii] = z[ii];
+          pub[16 * q + ii] = z[ii];
         }
       }
     }
     __syncthreads();
     if (flag[0]) return false;  // uniform
+    double pj[16];
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) pj[ii] = pub[16 * q + ii];
     double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-    double pj[32];
 #pragma unroll
-    for (int ii = 0; ii < 32; ++ii) pj[ii] = pub[32 * h + ii];
-#pragma unroll
-    for (int ii = 0; ii < 32; ii += 4) {
+    for (int ii = 0; ii < 16; ii += 4) {
       p0 = fma(pj[ii], z[ii], p0);
       p1 = fma(pj[ii + 1], z[ii + 1], p1);
       p2 = fma(pj[ii + 2], z[ii + 2], p2);
       p3 = fma(pj[ii + 3], z[ii + 3], p3);
     }
-    const double d = sum_halves((p0 + p1) + (p2 + p3));
+    const double d = sum_rows4((p0 + p1) + (p2 + p3));
     if (own && b > j) {
 #pragma unroll
-      for (int ii = 0; ii < 32; ++ii) z[ii] = fma(-d, pj[ii], z[ii]);
+      for (int ii = 0; ii < 16; ++ii) z[ii] = fma(-d, pj[ii], z[ii]);
     }
     __syncthreads();  // pub is rewritten by the next step
   }
-  if (w < 2) {
+  if (16 * w < r) {
     for (int j = E - 3; j >= 0; --j) {
       const double beta = bt[j];
       if (beta == 0.0) continue;  // uniform
-      double rw[32];
+      double rw[16];
 #pragma unroll
-      for (int ii = 0; ii < 32; ++ii) rw[ii] = A[j * lda + 32 * h + ii];
+      for (int ii = 0; ii < 16; ++ii) rw[ii] = A[j * lda + 16 * q + ii];
       double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
-      for (int ii = 0; ii < 32; ii += 4) {
+      for (int ii = 0; ii < 16; ii += 4) {
         d0 = fma(rw[ii], z[ii], d0);
         d1 = fma(rw[ii + 1], z[ii + 1], d1);
         d2 = fma(rw[ii + 2], z[ii + 2], d2);
         d3 = fma(rw[ii + 3], z[ii + 3], d3);
       }
-      const double d = beta * sum_halves((d0 + d1) + (d2 + d3));
+      const double d = beta * sum_rows4((d0 + d1) + (d2 + d3));
 #pragma unroll
-      for (int ii = 0; ii < 32; ++ii) z[ii] = fma(-d, rw[ii], z[ii]);
+      for (int ii = 0; ii < 16; ++ii) z[ii] = fma(-d, rw[ii], z[ii]);
     }
 #pragma unroll
-    for (int ii = 0; ii < 32; ++ii) {
-      const int i = 32 * h + ii;
+    for (int ii = 0; ii < 16; ++ii) {
+      const int i = 16 * q + ii;
       if (own && i < E) Z[i * ldz + b] = z[ii];
     }
   }
@@ -741,6 +756,105 @@ __device__ inline void tridiag_vec(lds_ptr<const double> dg, lds_ptr<const doubl
   z[r * ldz] = 1.0;
   const double inv = 1.0 / sqrt(nrm2);
   for (int i = 0; i < E; ++i) z[i * ldz] *= inv;
+}
+
+// The same twisted factorisation with two lanes per vector, for r <= 32
+// vectors (wave 0): lane b sweeps top-down (T - lam I = L D+ L^T, l_i into
+// column b of Z) while lane b + 32 sweeps bottom-up (U D- U^T, u_i into
+// column b + 32, free since r <= 32); both run one instruction stream with
+// mirrored indices.  The twist index minimises
+//   |gamma_i| = |(a_i - lam) - l_{i-1} b_{i-1} - u_{i+1} b_i|
+// (ties to the larger index), each lane scanning half of i; then lane b
+// builds the vector upward from it (z_i = -l_i z_{i+1}) and lane b + 32
+// downward (z_i = -u_i z_{i-1}), both into column b, which is normalised.
+template <class MP>
+__device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double> od, int E,
+                                 lds_ptr<const double> lam, MP Z, int ldz, int r, double tiny) {
+  const int l = threadIdx.x & 63;
+  const int b = l & 31, hb = l >> 5;
+  const bool act = b < r;
+  const double lm = lam[act ? b : 0];
+  MP zc = Z + b;
+  MP own = Z + b + 32 * hb;  // where this lane's sweep stores l_i or u_i
+  if (E == 1) {
+    if (act && hb == 0) zc[0] = 1.0;
+    wave_lds_sync();
+    return;
+  }
+  // sweeps: step t handles row i = t (top-down) or i = E-1-t (bottom-up)
+  {
+    const int i0 = hb ? E - 1 : 0;
+    double dcur = dg[i0] - lm;
+    if (fabs(dcur) < tiny) dcur = tiny;
+    for (int t = 0; t + 1 < E; ++t) {
+      const int ie = hb ? E - 2 - t : t;      // off-diagonal entry b_ie
+      const int is = hb ? E - 1 - t : t;      // row of the stored factor
+      const int in = hb ? E - 2 - t : t + 1;  // next diagonal entry
+      const double bo = od[ie];
+      const double x = bo * rcp_acc(dcur);
+      if (act) own[is * ldz] = x;
+      dcur = (dg[in] - lm) - x * bo;
+      if (fabs(dcur) < tiny) dcur = tiny;
+    }
+  }
+  wave_lds_sync();
+  // twist index: lane hb scans i in [lo, hi)
+  int best = -1;
+  double gbest = 0.0;
+  {
+    const int half = (E + 1) / 2;
+    const int lo = hb ? half : 0, hi = hb ? E : half;
+    for (int i = hi - 1; i >= lo; --i) {
+      double g = dg[i] - lm;
+      if (i > 0) g -= (act ? zc[(i - 1) * ldz] : 0.0) * od[i - 1];
+      if (i + 1 < E) g -= (act ? Z[(i + 1) * ldz + b + 32] : 0.0) * od[i];
+      const double ag = fabs(g);
+      if (best < 0 || ag < gbest) {
+        best = i;
+        gbest = ag;
+      }
+    }
+  }
+  {
+    // combine the halves: the upper half wins ties (larger index)
+    const int lo_b = __double2loint(gbest), hi_b = __double2hiint(gbest);
+    const auto sa = __builtin_amdgcn_permlane32_swap(lo_b, lo_b, false, false);
+    const auto sb = __builtin_amdgcn_permlane32_swap(hi_b, hi_b, false, false);
+    const auto si = __builtin_amdgcn_permlane32_swap(best, best, false, false);
+    // element 0: lower half's values, element 1: upper half's, in every lane
+    const double g0 = __hiloint2double(sb[0], sa[0]), g1 = __hiloint2double(sb[1], sa[1]);
+    const int b0 = si[0], b1 = si[1];
+    best = (b1 >= 0 && (b0 < 0 || g1 <= g0)) ? b1 : b0;
+  }
+  const int tw = best;
+  // outward recurrences from the twist: lane hb = 0 up, hb = 1 down
+  double nrm2 = 0.0;
+  {
+    const int steps = hb ? (E - 1 - tw) : tw;
+    const int smax = (tw > E - 1 - tw) ? tw : E - 1 - tw;
+    double zp = 1.0;
+    for (int t = 0; t < smax; ++t) {
+      if (t < steps) {
+        const int i = hb ? tw + 1 + t : tw - 1 - t;
+        const double x = act ? own[i * ldz] : 0.0;
+        zp = -x * zp;
+        if (act) zc[i * ldz] = zp;
+        nrm2 = fma(zp, zp, nrm2);
+      }
+    }
+  }
+  // total squared norm: both halves plus z_tw = 1
+  const double tot = sum_halves(nrm2) + 1.0;
+  wave_lds_sync();
+  if (act && hb == 0) zc[tw * ldz] = 1.0;
+  wave_lds_sync();
+  const double inv = rsq_acc(tot);
+  if (act) {
+    const int half = (E + 1) / 2;
+    const int lo = hb ? half : 0, hi = hb ? E : half;
+    for (int i = lo; i < hi; ++i) zc[i * ldz] *= inv;
+  }
+  wave_lds_sync();
 }
 
 // Solve (T - mu I) y = b in place (b[i*ldb], i < E) by Gaussian elimination
