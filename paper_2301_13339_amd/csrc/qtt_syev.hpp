@@ -421,12 +421,13 @@ __device__ __forceinline__ double rsq_acc(double x) {
 // sy_tridiag64, all in registers.  Column b lives in wave b / 16, in the
 // lanes at position b % 16 of the four DPP rows, row q holding entries
 // 16q..16q+15; a dot product is a per-lane sum plus two lane swaps.  Step j
-// normalises column j, publishes it in pub (64 doubles of LDS) and removes
-// it from the later columns.  A column that keeps less than a quarter of its
+// publishes column j (as it stands, unnormalised) and 1 / ||z_j||^2 in a
+// double-buffered LDS slot (pub: 2 x 72 doubles) and every later column
+// removes its projection on it; one barrier per step.  The columns are
+// normalised at the end.  A column that keeps less than a quarter of its
 // norm (a repeated eigenvalue: the twisted factorisation returned the same
-// vector twice) stops the routine, which then returns false with Z
-// untouched, and the caller takes mgs_cols, whose inverse iteration replaces
-// such columns.
+// vector twice) makes the routine return false with Z untouched, and the
+// caller takes mgs_cols, whose inverse iteration replaces such columns.
 template <class MP>
 __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP Z, int ldz, int r,
                              ldsd pub, ldsi flag) {
@@ -443,9 +444,16 @@ __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP 
     z[ii] = (i < E) ? t : 0.0;         // other lanes' values are never stored
   }
   if (tid == 0) flag[0] = 0;
+  double nz = 1.0;  // squared norm of the own column when it was published
   __syncthreads();
   for (int j = 0; j < r; ++j) {
+    ldsd slot = pub + 72 * (j & 1);
     if (w == (j >> 4)) {
+      const bool pubr = (l & 15) == (j & 15);
+      if (pubr) {
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) slot[16 * q + ii] = z[ii];
+      }
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
       for (int ii = 0; ii < 16; ii += 4) {
@@ -454,22 +462,20 @@ __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP 
         s2 = fma(z[ii + 2], z[ii + 2], s2);
         s3 = fma(z[ii + 3], z[ii + 3], s3);
       }
-      const double s = sum_rows4((s0 + s1) + (s2 + s3));
-      if ((l & 15) == (j & 15)) {
-        if (j > 0 && !(s >= 0.25)) flag[0] = 1;
-        const double inv = s > 0.0 ? rsq_acc(s) : 0.0;
-#pragma unroll
-        for (int ii = 0; ii < 16; ++ii) {
-          z[ii] *= inv;
-          pub[16 * q + ii] = z[ii];
+      const double sn = sum_rows4((s0 + s1) + (s2 + s3));
+      if (pubr) {
+        nz = sn;
+        if (l == (j & 15)) {
+          slot[64] = sn > 0.0 ? rcp_acc(sn) : 0.0;
+          if (j > 0 && !(sn >= 0.25)) flag[0] = 1;
         }
       }
     }
     __syncthreads();
-    if (flag[0]) return false;  // uniform
     double pj[16];
 #pragma unroll
-    for (int ii = 0; ii < 16; ++ii) pj[ii] = pub[16 * q + ii];
+    for (int ii = 0; ii < 16; ++ii) pj[ii] = slot[16 * q + ii];
+    const double is = slot[64];
     double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
 #pragma unroll
     for (int ii = 0; ii < 16; ii += 4) {
@@ -478,20 +484,36 @@ __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP 
       p2 = fma(pj[ii + 2], z[ii + 2], p2);
       p3 = fma(pj[ii + 3], z[ii + 3], p3);
     }
-    const double d = sum_rows4((p0 + p1) + (p2 + p3));
-    if (own && b > j) {
+    // no branch around the update: the compiler would sink the load of is
+    // into it and serialise a second LDS round trip
+    const double d = (own && b > j) ? sum_rows4((p0 + p1) + (p2 + p3)) * is : 0.0;
 #pragma unroll
-      for (int ii = 0; ii < 16; ++ii) z[ii] = fma(-d, pj[ii], z[ii]);
-    }
-    __syncthreads();  // pub is rewritten by the next step
+    for (int ii = 0; ii < 16; ++ii) z[ii] = fma(-d, pj[ii], z[ii]);
   }
-  if (16 * w < r) {
+  __syncthreads();
+  if (flag[0]) return false;  // uniform; Z was not written
+  {
+    const double inv = nz > 0.0 ? rsq_acc(nz) : 0.0;
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) z[ii] *= inv;
+  }
+  if (16 * w < r && E >= 3) {
+    // reflectors E-3 .. 0; the next row and beta are loaded a step ahead
+    double rn[16];
+    double bn = bt[E - 3];
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) rn[ii] = A[(E - 3) * lda + 16 * q + ii];
     for (int j = E - 3; j >= 0; --j) {
-      const double beta = bt[j];
-      if (beta == 0.0) continue;  // uniform
       double rw[16];
 #pragma unroll
-      for (int ii = 0; ii < 16; ++ii) rw[ii] = A[j * lda + 16 * q + ii];
+      for (int ii = 0; ii < 16; ++ii) rw[ii] = rn[ii];
+      const double beta = bn;
+      if (j > 0) {
+        bn = bt[j - 1];
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) rn[ii] = A[(j - 1) * lda + 16 * q + ii];
+      }
+      if (beta == 0.0) continue;  // uniform
       double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
       for (int ii = 0; ii < 16; ii += 4) {
@@ -504,6 +526,8 @@ __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP 
 #pragma unroll
       for (int ii = 0; ii < 16; ++ii) z[ii] = fma(-d, rw[ii], z[ii]);
     }
+  }
+  if (16 * w < r) {
 #pragma unroll
     for (int ii = 0; ii < 16; ++ii) {
       const int i = 16 * q + ii;
