@@ -385,6 +385,115 @@ __global__ void __launch_bounds__(256) k_project_gram(const T* Ain, double B, in
   }
 }
 
+// The same projection and partial Gram on the FP64 matrix cores.  A stage
+// of 32 rows: A (32 x WA) is staged in LDS k-major, Y = A U is formed by
+// 16 x 16 blocks (wave w: row block w & 1, column blocks w >> 1, (w >> 1) + 2,
+// ...), written to Xout and kept in LDS, and the Gram of the next remainder
+// (Y read as 16 x 2r) accumulates in registers, 16 x 16 blocks of the
+// 2r x 2r result spread round-robin over the waves.  RB: bound on r (16, 32
+// or 64).  v_mfma_f64_16x16x4f64: A entry (row l % 16, k l / 16), B entry
+// (k l / 16, column l % 16), result D[4i + l / 16][l % 16] in element i.
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, int GEN, int RB>
+__global__ void __launch_bounds__(256) k_project_mfma(const T* Ain, double B, int nk,
+                                                      long long rowsA, int wa_fixed,
+                                                      const int32_t* ranks, int kin,
+                                                      const double* U, T* Xout, int do_gram,
+                                                      double* partials, int pstride,
+                                                      int mstride) {
+  constexpr int SR = 32, LT = SR + 1;
+  constexpr int NCB = RB / 16;          // column blocks of Y
+  constexpr int MB = 2 * RB / 16;       // blocks per side of the Gram
+  constexpr int GPW = (MB * MB + 3) / 4;  // Gram blocks per wave
+  extern __shared__ double smem[];
+  const int WA = wa_fixed > 0 ? wa_fixed : 2 * ranks[kin - 1];
+  const int r = ranks[kin];
+  const int M = 2 * r;
+  double* Us = smem;              // WA x r
+  double* At = Us + WA * r;       // WA x LT (k-major)
+  double* Ys = At + WA * LT;      // SR x r
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  for (int e = tid; e < WA * r; e += 256) Us[e] = U[e];
+  f64x4 g[GPW];
+#pragma unroll
+  for (int t = 0; t < GPW; ++t) g[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const long long nstage = (rowsA + SR - 1) / SR;
+  for (long long sidx = blockIdx.x; sidx < nstage; sidx += gridDim.x) {
+    const long long r0 = sidx * SR;
+    const int nr = (int)((rowsA - r0) < SR ? (rowsA - r0) : SR);
+    __syncthreads();  // At, Ys of the previous stage consumed (Us written)
+    for (int e = tid; e < SR * WA; e += 256) {
+      const int row = e / WA, c = e - row * WA;
+      At[c * LT + row] = row < nr ? sample<T, GEN>(Ain, (r0 + row) * WA + c, B, nk) : 0.0;
+    }
+    __syncthreads();
+    // Y = A U
+    {
+      const int rb = w & 1;
+#pragma unroll
+      for (int cc = 0; cc < NCB; ++cc) {
+        const int cb = (w >> 1) + 2 * cc;
+        if (cb >= NCB || 16 * cb >= r) continue;  // wave-uniform
+        f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+        const int col = 16 * cb + lr;
+        const bool cin = col < r;
+        for (int k0 = 0; k0 < WA; k0 += 4) {
+          const int kk = k0 + lk;
+          const double a = kk < WA ? At[kk * LT + 16 * rb + lr] : 0.0;
+          const double bv = (kk < WA && cin) ? Us[kk * r + col] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int row = 16 * rb + 4 * i + lk;
+          if (row < nr && cin) {
+            Ys[row * r + col] = acc[i];
+            Xout[(r0 + row) * r + col] = (T)acc[i];
+          }
+        }
+      }
+    }
+    if (do_gram) {
+      __syncthreads();
+      // rows of Y beyond nr hold values of an earlier stage: only pairs
+      // p < nr / 2 take part
+      const int np = nr >> 1;
+#pragma unroll
+      for (int t = 0; t < GPW; ++t) {
+        const int blk = w + 4 * t;
+        if (blk >= MB * MB) break;
+        const int bi = blk / MB, bj = blk - bi * MB;
+        if (16 * bi >= M || 16 * bj >= M) continue;  // wave-uniform
+        const int mi = 16 * bi + lr, nj = 16 * bj + lr;
+#pragma unroll
+        for (int k0 = 0; k0 < SR / 2; k0 += 4) {
+          const int pk = k0 + lk;
+          const bool pin = pk < np;
+          const double a = (pin && mi < M) ? Ys[2 * pk * r + mi] : 0.0;
+          const double bv = (pin && nj < M) ? Ys[2 * pk * r + nj] : 0.0;
+          g[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, g[t], 0, 0, 0);
+        }
+      }
+    }
+  }
+  if (do_gram) {
+    double* P = partials + (size_t)blockIdx.x * pstride;
+#pragma unroll
+    for (int t = 0; t < GPW; ++t) {
+      const int blk = w + 4 * t;
+      if (blk >= MB * MB) break;
+      const int bi = blk / MB, bj = blk - bi * MB;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int row = 16 * bi + 4 * i + lk, col = 16 * bj + lr;
+        if (row < M && col < M) P[row * mstride + col] = g[t][i];
+      }
+    }
+  }
+}
+
 // --------------------------------------------------------------- eig step
 // Step k from the Gram already in A (M x M, stride lda), M = 2 r_{k-1}: the
 // truncated eigendecomposition, core k, and U_k (M x r_k, row-major) in umat.
@@ -833,6 +942,9 @@ static size_t lds_tail() {
 static size_t lds_project(int wa, int r) {
   return sizeof(double) * ((size_t)wa * r + 32 * (size_t)wa + 32 * (size_t)r);
 }
+static size_t lds_project_mfma(int wa, int r) {
+  return sizeof(double) * ((size_t)wa * r + 33 * (size_t)wa + 32 * (size_t)r);
+}
 
 int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p) {
   DecompPlan& P = *p;
@@ -914,6 +1026,18 @@ static void set_attrs() {
                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   hipFuncSetAttribute((const void*)k_project_gram<T, 0, 8>,
                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_mfma<T, GEN, 16>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_mfma<T, GEN, 32>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_mfma<T, GEN, 64>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_mfma<T, 0, 16>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_mfma<T, 0, 32>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipFuncSetAttribute((const void*)k_project_mfma<T, 0, 64>,
+                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
 }
 
 template <typename T, int GEN>
@@ -926,9 +1050,26 @@ static int launch_project(const T* Ain, const Source& src, long long rowsA, int 
   int blocks = (int)(nstage < kMaxPartials ? nstage : kMaxPartials);
   if (blocks < 1) blocks = 1;
   *nparts = blocks;
-  const size_t lds = lds_project(wa_cap, rcap_out);
   const int Mc = 2 * rcap_out;
   ProbeScope _ps(QTT_K_PROJECT, stream);
+  if (rcap_out <= kMaxRank) {
+    const size_t lm = lds_project_mfma(wa_cap, rcap_out);
+    if (rcap_out <= 16)
+      k_project_mfma<T, GEN, 16><<<blocks, 256, lm, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
+                                                              ranks, kin, U, Xout, do_gram,
+                                                              P.partials, P.pstride, mstride);
+    else if (rcap_out <= 32)
+      k_project_mfma<T, GEN, 32><<<blocks, 256, lm, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
+                                                              ranks, kin, U, Xout, do_gram,
+                                                              P.partials, P.pstride, mstride);
+    else
+      k_project_mfma<T, GEN, 64><<<blocks, 256, lm, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
+                                                              ranks, kin, U, Xout, do_gram,
+                                                              P.partials, P.pstride, mstride);
+    QTT_LAUNCH_CHECK();
+    return QTT_OK;
+  }
+  const size_t lds = lds_project(wa_cap, rcap_out);
   if (Mc <= 16) {
     k_project_gram<T, GEN, 1><<<blocks, 256, lds, stream>>>(Ain, src.B, src.nk, rowsA, wa_fixed,
                                                             ranks, kin, U, Xout, do_gram,
