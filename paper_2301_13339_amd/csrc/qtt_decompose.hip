@@ -178,8 +178,17 @@ __global__ void __launch_bounds__(256) k_reduce(const double* partials, int pstr
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + el;
   double s = 0.0;
-  if (e < count)
-    for (int b = g; b < nparts; b += 4) s += partials[(size_t)b * pstride + e];
+  if (e < count) {
+    // eight independent loads in flight per thread, summed in a fixed order
+    int b = g;
+    for (; b + 28 < nparts; b += 32) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = partials[(size_t)(b + 4 * u) * pstride + e];
+      s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+    }
+    for (; b < nparts; b += 4) s += partials[(size_t)b * pstride + e];
+  }
   red[g][el] = s;
   __syncthreads();
   if (g == 0 && e < count) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);

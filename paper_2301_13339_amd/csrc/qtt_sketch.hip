@@ -156,8 +156,16 @@ __global__ void k_sum_partials(const double* partials, int pstride, int nparts,
   const int count = m * m + m * ell;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
+  // eight independent loads in flight, summed in a fixed order
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += partials[(size_t)b * pstride + e];
+  int b = 0;
+  for (; b + 7 < nparts; b += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = partials[(size_t)(b + u) * pstride + e];
+    s += ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+  }
+  for (; b < nparts; ++b) s += partials[(size_t)b * pstride + e];
   out[e] = s;
 }
 
