@@ -31,6 +31,35 @@ __device__ inline int truncation_rank_dev(lds_ptr<const double> lam, int E, doub
   return r < cap ? r : cap;
 }
 
+// The same rule run by one wave: the eigenvalues are loaded into lanes
+// (lam[i] in lane i % 64, register i / 64) and read back one at a time in the
+// order of truncation_rank_dev, so the sums round identically.  E <= 128.
+__device__ inline int truncation_rank_wave(lds_ptr<const double> lam, int E, double tau2, int cap,
+                                           int* over) {
+  const int l = threadIdx.x & 63;
+  const double v0 = (l < E) ? lam[l] : 0.0;
+  const double v1 = (l + 64 < E) ? lam[l + 64] : 0.0;
+  double tail = 0.0;
+  int r = E;
+  for (int i = E - 1; i >= 1; --i) {
+    const double x = (i < 64) ? v0 : v1;
+    const int src = i & 63;
+    const double li = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), src),
+                                       __builtin_amdgcn_readlane(__double2loint(x), src));
+    const double lc = li > 0.0 ? li : 0.0;
+    const double t2 = tail + lc;
+    if (t2 <= tau2) {
+      tail = t2;
+      r = i;
+    } else {
+      break;
+    }
+  }
+  if (r < 1) r = 1;
+  *over = r > cap;
+  return r < cap ? r : cap;
+}
+
 // ----------------------------------------------------- step bookkeeping
 // capacities and core offsets, passed by value to the kernels
 struct Meta {
@@ -51,6 +80,7 @@ struct StepOut {
 // lam[0..E) = eigenvalues in non-increasing order, perm[b] = b.  sx: scratch
 // of kEigScratch doubles.  Returns r.  Must be called by all threads.
 constexpr int kEigScratch = 10 * kMaxM + 16;
+constexpr int kEigNrmSlot = 10 * kMaxM;  // sx[kEigNrmSlot]: Gershgorin bound of T
 // one workgroup of 4 waves: a barrier costs ~40 cycles with 4 waves and
 // ~470 with 16 on gfx950, and every eigen step is barrier/latency bound
 constexpr int kEigThreads = 256;
@@ -68,11 +98,12 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   ldsd la = e2 + kMaxM;  // ascending eigenvalues
   // the tridiagonalisation takes pv .. pv + 4 kMaxM (over e2 and la, which are
   // used only after it) for its column and p buffers
-  // finiteness of the Gram (NaN/Inf input)
-  if (tid == 0) {
+  // finiteness of the Gram (NaN/Inf input): its trace, by wave 0
+  if (tid < 64) {
     double tr = 0.0;
-    for (int i = 0; i < E; ++i) tr += A[i * lda + i];
-    iscr[1] = isfinite(tr) ? 1 : 0;
+    for (int i = tid; i < E; i += 64) tr += A[i * lda + i];
+    tr = sum64(tr);
+    if (tid == 0) iscr[1] = isfinite(tr) ? 1 : 0;
   }
   __syncthreads();
   const int finite = iscr[1];
@@ -80,6 +111,7 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   long long tt[6];
   tt[0] = wall_clock64();
 #endif
+  double tnrm = 0.0;  // Gershgorin bound of T
   if (finite) {
     if constexpr (BIG) {
       if (E > 64)
@@ -92,7 +124,8 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
 #ifdef QTT_EIG_TIMING
     tt[1] = wall_clock64();
 #endif
-    tridiag_eigvals<NT>(dg, od, E, la, e2, pv);
+    tnrm = tridiag_gersh(dg, od, E, sx + kEigNrmSlot);
+    tridiag_eigvals<NT>(dg, od, E, la, e2, pv, tnrm);
   }
 #ifdef QTT_EIG_TIMING
   tt[2] = wall_clock64();
@@ -102,14 +135,16 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
     perm[i] = i;
   }
   __syncthreads();
-  if (tid == 0) {
+  if (tid < 64) {
     int over = 0;
-    const int r = truncation_rank_dev(lam, E, tau2, cap, &over);
-    iscr[2] = r;
-    so.ranks[k] = r;
-    if (so.status) {
-      if (!finite) atomicOr(so.status, QTT_STATUS_NONFINITE);
-      if (over && so.lib_capped) atomicOr(so.status, QTT_STATUS_RANKCAP);
+    const int r = truncation_rank_wave(lam, E, tau2, cap, &over);
+    if (tid == 0) {
+      iscr[2] = r;
+      so.ranks[k] = r;
+      if (so.status) {
+        if (!finite) atomicOr(so.status, QTT_STATUS_NONFINITE);
+        if (over && so.lib_capped) atomicOr(so.status, QTT_STATUS_RANKCAP);
+      }
     }
   }
   if (so.sv) {
@@ -130,10 +165,7 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   }
   // eigenvectors of T for the kept eigenvalues, one lane per vector
   {
-    double nrm = 0.0;
-    for (int i = 0; i < E; ++i)
-      nrm = fmax(nrm, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0));
-    const double tiny = 1e-300 + 1e-30 * nrm;
+    const double tiny = 1e-300 + 1e-30 * tnrm;
     if (E <= 64 && r <= 32) {
       if (tid < 64) tridiag_vec_pair(dg, od, E, lam, V, lda, r, tiny);
     } else {

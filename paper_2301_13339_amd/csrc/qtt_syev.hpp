@@ -55,6 +55,39 @@ __device__ __forceinline__ double sum32(double v) { return sum_row_pairs(sum16(v
 // sum over the whole wave (every lane gets the sum)
 __device__ __forceinline__ double sum64(double v) { return sum_halves(sum_row_pairs(sum16(v))); }
 
+// max over the whole wave of non-negative values (every lane gets it)
+__device__ __forceinline__ double max64(double v) {
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const auto a16 = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto b16 = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    v = fmax(__hiloint2double(b16[0], a16[0]), __hiloint2double(b16[1], a16[1]));
+  }
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  const auto a32 = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto b32 = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  return fmax(__hiloint2double(b32[0], a32[0]), __hiloint2double(b32[1], a32[1]));
+}
+
+// Gershgorin bound max_i |a_i| + |b_{i-1}| + |b_i| of the tridiagonal T,
+// by wave 0 and handed to every thread through slot (one double of LDS).
+__device__ inline double tridiag_gersh(lds_ptr<const double> dg, lds_ptr<const double> od, int E,
+                                       ldsd slot) {
+  if (threadIdx.x < 64) {
+    double m = 0.0;
+    for (int i = threadIdx.x; i < E; i += 64)
+      m = fmax(m, fabs(dg[i]) + (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0));
+    m = max64(m);
+    if (threadIdx.x == 0) slot[0] = m;
+  }
+  __syncthreads();
+  return slot[0];
+}
+
 // 1/x to FP64 accuracy from the hardware estimate (two Newton steps)
 __device__ __forceinline__ double rcp_acc(double x) {
   double y = __builtin_amdgcn_rcp(x);
@@ -668,14 +701,9 @@ __device__ void multisect4(lds_ptr<const double> dn, lds_ptr<const double> e2n, 
 // accuracy of about 1e-15 ||T||.  e2, dn: >= E doubles of scratch each.
 template <int NT>
 __device__ void tridiag_eigvals(lds_ptr<const double> dg, lds_ptr<const double> od, int E, ldsd lam,
-                                ldsd e2, ldsd dn) {
+                                ldsd e2, ldsd dn, double nrm) {
+  // nrm: the Gershgorin bound of T (tridiag_gersh)
   const int tid = threadIdx.x;
-  // Gershgorin scale (every thread)
-  double nrm = 0.0;
-  for (int i = 0; i < E; ++i) {
-    const double r = (i > 0 ? fabs(od[i - 1]) : 0.0) + (i + 1 < E ? fabs(od[i]) : 0.0);
-    nrm = fmax(nrm, fabs(dg[i]) + r);
-  }
   if (!(nrm > 0.0)) {
     for (int i = tid; i < E; i += NT) lam[i] = 0.0;
     __syncthreads();
