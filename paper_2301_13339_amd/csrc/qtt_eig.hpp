@@ -60,6 +60,27 @@ __device__ inline int truncation_rank_wave(lds_ptr<const double> lam, int E, dou
   return r < cap ? r : cap;
 }
 
+// The rule when only the K = cap largest eigenvalues are known (K < E): the
+// tail sums are trace(G) - lam_0 - ... - lam_{r-1}, r = 1..K; when none is
+// within tau2 the eps-rank exceeds cap.  One wave; lam[i] in lane i.
+__device__ inline int truncation_rank_top(lds_ptr<const double> lam, int K, double trace,
+                                          double tau2, int cap, int* over) {
+  const int l = threadIdx.x & 63;
+  const double v = (l < K) ? lam[l] : 0.0;
+  double head = 0.0;
+  int r = K + 1;
+  for (int i = 0; i < K; ++i) {
+    head += __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), i),
+                             __builtin_amdgcn_readlane(__double2loint(v), i));
+    if (trace - head <= tau2) {
+      r = i + 1;
+      break;
+    }
+  }
+  *over = r > cap;
+  return r < cap ? r : cap;
+}
+
 // ----------------------------------------------------- step bookkeeping
 // capacities and core offsets, passed by value to the kernels
 struct Meta {
@@ -103,7 +124,10 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
     double tr = 0.0;
     for (int i = tid; i < E; i += 64) tr += A[i * lda + i];
     tr = sum64(tr);
-    if (tid == 0) iscr[1] = isfinite(tr) ? 1 : 0;
+    if (tid == 0) {
+      iscr[1] = isfinite(tr) ? 1 : 0;
+      sx[kEigNrmSlot + 1] = tr;
+    }
   }
   __syncthreads();
   const int finite = iscr[1];
@@ -112,6 +136,10 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   tt[0] = wall_clock64();
 #endif
   double tnrm = 0.0;  // Gershgorin bound of T
+  // eigenvalues computed: all when the singular values are reported, the cap
+  // does not bind or the tolerance is zero, else the cap largest (the rank
+  // rule then works from the trace)
+  const int K = (so.sv || cap >= E || !(tau2 > 0.0)) ? E : cap;
   if (finite) {
     if constexpr (BIG) {
       if (E > 64)
@@ -125,19 +153,20 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
     tt[1] = wall_clock64();
 #endif
     tnrm = tridiag_gersh(dg, od, E, sx + kEigNrmSlot);
-    tridiag_eigvals<NT>(dg, od, E, la, e2, pv, tnrm);
+    tridiag_eigvals<NT>(dg, od, E, la, e2, pv, tnrm, K);
   }
 #ifdef QTT_EIG_TIMING
   tt[2] = wall_clock64();
 #endif
   for (int i = tid; i < E; i += NT) {
-    lam[i] = finite ? la[E - 1 - i] : 0.0;
+    lam[i] = (finite && i < K) ? la[E - 1 - i] : 0.0;
     perm[i] = i;
   }
   __syncthreads();
   if (tid < 64) {
     int over = 0;
-    const int r = truncation_rank_wave(lam, E, tau2, cap, &over);
+    const int r = (K < E) ? truncation_rank_top(lam, K, sx[kEigNrmSlot + 1], tau2, cap, &over)
+                          : truncation_rank_wave(lam, E, tau2, cap, &over);
     if (tid == 0) {
       iscr[2] = r;
       so.ranks[k] = r;

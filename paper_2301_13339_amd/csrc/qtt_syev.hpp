@@ -667,42 +667,45 @@ __device__ void multisect(lds_ptr<const double> dn, lds_ptr<const double> e2n, i
     if (t < nk && l16 == 0) lam[g16 + t * NG16] = 0.5 * (l[t] + u[t]) * scale;
 }
 
-// Multisection for E <= 64 with one quad of lanes per eigenvalue: lanes
-// 4k..4k+3 of the workgroup bracket eigenvalue k (ascending) and narrow the
-// bracket 5x per pass with one Sturm count each.  All brackets start equal
-// and shrink by the same factor, so the pass count is fixed up front.
-template <int NT>
-__device__ void multisect4(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E, double lo,
-                           double hi, double width_stop, double scale, ldsd lam) {
-  static_assert(NT == 256, "64 quads");
+// Multisection for the K largest eigenvalues (K <= 256 / G) with a group of
+// G lanes per eigenvalue: group g brackets eigenvalue E-1-g (ascending
+// index) and narrows its bracket (G+1)x per pass with one Sturm count per
+// lane.  All brackets start equal and shrink by the same factor, so the pass
+// count is fixed up front.
+template <int NT, int G>
+__device__ void multisect_top(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E, int K,
+                              double lo, double hi, double width_stop, double scale, ldsd lam) {
+  static_assert(NT == 256 && (G == 4 || G == 8 || G == 16), "lane groups of a 256-thread block");
   const int tid = threadIdx.x;
-  const int k = tid >> 2, l4 = tid & 3;
-  const int qshift = tid & 60;  // first lane of the quad within the wave
-  const double frac = (double)(l4 + 1) * 0.2;
-  const int passes = (int)ceil(log((hi - lo) / width_stop) / log(5.0));
+  const int grp = tid / G, lg = tid & (G - 1);
+  const int k = E - 1 - grp;
+  const int gshift = (tid & 63) & ~(G - 1);  // first lane of the group within the wave
+  const double frac = (double)(lg + 1) * (1.0 / (double)(G + 1));
+  const int passes = (int)ceil(log((hi - lo) / width_stop) / log((double)(G + 1)));
   double l = lo, u = hi;
   for (int it = 0; it < passes; ++it) {
     const double x = l + (u - l) * frac;
     int c;
     sturm_counts<1>(dn, e2n, E, &x, &c);
     const unsigned long long bal = __ballot(c > k);
-    const unsigned int qb = (unsigned int)((bal >> qshift) & 0xFull);
-    const int first = qb ? __builtin_ctz(qb) : 4;
-    const double w = (u - l) * 0.2;
+    const unsigned int gb = (unsigned int)((bal >> gshift) & ((1ull << G) - 1));
+    const int first = gb ? __builtin_ctz(gb) : G;
+    const double w = (u - l) * (1.0 / (double)(G + 1));
     const double nl = (first == 0) ? l : l + w * (double)first;
-    const double nu = (first == 4) ? u : l + w * (double)(first + 1);
+    const double nu = (first == G) ? u : l + w * (double)(first + 1);
     l = nl;
     u = nu;
   }
-  if (l4 == 0 && k < E) lam[k] = 0.5 * (l + u) * scale;
+  if (lg == 0 && grp < K && k >= 0) lam[k] = 0.5 * (l + u) * scale;
 }
 
 // All eigenvalues of T in ascending order into lam[0..E), to an absolute
 // accuracy of about 1e-15 ||T||.  e2, dn: >= E doubles of scratch each.
 template <int NT>
 __device__ void tridiag_eigvals(lds_ptr<const double> dg, lds_ptr<const double> od, int E, ldsd lam,
-                                ldsd e2, ldsd dn, double nrm) {
-  // nrm: the Gershgorin bound of T (tridiag_gersh)
+                                ldsd e2, ldsd dn, double nrm, int K) {
+  // nrm: the Gershgorin bound of T (tridiag_gersh); for E <= 64 only the K
+  // largest eigenvalues are computed (lam[E-K..E)), otherwise all
   const int tid = threadIdx.x;
   if (!(nrm > 0.0)) {
     for (int i = tid; i < E; i += NT) lam[i] = 0.0;
@@ -724,9 +727,16 @@ __device__ void tridiag_eigvals(lds_ptr<const double> dg, lds_ptr<const double> 
   const int nkmax = (E + NG16 - 1) / NG16;
   // (5x per pass: stop at 2e-16, below the 17x scheme's last width, since the
   // eigenvector error of the twisted factorisation follows the eigenvalue's)
-  if (NT == 256 && E <= 64)
-    multisect4<NT>(dn, e2, E, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
-  else if (nkmax <= 1)
+  if (NT == 256 && E <= 64) {
+    // only the K largest (ascending slots E-K..E-1 of lam); finer groups
+    // when fewer are wanted, fewer passes
+    if (K <= 16)
+      multisect_top<NT, 16>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
+    else if (K <= 32)
+      multisect_top<NT, 8>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
+    else
+      multisect_top<NT, 4>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
+  } else if (nkmax <= 1)
     multisect<NT, 1>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
   else if (nkmax <= 2)
     multisect<NT, 2>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
