@@ -581,6 +581,51 @@ __global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, in
   eig_step_solve_at<T>(L, M, k, scal[1], cap_k, cores, off_k, umat, so);
 }
 
+// ------------------------------------------------------ small LDS products
+// C (M x N) = A (M x K) B (K x N) with all operands in LDS: A(i, k) =
+// A[i*ai + k*ak], B(k, j) = B[k*bk + j*bj].  The 256 threads form a 16 x 16
+// grid and each keeps a 4 x 4 tile of C in registers (64 x 64 per pass over
+// the grid), so every pair of loads feeds four FMAs and the sixteen
+// accumulators are independent.  store(i, j, v) receives the results.
+template <class F>
+__device__ __forceinline__ void lds_gemm(int M, int N, int K, lds_ptr<const double> A, int ai,
+                                         int ak, lds_ptr<const double> B, int bk, int bj,
+                                         F store) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  for (int i0 = 0; i0 < M; i0 += 64)
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      const int ib = i0 + 4 * ty, jb = j0 + 4 * tx;
+      if (ib >= M || jb >= N) continue;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+      int ia[4], jc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) ia[a] = (ib + a < M ? ib + a : M - 1) * ai;  // clamped rows: in bounds, results unused
+#pragma unroll
+      for (int c = 0; c < 4; ++c) jc[c] = (jb + c < N ? jb + c : N - 1) * bj;
+#pragma unroll 2
+      for (int k = 0; k < K; ++k) {
+        double xa[4], xb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) xa[a] = A[ia[a] + k * ak];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xb[c] = B[k * bk + jc[c]];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[a][c] = fma(xa[a], xb[c], acc[a][c]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (ib + a < M && jb + c < N) store(ib + a, jb + c, acc[a][c]);
+    }
+}
+
 // -------------------------------------------------------------------- tail
 // Finish the sweep from step k0 in one workgroup.  X_{k0} (n x m) comes from
 // Xin (k0 > 1) or from the samples (k0 == 1, m = 2).  With k0 == 1 the norm
@@ -643,77 +688,105 @@ __device__ void tail_steps(double* smem, const T* Xin, double B, int nk, int k0,
     tau2 = scal[1];
     __syncthreads();
   }
-  constexpr int kPer = kTailElems / NT;  // remainder entries per thread
   for (int k = k0; k <= D - 1; ++k) {
+#ifdef QTT_EIG_TIMING
+    const long long ts0 = wall_clock64();
+#endif
     const bool dual = n < m;
     const int E = dual ? n : m;
     // Gram (primal X^T X or dual X X^T)
-    for (int e = tid; e < E * E; e += NT) {
-      const int i = e / E, j = e - i * E;
-      double s = 0.0;
-      if (!dual) {
-        for (int b = 0; b < n; ++b) s = fma(X[b * m + i], X[b * m + j], s);
-      } else {
-        for (int c = 0; c < m; ++c) s = fma(X[i * m + c], X[j * m + c], s);
-      }
-      A[i * LDA + j] = s;
+    {
+      ldsd Al = lds(A);
+      auto st = [&](int i, int j, double v) { Al[i * LDA + j] = v; };
+      if (!dual)
+        lds_gemm(E, E, n, lds<const double>(X), 1, m, lds<const double>(X), m, 1, st);
+      else
+        lds_gemm(E, E, m, lds<const double>(X), m, 1, lds<const double>(X), 1, m, st);
     }
     __syncthreads();
+#ifdef QTT_EIG_TIMING
+    const long long ts1 = wall_clock64();
+#endif
     const int r =
         solve_and_truncate<NT>(lds(A), lds(V), E, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
                                tau2, meta.caps[k], k, so);
+#ifdef QTT_EIG_TIMING
+    const long long ts2 = wall_clock64();
+#endif
     const long long off = meta.offs[k - 1];
     const int total = rp * 2 * r;
-    double yv[kPer];
+    // U has the kept eigenvectors in its first r columns (perm is the identity)
     if (!dual) {
       for (int e = tid; e < total; e += NT) {
         const int b = e % r, ai = e / r;
         const int i = ai & 1, a = ai >> 1;
-        cores[off + e] = (T)V[(a + rp * i) * LDA + perm[b]];
-      }
-      // Y = X U (n x r), held in registers until every thread has read X
-#pragma unroll
-      for (int j = 0; j < kPer; ++j) {
-        const int e = tid + j * NT;
-        double s = 0.0;
-        if (e < n * r) {
-          const int row = e / r, b = e - row * r;
-          const int col = perm[b];
-          for (int c = 0; c < m; ++c) s = fma(X[row * m + c], V[c * LDA + col], s);
-        }
-        yv[j] = s;
+        cores[off + e] = (T)V[(a + rp * i) * LDA + b];
       }
     } else {
-      // U[:, b] = X^T v_b / sigma_b, Y[:, b] = sigma_b v_b
-      for (int e = tid; e < total; e += NT) {
-        const int b = e % r, ai = e / r;
-        const int i = ai & 1, a = ai >> 1;
-        const int c = a + rp * i;
-        const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
-        double s = 0.0;
-        for (int row = 0; row < n; ++row) s = fma(X[row * m + c], V[row * LDA + perm[b]], s);
-        cores[off + e] = (T)(sg > 1e-300 ? s / sg : 0.0);
+      // U[:, b] = X^T v_b / sigma_b
+      lds_gemm(m, r, n, lds<const double>(X), 1, m, lds<const double>(V), LDA, 1,
+               [&](int c, int b, double v) {
+                 const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
+                 const int i = c / rp, a = c - i * rp;
+                 cores[off + (long long)(a * 2 + i) * r + b] = (T)(sg > 1e-300 ? v / sg : 0.0);
+               });
+    }
+    if (n * r <= LDA * LDA) {
+      // Y (n x r, dense) into A, which the solve no longer needs
+      ldsd Yl = lds(A);
+      if (!dual) {
+        lds_gemm(n, r, m, lds<const double>(X), m, 1, lds<const double>(V), LDA, 1,
+                 [&](int row, int b, double v) { Yl[row * r + b] = v; });
+      } else {
+        for (int e = tid; e < n * r; e += NT) {
+          const int row = e / r, b = e - row * r;
+          const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
+          Yl[e] = sg * V[row * LDA + b];
+        }
       }
+      __syncthreads();
+      // next remainder: Y (n x r) read as (n/2) x (2r)
+      for (int e = tid; e < n * r; e += NT) X[e] = Yl[e];
+    } else {
+      // long thin remainders (few columns): Y in registers until every
+      // thread has read X
+      constexpr int kPer = kTailElems / NT;
+      double yv[kPer];
 #pragma unroll
       for (int j = 0; j < kPer; ++j) {
         const int e = tid + j * NT;
-        double s = 0.0;
+        double sv = 0.0;
         if (e < n * r) {
           const int row = e / r, b = e - row * r;
-          const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
-          s = sg * V[row * LDA + perm[b]];
+          if (!dual) {
+            for (int c = 0; c < m; ++c) sv = fma(X[row * m + c], V[c * LDA + b], sv);
+          } else {
+            const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
+            sv = sg * V[row * LDA + b];
+          }
         }
-        yv[j] = s;
+        yv[j] = sv;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int j = 0; j < kPer; ++j) {
+        const int e = tid + j * NT;
+        if (e < n * r) X[e] = yv[j];
       }
     }
     __syncthreads();
-    // next remainder: Y (n x r) read as (n/2) x (2r)
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-      const int e = tid + j * NT;
-      if (e < n * r) X[e] = yv[j];
+#ifdef QTT_EIG_TIMING
+    const long long ts3 = wall_clock64();
+#endif
+#ifdef QTT_EIG_TIMING
+    if (tid == 0 && so.dbg) {
+      const long long ts4 = wall_clock64();
+      so.dbg[300 + 4 * k] = (int)(ts1 - ts0);
+      so.dbg[301 + 4 * k] = (int)(ts2 - ts1);
+      so.dbg[302 + 4 * k] = (int)(ts3 - ts2);
+      so.dbg[303 + 4 * k] = (int)(ts4 - ts3);
     }
-    __syncthreads();
+#endif
     n >>= 1;
     rp = r;
     m = 2 * r;
