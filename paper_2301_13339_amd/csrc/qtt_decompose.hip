@@ -199,6 +199,51 @@ __global__ void __launch_bounds__(256) k_reduce(const double* partials, int pstr
   }
 }
 
+// ------------------------------------------------------ small LDS products
+// C (M x N) = A (M x K) B (K x N) with all operands in LDS: A(i, k) =
+// A[i*ai + k*ak], B(k, j) = B[k*bk + j*bj].  The 256 threads form a 16 x 16
+// grid and each keeps a 4 x 4 tile of C in registers (64 x 64 per pass over
+// the grid), so every pair of loads feeds four FMAs and the sixteen
+// accumulators are independent.  store(i, j, v) receives the results.
+template <class F>
+__device__ __forceinline__ void lds_gemm(int M, int N, int K, lds_ptr<const double> A, int ai,
+                                         int ak, lds_ptr<const double> B, int bk, int bj,
+                                         F store) {
+  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
+  for (int i0 = 0; i0 < M; i0 += 64)
+    for (int j0 = 0; j0 < N; j0 += 64) {
+      const int ib = i0 + 4 * ty, jb = j0 + 4 * tx;
+      if (ib >= M || jb >= N) continue;
+      double acc[4][4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
+      int ia[4], jc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) ia[a] = (ib + a < M ? ib + a : M - 1) * ai;  // clamped rows: in bounds, results unused
+#pragma unroll
+      for (int c = 0; c < 4; ++c) jc[c] = (jb + c < N ? jb + c : N - 1) * bj;
+#pragma unroll 2
+      for (int k = 0; k < K; ++k) {
+        double xa[4], xb[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) xa[a] = A[ia[a] + k * ak];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xb[c] = B[k * bk + jc[c]];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int c = 0; c < 4; ++c) acc[a][c] = fma(xa[a], xb[c], acc[a][c]);
+      }
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+          if (ib + a < M && jb + c < N) store(ib + a, jb + c, acc[a][c]);
+    }
+}
+
 // ------------------------------------------------------------- level eig
 // Steps 1..L from the Gram GZ (64 x 64, at the start of smem) of the samples
 // viewed as (N/64) x 64.  Writes cores 1..L, ranks 0..L, tau^2 (scal[1]) and
@@ -233,28 +278,30 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
   for (int k = 1; k <= L; ++k) {
     const int w = 1 << k, half = w >> 1;
     const int m = 2 * rp;
-    // T1 = G_k P_k  (w x m); G_k[c][c'] = sum_h GZ[c + h w][c' + h w]
+    // G_k[c][c'] = sum_h GZ[c + h w][c' + h w]  (w x w, into V before the solve)
     const int reps = W / w;
-    for (int e = tid; e < w * m; e += NT) {
-      const int c = e / m, col = e - c * m;
-      const int i = col / rp, a = col - i * rp;
-      double s = 0.0;
-      for (int cl = 0; cl < half; ++cl) {
-        const int cc = cl + half * i;
-        double g = 0.0;
-        for (int h = 0; h < reps; ++h) g += GZ[(c + h * w) * W + cc + h * w];
-        s = fma(g, Phi[cl * 32 + a], s);
-      }
-      T1[c * m + col] = s;
+    for (int e = tid; e < w * w; e += NT) {
+      const int c = e / w, c2 = e - c * w;
+      double g = 0.0;
+      for (int h = 0; h < reps; ++h) g += GZ[(c + h * w) * W + c2 + h * w];
+      V[c * LDA + c2] = g;
     }
     __syncthreads();
-    // A = P_k^T T1  (m x m)
-    for (int e = tid; e < m * m; e += NT) {
-      const int row = e / m, col = e - row * m;
-      const int i = row / rp, a = row - i * rp;
-      double s = 0.0;
-      for (int cl = 0; cl < half; ++cl) s = fma(Phi[cl * 32 + a], T1[(cl + half * i) * m + col], s);
-      A[row * LDA + col] = s;
+    // T1 = G_k P_k (w x m): P_k[cl + half i][i' rp + a] = [i == i'] Phi[cl][a],
+    // so column block i of T1 is G_k[:, half i .. half i + half) Phi
+    {
+      ldsd T1l = lds(T1);
+      for (int i = 0; i < 2; ++i)
+        lds_gemm(w, rp, half, lds<const double>(V + half * i), LDA, 1, lds<const double>(Phi), 32, 1,
+                 [&](int c, int a, double v) { T1l[c * m + i * rp + a] = v; });
+    }
+    __syncthreads();
+    // A = P_k^T T1 (m x m): row block i is Phi^T T1[half i .. half i + half, :]
+    {
+      ldsd Al = lds(A);
+      for (int i = 0; i < 2; ++i)
+        lds_gemm(rp, m, half, lds<const double>(Phi), 1, 32, lds<const double>(T1 + half * i * m), m,
+                 1, [&](int a, int col, double v) { Al[(i * rp + a) * LDA + col] = v; });
     }
     __syncthreads();
     const int r =
@@ -269,13 +316,13 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
         cores[meta.offs[k - 1] + e] = (T)V[(a + rp * i) * LDA + perm[b]];
       }
     }
-    // Phi_k = P_k U_k  (w x r) into T1
-    for (int e = tid; e < w * r; e += NT) {
-      const int c = e / r, b = e - c * r;
-      const int i = c / half, cl = c - i * half;
-      double s = 0.0;
-      for (int a = 0; a < rp; ++a) s = fma(Phi[cl * 32 + a], V[(a + rp * i) * LDA + perm[b]], s);
-      T1[c * r + b] = s;
+    // Phi_k = P_k U_k (w x r) into T1: row block i is Phi U[rp i .. rp i + rp, :]
+    // (perm is the identity)
+    {
+      ldsd T1l = lds(T1);
+      for (int i = 0; i < 2; ++i)
+        lds_gemm(half, r, rp, lds<const double>(Phi), 32, 1, lds<const double>(V + rp * i * LDA), LDA,
+                 1, [&](int cl, int b, double v) { T1l[(cl + half * i) * r + b] = v; });
     }
     __syncthreads();
     if (k < L) {
@@ -579,51 +626,6 @@ __global__ void __launch_bounds__(kEigThreads) k_eig_step(const double* gram, in
   }
   __syncthreads();
   eig_step_solve_at<T>(L, M, k, scal[1], cap_k, cores, off_k, umat, so);
-}
-
-// ------------------------------------------------------ small LDS products
-// C (M x N) = A (M x K) B (K x N) with all operands in LDS: A(i, k) =
-// A[i*ai + k*ak], B(k, j) = B[k*bk + j*bj].  The 256 threads form a 16 x 16
-// grid and each keeps a 4 x 4 tile of C in registers (64 x 64 per pass over
-// the grid), so every pair of loads feeds four FMAs and the sixteen
-// accumulators are independent.  store(i, j, v) receives the results.
-template <class F>
-__device__ __forceinline__ void lds_gemm(int M, int N, int K, lds_ptr<const double> A, int ai,
-                                         int ak, lds_ptr<const double> B, int bk, int bj,
-                                         F store) {
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  for (int i0 = 0; i0 < M; i0 += 64)
-    for (int j0 = 0; j0 < N; j0 += 64) {
-      const int ib = i0 + 4 * ty, jb = j0 + 4 * tx;
-      if (ib >= M || jb >= N) continue;
-      double acc[4][4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-      int ia[4], jc[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) ia[a] = (ib + a < M ? ib + a : M - 1) * ai;  // clamped rows: in bounds, results unused
-#pragma unroll
-      for (int c = 0; c < 4; ++c) jc[c] = (jb + c < N ? jb + c : N - 1) * bj;
-#pragma unroll 2
-      for (int k = 0; k < K; ++k) {
-        double xa[4], xb[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) xa[a] = A[ia[a] + k * ak];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) xb[c] = B[k * bk + jc[c]];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[a][c] = fma(xa[a], xb[c], acc[a][c]);
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (ib + a < M && jb + c < N) store(ib + a, jb + c, acc[a][c]);
-    }
 }
 
 // -------------------------------------------------------------------- tail
