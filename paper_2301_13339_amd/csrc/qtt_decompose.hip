@@ -276,6 +276,9 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
   }
   int rp = 1;  // r_{k-1}
   for (int k = 1; k <= L; ++k) {
+#ifdef QTT_EIG_TIMING
+    const long long ls0 = wall_clock64();
+#endif
     const int w = 1 << k, half = w >> 1;
     const int m = 2 * rp;
     // G_k[c][c'] = sum_h GZ[c + h w][c' + h w]  (w x w, into V before the solve)
@@ -304,9 +307,15 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
                  1, [&](int a, int col, double v) { Al[(i * rp + a) * LDA + col] = v; });
     }
     __syncthreads();
+#ifdef QTT_EIG_TIMING
+    const long long ls1 = wall_clock64();
+#endif
     const int r =
         solve_and_truncate<NT>(lds(A), lds(V), m, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
                                tau2, meta.caps[k], k, so);
+#ifdef QTT_EIG_TIMING
+    const long long ls2 = wall_clock64();
+#endif
     // core k = V[:, perm[:r]]
     {
       const int total = rp * 2 * r;
@@ -334,6 +343,14 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
       for (int e = tid; e < w * r; e += NT) umat[e] = T1[e];
     }
     __syncthreads();
+#ifdef QTT_EIG_TIMING
+    if (tid == 0 && so.dbg) {
+      const long long ls3 = wall_clock64();
+      so.dbg[400 + 3 * k] = (int)(ls1 - ls0);
+      so.dbg[401 + 3 * k] = (int)(ls2 - ls1);
+      so.dbg[402 + 3 * k] = (int)(ls3 - ls2);
+    }
+#endif
     rp = r;
   }
 }
