@@ -96,6 +96,15 @@ __device__ __forceinline__ double rcp_acc(double x) {
   return y;
 }
 
+// 1/sqrt(x) to FP64 accuracy from the hardware estimate (two Newton steps)
+__device__ __forceinline__ double rsq_acc(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+
 // ------------------------------------------------------- tridiagonalisation
 // A (E x E symmetric, full storage, stride lda >= 16*BS, at least 16*BS
 // rows allocated, E <= 16*BS) -> T (dg, od)
@@ -319,10 +328,13 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
         }
         continue;
       }
-      const double alpha = sqrt(xs2 + x0 * x0);
+      // sqrt and division from the hardware estimates with Newton steps: on
+      // the critical path of every step
+      const double s2 = xs2 + x0 * x0;
+      const double alpha = s2 * rsq_acc(s2);
       const double sg = x0 >= 0.0 ? 1.0 : -1.0;
       const double v0 = x0 + sg * alpha;
-      const double beta = 2.0 / (xs2 + v0 * v0);
+      const double beta = 2.0 * rcp_acc(xs2 + v0 * v0);
       const double vc = (c == j + 1) ? v0 : t;
       // v on the own rows (zero on rows <= j): waves below jb hold no active row
       double vi[16];
@@ -440,14 +452,6 @@ __device__ void back_transform64(MP A, lds_ptr<const double> bt, int E, int lda,
 // x summed over the four DPP rows at the same position, in every lane
 __device__ __forceinline__ double sum_rows4(double x) { return sum_halves(sum_row_pairs(x)); }
 
-// 1/sqrt(x) to FP64 accuracy from the hardware estimate (two Newton steps)
-__device__ __forceinline__ double rsq_acc(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double hx = 0.5 * x;
-  y = y * fma(-hx * y, y, 1.5);
-  y = y * fma(-hx * y, y, 1.5);
-  return y;
-}
 
 // Modified Gram-Schmidt of the r kept eigenvectors of T (columns 0..r-1 of
 // Z, E <= 64 rows, r <= 64) followed by Z <- Q Z with the reflector rows of
@@ -579,8 +583,9 @@ __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP 
 // p_{i+1} = -b_i^2 p_{i-1} has the sign opposite to p_{i-1}, so the pair of
 // steps contributes one change whatever sign the zero is given.  Division-
 // free: one FMA on the dependent path per step.  The pair (p_i, p_{i-1}) is
-// rescaled by a power of two every 4 steps; with |a - x| <= 3 and b^2 in
-// [1e-60, 1] it stays within the double range.
+// rescaled by a power of two every 8 steps; with |a - x| <= 3 and b^2 in
+// [1e-60, 1] it grows at most 4^8-fold and shrinks at most 1e-240-fold in
+// between, within the normal double range.
 __device__ __forceinline__ int sign_change(double a, double b) {
   return (int)(((unsigned int)(__double2hiint(a) ^ __double2hiint(b))) >> 31);
 }
@@ -605,13 +610,15 @@ __device__ __forceinline__ void sturm_counts(lds_ptr<const double> dn, lds_ptr<c
     }
   };
   int i = 1;
-  for (; i + 3 < E; i += 4) {
-    const double a0 = dn[i], a1 = dn[i + 1], a2 = dn[i + 2], a3 = dn[i + 3];
-    const double b0 = e2n[i - 1], b1 = e2n[i], b2 = e2n[i + 1], b3 = e2n[i + 2];
-    step(a0, b0);
-    step(a1, b1);
-    step(a2, b2);
-    step(a3, b3);
+  for (; i + 7 < E; i += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      av[u] = dn[i + u];
+      bv[u] = e2n[i - 1 + u];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) step(av[u], bv[u]);
 #pragma unroll
     for (int t = 0; t < NC; ++t) {
       const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pc[t]), fabs(pm[t])));
