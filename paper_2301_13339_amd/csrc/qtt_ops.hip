@@ -240,16 +240,19 @@ __global__ void __launch_bounds__(256) k_chain_gemm(const T* A, const T* B, T* C
 // FP64 chain product on the matrix cores.  v_mfma_f64_16x16x4f64 takes one
 // A entry per lane (row l % 16, k = l / 16), one B entry (k = l / 16,
 // column l % 16) and leaves D[4i + l / 16][l % 16] in accumulator i.  A
-// workgroup of four waves owns a 64 x 64 tile of C, each wave a 32 x 32
-// quarter as 2 x 2 blocks of 16 x 16; the A and B panels of 16 k-values
+// workgroup of four waves owns a tile of C (32 x 32: one 16 x 16 block per
+// wave, which keeps several workgroups per compute unit for the narrow
+// chains of Full); the A and B panels of 16 k-values
 // pass through LDS (stored k-major, so the fragment reads of a wave are 16
 // consecutive doubles per k).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int MODE>
+template <int MODE, int SZ>
 __global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const double* B, double* C,
                                                     const int32_t* ranks, int k, int Mh, int Nh) {
-  constexpr int TM = 64, TN = 64, TK = 16, LD = 64 + 4;
+  // SZ x SZ tile per workgroup; each wave an (SZ/2) x (SZ/2) quarter made of
+  // NB x NB blocks of 16 x 16
+  constexpr int TK = 16, LD = SZ + 4, NB = SZ / 32, PA = SZ / 16;
   __shared__ double As[2][TK][LD];
   __shared__ double Bs[2][TK][LD];
   int M, N, K, rk = 0;
@@ -267,41 +270,41 @@ __global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const doubl
     K = ranks[k];
     N = Nh;
   }
-  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
+  const int row0 = blockIdx.y * SZ, col0 = blockIdx.x * SZ;
   if (row0 >= M || col0 >= N) return;
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
-  const int wr = (w >> 1) * 32, wc = (w & 1) * 32;
-  // global -> LDS assignment: A panel 64 rows x 16 k (4 consecutive k per
-  // thread), B panel 16 k x 64 columns (4 consecutive columns per thread)
-  const int am = tid >> 2, ak = (tid & 3) * 4;
-  const int bk = tid >> 4, bn = (tid & 15) * 4;
-  double ra[4], rb[4];
+  const int wr = (w >> 1) * (SZ / 2), wc = (w & 1) * (SZ / 2);
+  // global -> LDS assignment: A panel SZ rows x 16 k (PA consecutive k per
+  // thread), B panel 16 k x SZ columns (PA consecutive columns per thread)
+  const int am = tid / (16 / PA), ak = (tid % (16 / PA)) * PA;
+  const int bk = tid >> 4, bn = (tid & 15) * PA;
+  double ra[PA], rb[PA];
   auto load = [&](int k0) {
     const int gr = row0 + am;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < PA; ++t) {
       const int gk = k0 + ak + t;
       ra[t] = (gr < M && gk < K) ? A[(long long)gr * K + gk] : 0.0;
     }
     const int gk = k0 + bk;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
+    for (int t = 0; t < PA; ++t) {
       const int gc = col0 + bn + t;
       rb[t] = (gk < K && gc < N) ? B[(long long)gk * N + gc] : 0.0;
     }
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) As[buf][ak + t][am] = ra[t];
+    for (int t = 0; t < PA; ++t) As[buf][ak + t][am] = ra[t];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) Bs[buf][bk][bn + t] = rb[t];
+    for (int t = 0; t < PA; ++t) Bs[buf][bk][bn + t] = rb[t];
   };
-  f64x4 acc[2][2];
+  f64x4 acc[NB][NB];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int nk = (K + TK - 1) / TK;
   load(0);
   store(0);
@@ -312,24 +315,24 @@ __global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const doubl
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (l >> 4);
-      double fa[2], fb[2];
+      double fa[NB], fb[NB];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = As[cur][kr][wr + 16 * i + (l & 15)];
+      for (int i = 0; i < NB; ++i) fa[i] = As[cur][kr][wr + 16 * i + (l & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) fb[j] = Bs[cur][kr][wc + 16 * j + (l & 15)];
+      for (int j = 0; j < NB; ++j) fb[j] = Bs[cur][kr][wc + 16 * j + (l & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < NB; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
     }
     if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int gr = row0 + wr + 16 * i + 4 * e + (l >> 4);
@@ -410,11 +413,12 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     T* dst = static_cast<T*>(bufs[li]);
     const int Mh = 1 << (k - 1);
     const int Ncap = 2 * cap[k];
-    dim3 grid((Ncap + 63) / 64, (Mh + 63) / 64);
+    const int ts = sizeof(T) == 8 ? 32 : 64;  // tile of the FP64 matrix-core kernel / vector kernel
+    dim3 grid((Ncap + ts - 1) / ts, (Mh + ts - 1) / ts);
     {
       ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
       if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_LEFT><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst, t.ranks,
+        k_chain_mfma<GEMM_LEFT, 32><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst, t.ranks,
                                                           k, Mh, 0);
       else
         k_chain_gemm<T, GEMM_LEFT><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst,
@@ -431,11 +435,12 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     T* dst = static_cast<T*>(bufs[ri]);
     const int Nh = 1 << (d - k);
     const int Mcap = 2 * cap[k - 1];
-    dim3 grid((Nh + 63) / 64, (Mcap + 63) / 64);
+    const int ts = sizeof(T) == 8 ? 32 : 64;
+    dim3 grid((Nh + ts - 1) / ts, (Mcap + ts - 1) / ts);
     {
       ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
       if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_RIGHT><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst, t.ranks,
+        k_chain_mfma<GEMM_RIGHT, 32><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst, t.ranks,
                                                            k, 0, Nh);
       else
         k_chain_gemm<T, GEMM_RIGHT><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst,
@@ -447,11 +452,12 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
   }
   {
     const int Mh = 1 << m, Nh = 1 << (d - m);
-    dim3 grid((Nh + 63) / 64, (Mh + 63) / 64);
+    const int ts = sizeof(T) == 8 ? 32 : 64;
+    dim3 grid((Nh + ts - 1) / ts, (Mh + ts - 1) / ts);
     {
       ProbeScope _ps(QTT_K_FULL_FINAL, stream);
       if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_FINAL><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
+        k_chain_mfma<GEMM_FINAL, 32><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
       else
         k_chain_gemm<T, GEMM_FINAL><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
     }
