@@ -855,6 +855,7 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
     const int i0 = hb ? E - 1 : 0;
     double dcur = dg[i0] - lm;
     if (fabs(dcur) < tiny) dcur = tiny;
+#pragma unroll 4
     for (int t = 0; t + 1 < E; ++t) {
       const int ie = hb ? E - 2 - t : t;      // off-diagonal entry b_ie
       const int is = hb ? E - 1 - t : t;      // row of the stored factor
@@ -873,6 +874,7 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
   {
     const int half = (E + 1) / 2;
     const int lo = hb ? half : 0, hi = hb ? E : half;
+#pragma unroll 4
     for (int i = hi - 1; i >= lo; --i) {
       double g = dg[i] - lm;
       if (i > 0) g -= (act ? zc[(i - 1) * ldz] : 0.0) * od[i - 1];
@@ -902,6 +904,7 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
     const int steps = hb ? (E - 1 - tw) : tw;
     const int smax = (tw > E - 1 - tw) ? tw : E - 1 - tw;
     double zp = 1.0;
+#pragma unroll 4
     for (int t = 0; t < smax; ++t) {
       if (t < steps) {
         const int i = hb ? tw + 1 + t : tw - 1 - t;
@@ -921,6 +924,7 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
   if (act) {
     const int half = (E + 1) / 2;
     const int lo = hb ? half : 0, hi = hb ? E : half;
+#pragma unroll 4
     for (int i = lo; i < hi; ++i) zc[i * ldz] *= inv;
   }
   wave_lds_sync();
