@@ -71,6 +71,9 @@ __global__ void __launch_bounds__(256) k_gram_sketch(const T* X, long long n, co
                                                      int pstride) {
   extern __shared__ double smem[];
   const int m = (kin == 0) ? 2 : 2 * ranks[kin];
+  // with ell >= m the range finder spans all of R^m whatever Omega is (the
+  // step is the exact SVD): only the Gram is formed
+  if (m <= ell) ell = 0;
   double* Xs = smem;                                     // kSkSR x m
   float* Os = reinterpret_cast<float*>(Xs + kSkSR * m);  // kSkSR x ell
   const int tid = threadIdx.x;
@@ -153,7 +156,7 @@ __global__ void __launch_bounds__(256) k_gram_sketch(const T* X, long long n, co
 __global__ void k_sum_partials(const double* partials, int pstride, int nparts,
                                const int32_t* ranks, int kin, int ell, double* out) {
   const int m = (kin == 0) ? 2 : 2 * ranks[kin];
-  const int count = m * m + m * ell;
+  const int count = m * m + (m > ell ? m * ell : 0);
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= count) return;
   // eight independent loads in flight, summed in a fixed order
@@ -202,15 +205,25 @@ __global__ void __launch_bounds__(kEigThreads) k_sketch_step(
     scal[1] = (D > 1) ? eps * eps * nrm2 / (double)(D - 1) : 0.0;
     so.ranks[0] = 1;
   }
-  for (int e = tid; e < m * el; e += NT) {
-    const int i = e / el, j = e - i * el;
-    Qs[i * LQ + j] = Yg[i * ell + j];
+  // ell >= m: the range of Y is all of R^m (Q square), so H = Q^T G Q is
+  // similar to G and U = Q U~ are G's eigenvectors: the exact step on G
+  const bool full = el == m;
+  if (!full) {
+    for (int e = tid; e < m * el; e += NT) {
+      const int i = e / el, j = e - i * el;
+      Qs[i * LQ + j] = Yg[i * ell + j];
+    }
+  } else {
+    for (int e = tid; e < m * m; e += NT) {
+      const int i = e / m, j = e - i * m;
+      A[i * LDA + j] = G[e];
+    }
   }
   __threadfence();
   __syncthreads();
   const double tau2 = scal[1];
   // Householder QR of Y (m x el); reflector j overwrites column j (rows j..)
-  for (int j = 0; j < el; ++j) {
+  for (int j = 0; !full && j < el; ++j) {
     double xs = 0.0;
     for (int i = j + (tid & 63); i < m; i += 64) xs = fma(Qs[i * LQ + j], Qs[i * LQ + j], xs);
     xs = sum64(xs);
@@ -238,7 +251,7 @@ __global__ void __launch_bounds__(kEigThreads) k_sketch_step(
     __syncthreads();
   }
   // Q = H_0 ... H_{el-1} [I; 0], formed in place from the last reflector
-  for (int j = el - 1; j >= 0; --j) {
+  for (int j = el - 1; !full && j >= 0; --j) {
     const double beta = bt[j];
     for (int c = j + 1 + g16; c < el; c += NG16) {
       double d = 0.0;
@@ -263,7 +276,7 @@ __global__ void __launch_bounds__(kEigThreads) k_sketch_step(
     __syncthreads();
   }
   // T1 = G Q (m x el) into gT, then H = Q^T T1 (el x el) into A
-  for (int e = tid; e < m * el; e += NT) {
+  for (int e = tid; !full && e < m * el; e += NT) {
     const int i = e / el, b = e - i * el;
     double s = 0.0;
     for (int j2 = 0; j2 < m; ++j2) s = fma(G[i * m + j2], Qs[j2 * LQ + b], s);
@@ -271,7 +284,7 @@ __global__ void __launch_bounds__(kEigThreads) k_sketch_step(
   }
   __threadfence();
   __syncthreads();
-  for (int e = tid; e < el * el; e += NT) {
+  for (int e = tid; !full && e < el * el; e += NT) {
     const int a = e / el, b = e - a * el;
     double s = 0.0;
     for (int i = 0; i < m; ++i) s = fma(Qs[i * LQ + a], gT[i * el + b], s);
@@ -294,7 +307,11 @@ __global__ void __launch_bounds__(kEigThreads) k_sketch_step(
   for (int e = tid; e < m * r; e += NT) {
     const int i = e / r, b = e - i * r;
     double s = 0.0;
-    for (int a = 0; a < el; ++a) s = fma(Qs[i * LQ + a], V[a * LDA + b], s);
+    if (full) {
+      s = V[i * LDA + b];
+    } else {
+      for (int a = 0; a < el; ++a) s = fma(Qs[i * LQ + a], V[a * LDA + b], s);
+    }
     umat[e] = s;
     // core k: (a, i, b) <- U[a + rp*i][b]
     const int ii = i / rp, aa = i - ii * rp;
