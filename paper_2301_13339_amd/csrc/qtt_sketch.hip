@@ -152,6 +152,44 @@ __global__ void __launch_bounds__(256) k_gram_sketch(const T* X, long long n, co
   }
 }
 
+// The Gram alone for narrow remainders (m <= 16, and m <= ell so that no
+// sketch is needed): thread t accumulates entry (i, j) of G over the rows
+// g, g + Gr, ... of each 2048-value stage (g = t / m^2, Gr = 256 / m^2 row
+// groups), so all threads work however small m is; the groups are summed in
+// a fixed order at the end.
+template <typename T>
+__global__ void __launch_bounds__(256) k_gram_small(const T* X, long long n, const int32_t* ranks,
+                                                    int kin, double* partials, int pstride) {
+  constexpr int SV = 2048;
+  __shared__ double Xs[SV];
+  __shared__ double red[256];
+  const int m = (kin == 0) ? 2 : 2 * ranks[kin];
+  const int m2 = m * m, Gr = 256 / m2;
+  const int tid = threadIdx.x, g = tid / m2, e = tid - g * m2, i = e / m, j = e - i * m;
+  const bool act = g < Gr;
+  const int SRs = SV / m;  // rows per stage
+  const long long nstage = (n + SRs - 1) / SRs;
+  double acc = 0.0;
+  for (long long sidx = blockIdx.x; sidx < nstage; sidx += gridDim.x) {
+    const long long r0 = sidx * SRs;
+    const int nr = (int)((n - r0) < SRs ? (n - r0) : SRs);
+    __syncthreads();
+    for (int q = tid; q < nr * m; q += 256) Xs[q] = (double)X[r0 * m + q];
+    __syncthreads();
+    if (act) {
+#pragma unroll 4
+      for (int rr = g; rr < nr; rr += Gr) acc = fma(Xs[rr * m + i], Xs[rr * m + j], acc);
+    }
+  }
+  red[tid] = act ? acc : 0.0;
+  __syncthreads();
+  if (tid < m2) {
+    double sum = 0.0;
+    for (int gg = 0; gg < Gr; ++gg) sum += red[gg * m2 + tid];
+    partials[(size_t)blockIdx.x * pstride + tid] = sum;  // entry i*m + j
+  }
+}
+
 // out[e] = sum over the partials of entry e (fixed order)
 __global__ void k_sum_partials(const double* partials, int pstride, int nparts,
                                const int32_t* ranks, int kin, int ell, double* out) {
@@ -422,7 +460,13 @@ static int sketch_t(const T* y, int D, double eps, const int* cap, int ell, uint
     const int blocks = (int)(nstage < kMaxPartials ? nstage : kMaxPartials);
     const size_t lds = sizeof(double) * kSkSR * mcap + sizeof(float) * kSkSR * ell;
     const int kin = k - 1;  // ranks index of r_{k-1}; 0 -> m = 2
-    if (mcap <= 16)
+    int nparts = blocks;
+    if (mcap <= 16 && mcap <= ell) {
+      // narrow and exact: the Gram alone, in 2048-value stages
+      const long long ns2 = (n * mcap + 2047) / 2048;
+      nparts = (int)(ns2 < kMaxPartials ? ns2 : kMaxPartials);
+      k_gram_small<T><<<nparts, 256, 0, s>>>(X, n, out.ranks, kin, p.partials, p.pstride);
+    } else if (mcap <= 16)
       k_gram_sketch<T, BF, 1><<<blocks, 256, lds, s>>>(X, n, out.ranks, kin, ell, k0, k1, k,
                                                        p.partials, p.pstride);
     else if (mcap <= 32)
@@ -436,7 +480,7 @@ static int sketch_t(const T* y, int D, double eps, const int* cap, int ell, uint
                                                        p.partials, p.pstride);
     QTT_LAUNCH_CHECK();
     const int cnt = mcap * mcap + mcap * ell;
-    k_sum_partials<<<(cnt + 255) / 256, 256, 0, s>>>(p.partials, p.pstride, blocks, out.ranks,
+    k_sum_partials<<<(cnt + 255) / 256, 256, 0, s>>>(p.partials, p.pstride, nparts, out.ranks,
                                                      kin, ell, p.gy);
     QTT_LAUNCH_CHECK();
     // 2. QR, small eigenproblem, core k
