@@ -218,6 +218,7 @@ __global__ void __launch_bounds__(64) k_batch_toep(const T* wcores, const int32_
   const T* W = wcores + ln.w_core;
   double* S0 = sm;
   double* S1 = sm + 2 * wcap * pmax;
+  double* Ws = S1 + 2 * wcap * pmax;  // the core of the current step (rin x 2 x rout)
   // this workgroup takes kToepPerWG consecutive values of the other d - cb bits
   const long long nout = 1LL << (d - cb);
   const long long o_beg = ((long long)blockIdx.x - wg0[l]) * kToepPerWG;
@@ -246,7 +247,12 @@ __global__ void __launch_bounds__(64) k_batch_toep(const T* wcores, const int32_
     const int k = b0 + j + 1;  // 1-based bit
     const int rin = (k == 1) ? 1 : wr[k - 1];
     const int rout = wr[k];
-    const T* Wk = W + core_off_dev(d + 1, wcap, k - 1);
+    {
+      // the core once into LDS: every work item reads all of it
+      const T* Wk = W + core_off_dev(d + 1, wcap, k - 1);
+      for (int e = lane; e < rin * 2 * rout; e += 64) Ws[e] = (double)Wk[e];
+      __syncthreads();
+    }
     const int half = 1 << j;
     const int npair = P >> 1;
     const int ngroup = (2 * rout + 7) >> 3;
@@ -262,8 +268,8 @@ __global__ void __launch_bounds__(64) k_batch_toep(const T* wcores, const int32_
 #pragma unroll
         for (int t2 = 0; t2 < 4; ++t2) {
           const int a1 = g * 4 + t2;
-          w[t2][0] = a1 < rout ? (double)Wk[(a * 2) * rout + a1] : 0.0;
-          w[t2][1] = a1 < rout ? (double)Wk[(a * 2 + 1) * rout + a1] : 0.0;
+          w[t2][0] = a1 < rout ? Ws[(a * 2) * rout + a1] : 0.0;
+          w[t2][1] = a1 < rout ? Ws[(a * 2 + 1) * rout + a1] : 0.0;
         }
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
@@ -590,7 +596,8 @@ static int batch_stages(qtt_batch* p, const T* x, T* out, char* ws, hipStream_t 
     k_batch_full<T><<<(unsigned)p->full_total, 256, 0, s>>>(fc, fr, lines, fwg, n, 0, p->f_rcap,
                                                              p->full_c, p->full_hb, f);
     QTT_LAUNCH_CHECK();
-    const size_t lds_max = sizeof(double) * 2 * kToepMaxBond * (1 << kToepMaxCB);
+    const size_t lds_max =
+        sizeof(double) * (2 * kToepMaxBond * (1 << kToepMaxCB) + kToepMaxBond * kToepMaxBond);
     static bool attr = false;
     if (!attr) {
       QTT_HIP_CHECK(hipFuncSetAttribute((const void*)k_batch_toep<T>,
@@ -602,7 +609,8 @@ static int batch_stages(qtt_batch* p, const T* x, T* out, char* ws, hipStream_t 
       if (p->toep_total[qi] > 0xFFFFFFFFLL / 64) return QTT_ENOTSUP;  // grid limit
       const long long* twg = reinterpret_cast<const long long*>(ws + p->o_twg) + (size_t)n * qi;
       const int pmax = 1 << p->toep_cbmax[qi];
-      const size_t lds = sizeof(double) * 2 * (2 * p->w_rcap) * pmax;
+      const size_t lds =
+          sizeof(double) * (2 * (2 * p->w_rcap) * pmax + p->w_rcap * 2 * p->w_rcap);
       k_batch_toep<T><<<(unsigned)p->toep_total[qi], 64, lds, s>>>(
           wc, wr, lines, twg, n, p->w_rcap, (int)qi, p->cb, pmax, f, st, y);
       QTT_LAUNCH_CHECK();
