@@ -101,6 +101,31 @@ def test_decompose_matches_ttsvd(name, gen, eps, R, dt):
                                                                    else 1e-5)
 
 
+# Without the singular-value output and with a binding cap the eigensolver
+# computes only the cap largest eigenvalues and takes the rank rule's tail
+# sums from the trace: same ranks, cores and reconstruction as the oracle.
+@pytest.mark.parametrize("name,d,seed,eps,R", [("scatter_d20_R32", 20, 2, 1e-4, 32),
+                                               ("scatter_d16_R16", 16, 3, 1e-4, 16),
+                                               ("scatter_d14_R8", 14, 4, 1e-3, 8)])
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_decompose_capped_without_sv(name, d, seed, eps, R, dt):
+    announce("decompose top-cap", name, dt)
+    x = G.scatterers_1d(d, seed)[0]
+    if dt == torch.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    ref, info = tt.tt_svd(x, eps, R, return_info=True)
+    t = q.decompose(torch.tensor(x, dtype=dt, device=DEV), eps, R)
+    ranks = t.ranks_host()
+    if info["margin"] > 1e-5 or dt == torch.float64:
+        assert ranks == info["ranks"]
+    assert max(ranks) == R  # the cap binds
+    assert rel(q.full(t).cpu().numpy(), tt.tt_full(ref)) <= tol_for(dt, eps)
+    for c in t.core_list()[:-1]:
+        U = c.reshape(-1, c.shape[2], order="F")
+        assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= (1e-10 if dt == torch.float64
+                                                                   else 1e-5)
+
+
 @pytest.mark.parametrize("kind,param", [("exp", 3.0), ("sin", 5.0), ("cos", 2.0), ("poly", 1),
                                         ("poly", 3)])
 @pytest.mark.parametrize("d", [10, 16])
