@@ -247,12 +247,12 @@ __global__ void __launch_bounds__(256) k_chain_gemm(const T* A, const T* B, T* C
 // consecutive doubles per k).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
-template <int MODE, int SZ>
+template <int MODE, int SZ, int TK>
 __global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const double* B, double* C,
                                                     const int32_t* ranks, int k, int Mh, int Nh) {
   // SZ x SZ tile per workgroup; each wave an (SZ/2) x (SZ/2) quarter made of
   // NB x NB blocks of 16 x 16
-  constexpr int TK = 16, LD = SZ + 4, NB = SZ / 32, PA = SZ / 16;
+  constexpr int LD = SZ + 4, NB = SZ / 32, PA = SZ * TK / 256;
   __shared__ double As[2][TK][LD];
   __shared__ double Bs[2][TK][LD];
   int M, N, K, rk = 0;
@@ -275,10 +275,10 @@ __global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const doubl
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int wr = (w >> 1) * (SZ / 2), wc = (w & 1) * (SZ / 2);
-  // global -> LDS assignment: A panel SZ rows x 16 k (PA consecutive k per
-  // thread), B panel 16 k x SZ columns (PA consecutive columns per thread)
-  const int am = tid / (16 / PA), ak = (tid % (16 / PA)) * PA;
-  const int bk = tid >> 4, bn = (tid & 15) * PA;
+  // global -> LDS assignment: A panel SZ rows x TK k (PA consecutive k per
+  // thread), B panel TK k x SZ columns (PA consecutive columns per thread)
+  const int am = tid / (TK / PA), ak = (tid % (TK / PA)) * PA;
+  const int bk = tid / (SZ / PA), bn = (tid % (SZ / PA)) * PA;
   double ra[PA], rb[PA];
   auto load = [&](int k0) {
     const int gr = row0 + am;
@@ -418,7 +418,7 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     {
       ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
       if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_LEFT, 32><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst, t.ranks,
+        k_chain_mfma<GEMM_LEFT, 32, 32><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst, t.ranks,
                                                           k, Mh, 0);
       else
         k_chain_gemm<T, GEMM_LEFT><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst,
@@ -440,7 +440,7 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     {
       ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
       if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_RIGHT, 32><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst, t.ranks,
+        k_chain_mfma<GEMM_RIGHT, 32, 32><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst, t.ranks,
                                                            k, 0, Nh);
       else
         k_chain_gemm<T, GEMM_RIGHT><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst,
@@ -457,7 +457,7 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     {
       ProbeScope _ps(QTT_K_FULL_FINAL, stream);
       if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_FINAL, 32><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
+        k_chain_mfma<GEMM_FINAL, 32, 32><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
       else
         k_chain_gemm<T, GEMM_FINAL><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
     }
