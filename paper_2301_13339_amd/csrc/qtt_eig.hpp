@@ -100,8 +100,8 @@ struct StepOut {
 // kept eigenvectors in the first r columns of V (descending eigenvalues):
 // lam[0..E) = eigenvalues in non-increasing order, perm[b] = b.  sx: scratch
 // of kEigScratch doubles.  Returns r.  Must be called by all threads.
-constexpr int kEigScratch = 10 * kMaxM + 16;
-constexpr int kEigNrmSlot = 10 * kMaxM;  // sx[kEigNrmSlot]: Gershgorin bound of T
+constexpr int kEigScratch = 10 * kMaxM + 16 + 256;
+constexpr int kEigNrmSlot = kEigScratch - 8;  // sx[kEigNrmSlot]: Gershgorin bound of T, [+1]: trace
 // one workgroup of 4 waves: a barrier costs ~40 cycles with 4 waves and
 // ~470 with 16 on gfx950, and every eigen step is barrier/latency bound
 constexpr int kEigThreads = 256;
@@ -207,14 +207,14 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
 #endif
   // pv .. pv + 7 kMaxM (pv, e2, la and the arrays after) are free now
   if (E <= 64) {
-    // reflectors are rows of A (sy_tridiag64)
-    const bool done = mgs_backtr64(A, bt, E, lda, V, lda, r, pv, iscr + 3);
+    // A holds Q^T of the reduction (sy_tridiag64)
+    const bool done = mgs_backtr64(A, E, lda, V, lda, r, pv, iscr + 3);
 #ifdef QTT_EIG_TIMING
     tt[4] = wall_clock64();
 #endif
     if (!done) {
       mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
-      back_transform64(A, bt, E, lda, V, lda, r);
+      backtr_gemm64(A, E, lda, V, r);
     }
   } else {
     mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);

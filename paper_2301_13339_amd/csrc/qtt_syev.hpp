@@ -278,9 +278,10 @@ __device__ void sy_tridiag(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd
 // vectors meet in LDS), and the step loop is unrolled by 16 so that row j,
 // published at step j, is a register with a compile-time index.  Same
 // reflectors as sy_tridiag (H_j = I - beta_j v v^T, v_{j+1} = x0 + sign(x0)
-// alpha); reflector j is stored as row j of A (entries 0..j zero, v in
-// j+1..63), beta_j in bt[j].  A: >= 64 rows allocated, lda >= 64.
-// buf: >= 704 doubles.
+// alpha).  The product X = H_{E-3} ... H_0 = Q^T is accumulated alongside in
+// the same register layout (its update needs vT X, one more partial vector
+// per wave in the same LDS exchange) and left in A; beta_j in bt[j].
+// A: >= 64 rows allocated, lda >= 64.  buf: >= 960 doubles.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -293,7 +294,10 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
   ldsd part = buf + 128;         // 4 x 64: partial A v of each wave
   ldsd wb = buf + 384 + 64 * q;  // 64 per wave (wave-private): w
   ldsd last = buf + 576;         // 2 x 64: rows E-2 and E-1 at the end
-  double a[16];
+  ldsd part2 = buf + 704;        // 4 x 64: partial v^T X of each wave
+  double a[16], x[16];
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) x[ii] = (16 * q + ii == c) ? 1.0 : 0.0;
 #pragma unroll
   for (int ii = 0; ii < 16; ++ii) {
     const int r = 16 * q + ii;
@@ -338,7 +342,7 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
       const double vc = (c == j + 1) ? v0 : t;
       // v on the own rows (zero on rows <= j): waves below jb hold no active row
       double vi[16];
-      double pp = 0.0;
+      double pp = 0.0, px = 0.0;
       if (q >= jb) {
 #pragma unroll
         for (int ii = 0; ii < 16; ++ii) vi[ii] = colb[16 * q + ii];
@@ -358,9 +362,18 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
           s3 = fma(a[ii + 3], vi[ii + 3], s3);
         }
         pp = (s0 + s1) + (s2 + s3);
+        double u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 16; ii += 4) {
+          u0 = fma(x[ii], vi[ii], u0);
+          u1 = fma(x[ii + 1], vi[ii + 1], u1);
+          u2 = fma(x[ii + 2], vi[ii + 2], u2);
+          u3 = fma(x[ii + 3], vi[ii + 3], u3);
+        }
+        px = (u0 + u1) + (u2 + u3);
       }
       part[q * 64 + c] = pp;
-      if (q == 3) A[j * lda + c] = vc;  // reflector row j (vc = 0 for c <= j)
+      part2[q * 64 + c] = px;
       if (tid == 0) {
         dg[j] = dj;
         od[j] = -sg * alpha;
@@ -379,6 +392,11 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
         for (int ii = 0; ii < 16; ++ii) wi[ii] = wb[16 * q + ii];
 #pragma unroll
         for (int ii = 0; ii < 16; ++ii) a[ii] = fma(-vi[ii], w, fma(-wi[ii], vc, a[ii]));
+        // X <- H_j X = X - beta v (v^T X)
+        const double bs =
+            beta * ((part2[c] + part2[64 + c]) + (part2[128 + c] + part2[192 + c]));
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) x[ii] = fma(-bs, vi[ii], x[ii]);
         wave_lds_sync();  // wb is rewritten next step
       }
     }
@@ -399,52 +417,48 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
     dg[E - 1] = last[64 + E - 1];
     bt[E - 1] = 0.0;
   }
+  // X = Q^T into A (A itself is no longer needed)
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) A[(16 * q + ii) * lda + c] = x[ii];
   __syncthreads();
 }
 
-// Z <- Q Z for the r <= 64 columns of Z, Q = H_0 ... H_{E-3} with reflector
-// j stored as row j of A (sy_tridiag64).  Lane b of wave 0 holds column b in
-// registers and applies every reflector in turn; blocks of 16 entries that
-// lie in the zero part (entries <= j) of a reflector are skipped.
+// Z <- Q Z for the r <= 64 columns of Z (E <= 64 rows) with X = Q^T in A
+// (sy_tridiag64), as one product on the FP64 matrix cores: wave w forms the
+// 16-row block w of U = X^T Z, one 16 x 16 block per 16 columns.  All
+// threads; Z is read completely before it is overwritten.
+typedef double syev_f64x4 __attribute__((ext_vector_type(4)));
+
 template <class MP>
-__device__ void back_transform64(MP A, lds_ptr<const double> bt, int E, int lda, MP Z, int ldz,
-                                 int r) {
-  if (threadIdx.x < 64) {
-    const int b = threadIdx.x;
-    double z[64];
+__device__ void backtr_gemm64(MP X, int E, int lda, MP Z, int r) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+  const int nbj = (r + 15) >> 4;  // <= 4
+  syev_f64x4 acc[4];
 #pragma unroll
-    for (int i = 0; i < 64; ++i) z[i] = Z[i * ldz + b];
+  for (int t = 0; t < 4; ++t) acc[t] = syev_f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int k0 = 0; k0 < E; k0 += 4) {
+    const int c = k0 + lk;
+    const bool cin = c < E;
+    const int cc = cin ? c : 0;
+    const double a = X[cc * lda + 16 * w + lr];  // X^T(i, c), i = 16w + lr < 64 <= lda
 #pragma unroll
-    for (int i = 0; i < 64; ++i) z[i] = (i < E) ? z[i] : 0.0;
-    for (int j = E - 3; j >= 0; --j) {
-      const double beta = bt[j];
-      if (beta == 0.0) continue;  // uniform
-      const MP row = A + j * lda;
-      double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (16 * k + 15 > j) {
-#pragma unroll
-          for (int ii = 0; ii < 16; ii += 4) {
-            d0 = fma(row[16 * k + ii], z[16 * k + ii], d0);
-            d1 = fma(row[16 * k + ii + 1], z[16 * k + ii + 1], d1);
-            d2 = fma(row[16 * k + ii + 2], z[16 * k + ii + 2], d2);
-            d3 = fma(row[16 * k + ii + 3], z[16 * k + ii + 3], d3);
-          }
-        }
-      }
-      const double d = beta * ((d0 + d1) + (d2 + d3));
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        if (16 * k + 15 > j) {
-#pragma unroll
-          for (int ii = 0; ii < 16; ++ii) z[16 * k + ii] = fma(-d, row[16 * k + ii], z[16 * k + ii]);
-        }
+    for (int t = 0; t < 4; ++t) {
+      if (t < nbj) {  // uniform
+        const double bz = Z[cc * lda + 16 * t + lr];  // column < 64 <= lda
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cin ? a : 0.0, cin ? bz : 0.0, acc[t], 0,
+                                                      0, 0);
       }
     }
+  }
+  __syncthreads();  // every wave has read Z
 #pragma unroll
-    for (int i = 0; i < 64; ++i)
-      if (i < E && b < r) Z[i * ldz + b] = z[i];
+  for (int t = 0; t < 4; ++t) {
+    if (t >= nbj) break;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * w + 4 * e + lk, b = 16 * t + lr;
+      if (i < E && b < r) Z[i * lda + b] = acc[t][e];
+    }
   }
   __syncthreads();
 }
@@ -452,10 +466,9 @@ __device__ void back_transform64(MP A, lds_ptr<const double> bt, int E, int lda,
 // x summed over the four DPP rows at the same position, in every lane
 __device__ __forceinline__ double sum_rows4(double x) { return sum_halves(sum_row_pairs(x)); }
 
-
 // Modified Gram-Schmidt of the r kept eigenvectors of T (columns 0..r-1 of
-// Z, E <= 64 rows, r <= 64) followed by Z <- Q Z with the reflector rows of
-// sy_tridiag64, all in registers.  Column b lives in wave b / 16, in the
+// Z, E <= 64 rows, r <= 64) in registers, followed by Z <- Q Z with the
+// accumulated Q^T of sy_tridiag64 in A.  Column b lives in wave b / 16, in the
 // lanes at position b % 16 of the four DPP rows, row q holding entries
 // 16q..16q+15; a dot product is a per-lane sum plus two lane swaps.  Step j
 // publishes column j (as it stands, unnormalised) and 1 / ||z_j||^2 in a
@@ -466,8 +479,7 @@ __device__ __forceinline__ double sum_rows4(double x) { return sum_halves(sum_ro
 // vector twice) makes the routine return false with Z untouched, and the
 // caller takes mgs_cols, whose inverse iteration replaces such columns.
 template <class MP>
-__device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP Z, int ldz, int r,
-                             ldsd pub, ldsi flag) {
+__device__ bool mgs_backtr64(MP A, int E, int lda, MP Z, int ldz, int r, ldsd pub, ldsi flag) {
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63, q = l >> 4;
   const int b = 16 * w + (l & 15);
@@ -534,36 +546,6 @@ __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP 
 #pragma unroll
     for (int ii = 0; ii < 16; ++ii) z[ii] *= inv;
   }
-  if (16 * w < r && E >= 3) {
-    // reflectors E-3 .. 0; the next row and beta are loaded a step ahead
-    double rn[16];
-    double bn = bt[E - 3];
-#pragma unroll
-    for (int ii = 0; ii < 16; ++ii) rn[ii] = A[(E - 3) * lda + 16 * q + ii];
-    for (int j = E - 3; j >= 0; --j) {
-      double rw[16];
-#pragma unroll
-      for (int ii = 0; ii < 16; ++ii) rw[ii] = rn[ii];
-      const double beta = bn;
-      if (j > 0) {
-        bn = bt[j - 1];
-#pragma unroll
-        for (int ii = 0; ii < 16; ++ii) rn[ii] = A[(j - 1) * lda + 16 * q + ii];
-      }
-      if (beta == 0.0) continue;  // uniform
-      double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
-#pragma unroll
-      for (int ii = 0; ii < 16; ii += 4) {
-        d0 = fma(rw[ii], z[ii], d0);
-        d1 = fma(rw[ii + 1], z[ii + 1], d1);
-        d2 = fma(rw[ii + 2], z[ii + 2], d2);
-        d3 = fma(rw[ii + 3], z[ii + 3], d3);
-      }
-      const double d = beta * sum_rows4((d0 + d1) + (d2 + d3));
-#pragma unroll
-      for (int ii = 0; ii < 16; ++ii) z[ii] = fma(-d, rw[ii], z[ii]);
-    }
-  }
   if (16 * w < r) {
 #pragma unroll
     for (int ii = 0; ii < 16; ++ii) {
@@ -572,6 +554,7 @@ __device__ bool mgs_backtr64(MP A, lds_ptr<const double> bt, int E, int lda, MP 
     }
   }
   __syncthreads();
+  backtr_gemm64(A, E, lda, Z, r);
   return true;
 }
 
