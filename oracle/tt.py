@@ -23,6 +23,14 @@ Readings of the text (where it is silent, garbled or inconsistent):
   ``r >= 1`` whose discarded tail satisfies ``sum_{i>r} sigma_i^2 <= tau^2``
   (equality keeps the smaller rank).  Modification (1) of Section 5 (max
   rank) then takes ``min(r, R_max)``; ``max_rank = 0`` means uncapped.
+* Modification (3) of Section 5 (singular-value drop-off) is read as: with
+  ``s`` non-increasing, the kept rank is the smallest ``k >= 1`` with
+  ``s_{k+1} < delta * s_k`` (1-based; the first relative drop below
+  ``delta`` cuts everything after it), and no cut when no ratio is below
+  ``delta``.  It is combined with the tolerance rule and the cap as
+  ``min(r_eps, r_delta, R_max)``; ``eps = 0`` and no cap give the pure
+  drop-off method, ``delta = 0`` turns it off.  A ratio ``0 / 0`` (two zero
+  singular values) is not a drop.
 * Sign gauge (cores are unique only up to it): each kept left singular vector
   is flipped so that its largest-magnitude entry is positive.
 * TT-rounding is not described in the paper (only the TT-SVD of O11 is);
@@ -68,6 +76,22 @@ def truncation_rank(s: np.ndarray, tau: float, max_rank: int = 0) -> int:
     return max(r, 1)
 
 
+def dropoff_rank(s: np.ndarray, delta: float):
+    """Rank kept by the singular-value drop-off rule, modification (3) of Section 5.
+
+    ``s`` holds singular values in non-increasing order.  Returns the smallest
+    ``k >= 1`` with ``s[k] < delta * s[k-1]`` (0-based, i.e. keep ``s[0..k-1]``),
+    or ``None`` when no ratio falls below ``delta`` (or ``delta <= 0``).
+    """
+    if not delta > 0.0:
+        return None
+    s = np.asarray(s, dtype=np.float64)
+    for k in range(1, s.size):
+        if s[k] < delta * s[k - 1]:
+            return k
+    return None
+
+
 def _gauge(u: np.ndarray, vt: np.ndarray):
     """Flip each column of ``u`` (and row of ``vt``) so its largest |entry| is > 0."""
     for j in range(u.shape[1]):
@@ -78,19 +102,22 @@ def _gauge(u: np.ndarray, vt: np.ndarray):
     return u, vt
 
 
-def tt_svd(a, eps: float, max_rank: int = 0, return_info: bool = False):
-    """Algorithm 1 (TT-SVD) on the QTT reshape of ``a``, with modification (1).
+def tt_svd(a, eps: float, max_rank: int = 0, return_info: bool = False, delta: float = 0.0):
+    """Algorithm 1 (TT-SVD) on the QTT reshape of ``a``, with modifications (1) and (3).
 
     ``a`` is a vector of length ``2**K`` (or a row-major array of that many
-    entries).  Returns the list of ``K`` cores (and, with ``return_info``, a
-    dict with the threshold, ranks, singular values of every unfolding and
-    the smallest relative distance ``|tail^2 - tau^2| / tau^2`` over the
-    decisions the threshold made, used to flag near-ties).
+    entries).  ``delta > 0`` adds the drop-off cut of modification (3)
+    (:func:`dropoff_rank`).  Returns the list of ``K`` cores (and, with
+    ``return_info``, a dict with the threshold, ranks, singular values of
+    every unfolding, the smallest relative distance ``|tail^2 - tau^2| /
+    tau^2`` over the decisions the threshold made, and the smallest
+    ``|s[k]/s[k-1] - delta| / delta`` over the ratios the drop-off rule
+    examined, both used to flag near-ties).
     """
     v = np.asarray(a, dtype=np.float64).ravel()
     K = log2_exact(v.size)
     norm = float(np.linalg.norm(v))
-    info = {"norm": norm, "sv": [], "ranks": [1], "margin": math.inf}
+    info = {"norm": norm, "sv": [], "ranks": [1], "margin": math.inf, "delta_margin": math.inf}
     if K == 1:
         cores = [v.reshape(1, 2, 1).copy()]
         info["tau"] = 0.0
@@ -105,6 +132,16 @@ def tt_svd(a, eps: float, max_rank: int = 0, return_info: bool = False):
         A = rem.reshape((2 * r_prev, -1), order="F")          # unfolding, Lemma 5.1 shape
         U, s, Vt = np.linalg.svd(A, full_matrices=False)
         r = truncation_rank(s, tau, max_rank)
+        r_drop = dropoff_rank(s, delta)
+        if r_drop is not None:
+            r = min(r, r_drop)
+        if delta > 0.0:
+            # ratios up to the first drop decided the cut (all of them if none)
+            last = r_drop if r_drop is not None else s.size - 1
+            for j in range(1, last + 1):
+                if s[j - 1] > 0.0:
+                    info["delta_margin"] = min(info["delta_margin"],
+                                               abs(s[j] / s[j - 1] - delta) / delta)
         info["sv"].append(s.copy())
         if tau > 0:
             tails = np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]])

@@ -213,3 +213,64 @@ def test_round_cores_left_orthonormal():
         U = c.reshape(-1, c.shape[2])
         assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= 1e-13
     assert np.linalg.norm(Z[-1]) == pytest.approx(np.linalg.norm(tt.tt_full(Z)), rel=1e-12)
+
+
+# ------------------------------------------- drop-off rule, modification (3)
+
+def test_dropoff_rank_definition():
+    """The first ratio s_{k+1}/s_k below delta keeps k values (Section 5, modification (3))."""
+    s = np.array([1.0, 0.5, 0.2, 0.01, 0.009])
+    # ratios 0.5, 0.4, 0.05, 0.9
+    assert tt.dropoff_rank(s, 0.3) == 3
+    assert tt.dropoff_rank(s, 0.45) == 2      # 0.4 < 0.45 comes before 0.05
+    assert tt.dropoff_rank(s, 0.55) == 1
+    assert tt.dropoff_rank(s, 0.04) is None   # no ratio below 0.04
+    assert tt.dropoff_rank(s, 0.0) is None    # off
+    # squared ratios would give 1 here (0.25 < 0.3): the rule is on sigma, not sigma^2
+    assert tt.dropoff_rank(np.array([1.0, 0.5, 0.6 * 0.5]), 0.3) is None
+    # equality is not a drop
+    assert tt.dropoff_rank(np.array([1.0, 0.25]), 0.25) is None
+    # zero singular values: a drop to zero cuts, 0/0 does not
+    assert tt.dropoff_rank(np.array([2.0, 0.0, 0.0]), 0.1) == 1
+    assert tt.dropoff_rank(np.array([0.0, 0.0]), 0.1) is None
+
+
+def _exp_sum(d, rates, amps):
+    x = np.arange(1 << d) / float(1 << d)
+    return sum(a * np.exp(c * x) for c, a in zip(rates, amps))
+
+
+@pytest.mark.parametrize("d", [8, 12])
+def test_dropoff_recovers_exact_ranks(d):
+    """A sum of three exponentials has QTT ranks min(2^k, 2^(d-k), 3); its further
+    singular values are rounding noise, so any delta between the noise ratio and the
+    smallest genuine ratio recovers exactly those ranks with eps = 0, where the
+    tolerance rule alone keeps the rounding noise (full ranks)."""
+    v = _exp_sum(d, [-1.0, 2.5, 6.0], [1.0, -0.7, 0.05])
+    want = [1] + [min(1 << k, 1 << (d - k), 3) for k in range(1, d)] + [1]
+    cores, info = tt.tt_svd(v, 0.0, 0, True, delta=1e-6)
+    assert info["ranks"] == want
+    rec = tt.tt_full(cores)
+    assert np.linalg.norm(rec - v) <= 1e-11 * np.linalg.norm(v)
+    # without the cut, eps = 0 keeps the rounding-level singular values
+    plain = tt.tt_svd(v, 0.0, 0, True)[1]["ranks"]
+    assert max(plain) > 3
+
+
+def test_dropoff_combines_with_tolerance_and_cap():
+    """The kept rank is min(eps-rank, drop-off rank, cap) at every unfolding."""
+    _, clean = G.gaussian_bumps_1d(10, seed=7, noise_rel=0.0)
+    rng = np.random.default_rng(3)
+    x = clean + 1e-3 * rng.standard_normal(clean.size)
+    for eps, cap, delta in [(1e-2, 0, 0.3), (1e-4, 0, 0.05), (1e-6, 6, 0.02), (0.0, 0, 0.1)]:
+        _, info = tt.tt_svd(x, eps, cap, True, delta=delta)
+        tau = info["tau"]
+        for k, s in enumerate(info["sv"], start=1):
+            r_eps = tt.truncation_rank(s, tau, 0)
+            r_d = tt.dropoff_rank(s, delta)
+            want = min(r_eps, r_d if r_d is not None else s.size, cap if cap > 0 else s.size)
+            assert info["ranks"][k] == max(want, 1)
+    # delta = 0 is plain Algorithm 1
+    a = tt.tt_svd(x, 1e-3, 0, True)[1]["ranks"]
+    b = tt.tt_svd(x, 1e-3, 0, True, delta=0.0)[1]["ranks"]
+    assert a == b
