@@ -135,6 +135,24 @@ int qtt_decompose(const void* x, int d, int dtype, double eps, int max_rank, qtt
                   double* sv, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * TT-SVD with the singular-value drop-off rule, modification (3) of Section 5
+ * ("SV drop off TT-SVD"), on top of the tolerance rule and the cap of
+ * qtt_decompose.  With s the singular values of unfolding k (non-increasing),
+ * the drop-off rank is the smallest j >= 1 with s_{j+1} < delta * s_j (the
+ * first relative drop below delta cuts every later value; two zero values
+ * are not a drop); the kept rank is min(eps-rank, drop-off rank, cap_k), or
+ * min(eps-rank, cap_k) when no ratio falls below delta.  eps = 0 and
+ * max_rank = 0 give the drop-off rule alone; delta = 0 is qtt_decompose.
+ * The ratios come from the FP64 Gram eigenvalues (s^2), so a decision on
+ * singular values below about 1e-7 of the largest is not reliable.
+ *   delta     threshold, 0 <= delta < 1 (else QTT_EINVAL)
+ * Everything else (sizes, workspace, outputs, errors) as qtt_decompose;
+ * QTT_STATUS_RANKCAP is set only when the cap, not the drop-off, decided.
+ */
+int qtt_decompose_dropoff(const void* x, int d, int dtype, double eps, double delta, int max_rank,
+                          qtt_tensor* out, double* sv, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * QTT of the Toeplitz generator of the normalised sinc kernel.
  * For N = 2^d the kernel is g_m = sinc(B x_m)/Z on x_m = -1/2 + m/N
  * (sinc(t) = sin(pi t)/(pi t), kernel (7.2) with B = 1/Delta_x and Z the

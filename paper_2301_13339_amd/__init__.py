@@ -167,8 +167,14 @@ def from_cores(cores, dtype=torch.float64, device="cuda") -> QTT:
     return t
 
 
-def decompose(x: torch.Tensor, eps: float, max_rank: int = 0, return_sv: bool = False):
-    """TT-SVD of the QTT reshape of ``x`` (length ``2**d``; images row-major)."""
+def decompose(x: torch.Tensor, eps: float, max_rank: int = 0, return_sv: bool = False,
+              delta: float = 0.0):
+    """TT-SVD of the QTT reshape of ``x`` (length ``2**d``; images row-major).
+
+    ``delta > 0`` adds the singular-value drop-off cut of modification (3) of
+    Section 5 (``qtt_decompose_dropoff``); ``eps = 0`` with it gives the
+    drop-off rule alone.
+    """
     if not x.is_cuda:
         raise ValueError("decompose expects a device tensor")
     x = x.contiguous().reshape(-1)
@@ -187,11 +193,18 @@ def decompose(x: torch.Tensor, eps: float, max_rank: int = 0, return_sv: bool = 
     if return_sv:
         sv = torch.zeros((max(d - 1, 1), 2 * QTT_MAX_RANK), dtype=torch.float64, device=x.device)
     t = out._c()
-    _check(lib().qtt_decompose(ctypes.c_void_p(x.data_ptr()), d, dt, float(eps), int(max_rank),
-                               ctypes.byref(t),
-                               ctypes.c_void_p(sv.data_ptr()) if sv is not None else None,
-                               ctypes.c_void_p(w.data_ptr()), ws.value, _stream(x.device)),
-           "qtt_decompose")
+    svp = ctypes.c_void_p(sv.data_ptr()) if sv is not None else None
+    if delta:
+        _check(lib().qtt_decompose_dropoff(ctypes.c_void_p(x.data_ptr()), d, dt, float(eps),
+                                           float(delta), int(max_rank), ctypes.byref(t), svp,
+                                           ctypes.c_void_p(w.data_ptr()), ws.value,
+                                           _stream(x.device)),
+               "qtt_decompose_dropoff")
+    else:
+        _check(lib().qtt_decompose(ctypes.c_void_p(x.data_ptr()), d, dt, float(eps), int(max_rank),
+                                   ctypes.byref(t), svp, ctypes.c_void_p(w.data_ptr()), ws.value,
+                                   _stream(x.device)),
+               "qtt_decompose")
     out._keep = [w, x]
     return (out, sv) if return_sv else out
 

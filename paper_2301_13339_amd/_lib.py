@@ -22,7 +22,7 @@ lib_path = os.path.join(HERE, "libqtt.so")
 # every symbol include/qtt.h declares
 EXPORTS = [
     "qtt_core_elems", "qtt_strerror", "qtt_last_hip_error",
-    "qtt_query_decompose", "qtt_decompose", "qtt_kernel_sinc",
+    "qtt_query_decompose", "qtt_decompose", "qtt_decompose_dropoff", "qtt_kernel_sinc",
     "qtt_query_conv", "qtt_conv",
     "qtt_query_round", "qtt_round", "qtt_query_round_sketch", "qtt_round_sketch",
     "qtt_query_full", "qtt_full",
@@ -80,6 +80,10 @@ def _declare(L):
     L.qtt_decompose.restype = ctypes.c_int
     L.qtt_decompose.argtypes = [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                 _TP, _VP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_decompose_dropoff.restype = ctypes.c_int
+    L.qtt_decompose_dropoff.argtypes = [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                        ctypes.c_double, ctypes.c_int, _TP, _VP, _VP,
+                                        ctypes.c_size_t, _VP]
     L.qtt_kernel_sinc.restype = ctypes.c_int
     L.qtt_kernel_sinc.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   _TP, _VP, ctypes.c_size_t, _VP]

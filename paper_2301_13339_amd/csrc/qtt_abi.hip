@@ -169,9 +169,9 @@ int qtt_query_decompose(int d, int max_rank, int dtype, int32_t* cap, size_t* ws
 
 static int decompose_common(const Source& src, int D, int dtype, double eps, int max_rank,
                             qtt_tensor* out, double* sv, void* ws, size_t ws_bytes,
-                            void* stream) {
+                            void* stream, double delta = 0.0) {
   if (D < 1 || D > kMaxModes + 1 || !dtype_ok(dtype) || !(eps >= 0.0) || !isfinite(eps) ||
-      max_rank < 0)
+      max_rank < 0 || !(delta >= 0.0 && delta < 1.0))
     return QTT_EINVAL;
   if (!ws) return QTT_EINVAL;
   DecompPlan p;
@@ -183,7 +183,7 @@ static int decompose_common(const Source& src, int D, int dtype, double eps, int
   if (rc) return rc;
   plan_decompose(D, eff_rank(max_rank), dtype, ws, &p);
   TensorDev td = make_dev(out);
-  return run_decompose(p, src, eps, td, sv, static_cast<hipStream_t>(stream));
+  return run_decompose(p, src, eps, td, sv, static_cast<hipStream_t>(stream), delta);
 }
 
 int qtt_decompose(const void* x, int d, int dtype, double eps, int max_rank, qtt_tensor* out,
@@ -191,6 +191,13 @@ int qtt_decompose(const void* x, int d, int dtype, double eps, int max_rank, qtt
   if (!x) return QTT_EINVAL;
   Source src{x, 0, 0.0, 0};
   return decompose_common(src, d, dtype, eps, max_rank, out, sv, ws, ws_bytes, stream);
+}
+
+int qtt_decompose_dropoff(const void* x, int d, int dtype, double eps, double delta, int max_rank,
+                          qtt_tensor* out, double* sv, void* ws, size_t ws_bytes, void* stream) {
+  if (!x) return QTT_EINVAL;
+  Source src{x, 0, 0.0, 0};
+  return decompose_common(src, d, dtype, eps, max_rank, out, sv, ws, ws_bytes, stream, delta);
 }
 
 int qtt_kernel_sinc(int d, double B, double eps_w, int dtype, qtt_tensor* w_out, void* ws,

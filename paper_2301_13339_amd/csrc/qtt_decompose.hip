@@ -927,6 +927,7 @@ __device__ __noinline__ void batch_line(const BatchTask& tk, const T* x, T* core
   so.sv = nullptr;
   so.lib_capped = tk.rcap >= kMaxRank ? 1 : 0;
   so.dbg = nullptr;
+  so.delta2 = 0.0;
   int32_t* flag = status + tk.status_idx;  // non-finite input sets bit 1 here directly
   const T* xl = GEN ? x : x + tk.x_off;
   const long long N = 1LL << D;
@@ -1194,7 +1195,7 @@ static int launch_project(const T* Ain, const Source& src, long long rowsA, int 
 
 template <typename T, int GEN>
 static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
-                           const TensorDev& out, double* sv, hipStream_t stream) {
+                           const TensorDev& out, double* sv, hipStream_t stream, double delta) {
   static bool attrs = false;
   if (!attrs) {
     set_attrs<T, GEN>();
@@ -1209,6 +1210,7 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
   so.sv = sv;
   so.lib_capped = P.rcap >= kMaxRank ? 1 : 0;
   so.dbg = P.iflags + 16;
+  so.delta2 = delta * delta;
   Meta meta;
   for (int k = 0; k <= QTT_MAXD; ++k) {
     meta.caps[k] = k <= D ? P.cap[k] : 0;
@@ -1326,15 +1328,15 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
 }
 
 int run_decompose(const DecompPlan& P, const Source& src, double eps, const TensorDev& out,
-                  double* sv, hipStream_t stream) {
+                  double* sv, hipStream_t stream, double delta) {
   if (P.dtype == QTT_F64) {
-    if (src.gen == 2) return run_decompose_t<double, 2>(P, src, eps, out, sv, stream);
-    return src.gen ? run_decompose_t<double, 1>(P, src, eps, out, sv, stream)
-                   : run_decompose_t<double, 0>(P, src, eps, out, sv, stream);
+    if (src.gen == 2) return run_decompose_t<double, 2>(P, src, eps, out, sv, stream, delta);
+    return src.gen ? run_decompose_t<double, 1>(P, src, eps, out, sv, stream, delta)
+                   : run_decompose_t<double, 0>(P, src, eps, out, sv, stream, delta);
   }
-  if (src.gen == 2) return run_decompose_t<float, 2>(P, src, eps, out, sv, stream);
-  return src.gen ? run_decompose_t<float, 1>(P, src, eps, out, sv, stream)
-                 : run_decompose_t<float, 0>(P, src, eps, out, sv, stream);
+  if (src.gen == 2) return run_decompose_t<float, 2>(P, src, eps, out, sv, stream, delta);
+  return src.gen ? run_decompose_t<float, 1>(P, src, eps, out, sv, stream, delta)
+                 : run_decompose_t<float, 0>(P, src, eps, out, sv, stream, delta);
 }
 
 }  // namespace qtt

@@ -81,6 +81,24 @@ __device__ inline int truncation_rank_top(lds_ptr<const double> lam, int K, doub
   return r < cap ? r : cap;
 }
 
+// Singular-value drop-off, modification (3) of Section 5: the smallest
+// k >= 1 with sigma_{k+1} < delta sigma_k, i.e. lam[k] < delta^2 lam[k-1]
+// on the non-increasing Gram eigenvalues (negative ones read as zero; 0/0 is
+// no drop), examined over the K eigenvalues known.  Returns a value above
+// every rank when no ratio falls below delta.  One wave.
+__device__ inline int dropoff_rank_wave(lds_ptr<const double> lam, int K, double delta2) {
+  const int l = threadIdx.x & 63;
+  for (int base = 0; base + 1 < K; base += 64) {
+    const int i = base + l;
+    const bool in = i + 1 < K;  // indices stay below K
+    const double a = fmax(lam[in ? i : 0], 0.0), b = fmax(lam[in ? i + 1 : 0], 0.0);
+    const bool cut = in & (b < delta2 * a);
+    const unsigned long long m = __ballot(cut);
+    if (m) return base + __ffsll((unsigned long long)m);  // (first i) + 1
+  }
+  return 1 << 30;
+}
+
 // ----------------------------------------------------- step bookkeeping
 // capacities and core offsets, passed by value to the kernels
 struct Meta {
@@ -93,7 +111,8 @@ struct StepOut {
   int32_t* status;
   double* sv;  // may be null
   int lib_capped;
-  int32_t* dbg;  // per-step diagnostics in the workspace (optional timings)
+  int32_t* dbg;   // per-step diagnostics in the workspace (optional timings)
+  double delta2;  // square of the drop-off threshold of modification (3); 0 = off
 };
 
 // Eigen-solve the Gram matrix in A (E x E), choose the rank, and leave the
@@ -165,8 +184,14 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   __syncthreads();
   if (tid < 64) {
     int over = 0;
-    const int r = (K < E) ? truncation_rank_top(lam, K, sx[kEigNrmSlot + 1], tau2, cap, &over)
-                          : truncation_rank_wave(lam, E, tau2, cap, &over);
+    int r = (K < E) ? truncation_rank_top(lam, K, sx[kEigNrmSlot + 1], tau2, cap, &over)
+                    : truncation_rank_wave(lam, E, tau2, cap, &over);
+    if (so.delta2 > 0.0 && finite) {
+      // the drop-off cut; a cut within the cap means the cap did not decide
+      const int rd = dropoff_rank_wave(lam, K, so.delta2);
+      if (rd < r) r = rd;
+      if (rd <= cap) over = 0;
+    }
     if (tid == 0) {
       iscr[2] = r;
       so.ranks[k] = r;

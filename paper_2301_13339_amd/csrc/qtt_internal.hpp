@@ -153,8 +153,9 @@ struct DecompPlan {
 };
 
 int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p);
+// delta: drop-off threshold of modification (3) of Section 5 (0 = off)
 int run_decompose(const DecompPlan& p, const Source& src, double eps, const TensorDev& out,
-                  double* sv, hipStream_t stream);
+                  double* sv, hipStream_t stream, double delta = 0.0);
 
 // ----------------------------------------------------------------- batched
 // One independent decomposition of a batch (see k_batch_decompose).

@@ -447,6 +447,7 @@ static int sketch_t(const T* y, int D, double eps, const int* cap, int ell, uint
   so.sv = nullptr;
   so.lib_capped = 1;
   so.dbg = nullptr;
+  so.delta2 = 0.0;
   T* cores = static_cast<T*>(out.cores);
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T* X = y;

@@ -86,6 +86,12 @@ def test_calls_validate_before_launching():
     t.cap[2] = cap[2]
     assert so.qtt_decompose(fake, 4, L.QTT_F32, 1e-3, 0, ctypes.byref(t), None, fake, ws.value,
                             None) == -1
+    # drop-off threshold outside [0, 1)
+    for dl in (-0.1, 1.0, float("nan")):
+        assert so.qtt_decompose_dropoff(fake, 4, L.QTT_F64, 0.0, dl, 0, ctypes.byref(t), None,
+                                        fake, ws.value, None) == -1
+    assert so.qtt_decompose_dropoff(None, 4, L.QTT_F64, 0.0, 0.1, 0, ctypes.byref(t), None,
+                                    fake, ws.value, None) == -1
     # kernel generator: bad bandwidth
     assert so.qtt_kernel_sinc(4, 0.0, 1e-5, L.QTT_F64, ctypes.byref(t), fake, 1 << 20, None) == -1
     assert so.qtt_kernel_sinc(4, float("nan"), 1e-5, L.QTT_F64, ctypes.byref(t), fake, 1 << 20,

@@ -126,6 +126,68 @@ def test_decompose_capped_without_sv(name, d, seed, eps, R, dt):
                                                                    else 1e-5)
 
 
+def _padded(v, K):
+    out = np.zeros(1 << K)
+    out[: v.size] = v
+    return out
+
+
+def _lowrank_noise(d, seed, noise):
+    """Three smooth terms (QTT ranks <= 5) plus white noise of the given std."""
+    x = np.arange(1 << d) / float(1 << d)
+    rng = np.random.default_rng(seed)
+    v = np.sin(2 * np.pi * 5 * x + 0.3) + 0.8 * np.exp(-3 * x) + 0.3 * np.cos(2 * np.pi * 11 * x)
+    return v + noise * rng.standard_normal(v.size)
+
+
+# Modification (3) of Section 5: the singular-value drop-off cut, alone
+# (eps = 0) or with the tolerance and the cap.  The cases cut at several
+# unfoldings (to rank 1 where the two sample halves are nearly equal) and run
+# through the tail-only, level + eig-step and tail paths.
+DROP_CASES = [
+    ("ex1_K12_d02", lambda: _padded(G.paper_example1(12, 0, True)[0], 12), 0.0, 32, 0.02),
+    ("ex1_K20_d02", lambda: _padded(G.paper_example1(20, 0, True)[0], 20), 0.0, 32, 0.02),
+    ("ex2_K16_d01", lambda: _padded(G.paper_example2(16, 0)[0], 16), 0.0, 32, 0.01),
+    ("lowrank_d10_d01", lambda: _lowrank_noise(10, 10, 1e-5), 0.0, 0, 0.01),
+    ("lowrank_d16_e6_d05", lambda: _lowrank_noise(16, 16, 1e-4), 1e-6, 32, 0.05),
+    ("lowrank_d20_d01", lambda: _lowrank_noise(20, 20, 1e-5), 0.0, 32, 0.01),
+]
+
+
+@pytest.mark.parametrize("name,gen,eps,R,delta", DROP_CASES, ids=[c[0] for c in DROP_CASES])
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_decompose_dropoff_matches_oracle(name, gen, eps, R, delta, dt):
+    announce("decompose drop-off", name, dt)
+    x = gen()
+    if dt == torch.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    ref, info = tt.tt_svd(x, eps, R, return_info=True, delta=delta)
+    t = q.decompose(torch.tensor(x, dtype=dt, device=DEV), eps, R, delta=delta)
+    ranks = t.ranks_host()
+    # every decision of the cases is at least 1e-4 (relative) from its threshold
+    assert info["delta_margin"] > 1e-4 and info["margin"] > 1e-4
+    assert ranks == info["ranks"]
+    assert t.status_host() == 0
+    assert rel(q.full(t).cpu().numpy(), tt.tt_full(ref)) <= tol_for(dt, 1e-5)
+    for c in t.core_list()[:-1]:
+        U = c.reshape(-1, c.shape[2], order="F")
+        assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= (1e-10 if dt == torch.float64
+                                                                   else 1e-5)
+
+
+def test_decompose_dropoff_zero_and_off():
+    """A zero vector has no drop (0/0) and rank 1 everywhere; delta = 0 is qtt_decompose."""
+    announce("decompose drop-off zero/off")
+    t = q.decompose(torch.zeros(1 << 12, dtype=torch.float64, device=DEV), 0.0, 0, delta=0.5)
+    assert t.ranks_host() == [1] * 13 and t.status_host() == 0
+    assert not np.any(q.full(t).cpu().numpy())
+    x = torch.tensor(G.scatterers_1d(14, 2)[0], dtype=torch.float64, device=DEV)
+    a = q.decompose(x, 1e-4, 32)
+    b = q.decompose(x, 1e-4, 32, delta=0.0)
+    assert a.ranks_host() == b.ranks_host()
+    assert torch.equal(q.full(a), q.full(b))
+
+
 @pytest.mark.parametrize("kind,param", [("exp", 3.0), ("sin", 5.0), ("cos", 2.0), ("poly", 1),
                                         ("poly", 3)])
 @pytest.mark.parametrize("d", [10, 16])
