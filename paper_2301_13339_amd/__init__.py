@@ -320,10 +320,14 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
         eps_w = eps / 10.0
     dt = x.dtype
     # the kernel QTT does not depend on the samples: build it on a side
-    # stream while the signal is decomposed on the current one
+    # stream while the signal is decomposed on the current one.  The signal's
+    # sweep is the longer chain, so its launches are issued first (launching
+    # the kernel QTT first would hold the signal back by the host time of
+    # those launches).
     main = torch.cuda.current_stream(x.device)
     side = _side_stream(x.device)
     side.wait_stream(main)
+    f = decompose(x, eps, max_rank)
     with torch.cuda.stream(side):
         if shape2d is None:
             w = [kernel_sinc(int(x.numel()).bit_length() - 1, float(B), eps_w, dt, x.device)]
@@ -333,7 +337,6 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
             bx, by = B
             w = [kernel_sinc(dx, float(bx), eps_w, dt, x.device),
                  kernel_sinc(dy, float(by), eps_w, dt, x.device)]
-    f = decompose(x, eps, max_rank)
     main.wait_stream(side)
     for t in w:
         t.record_stream(main)
