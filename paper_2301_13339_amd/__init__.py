@@ -349,6 +349,32 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
     return out, dict(f=f, w=w, y=y, z=z)
 
 
+class PipelineGraph:
+    """``pipeline`` captured once into a HIP graph and replayed.
+
+    Every launch of the pipeline (both streams, all stages) is recorded on
+    the first call after an eager warm-up; ``run()`` replays the graph, so a
+    step costs one launch on the host.  ``x`` is the captured input buffer:
+    copy new samples into it (same shape and dtype) before ``run()``.  The
+    outputs (``out``, ``stages``) are the captured tensors, rewritten by
+    every replay.
+    """
+
+    def __init__(self, x: torch.Tensor, B, eps: float, max_rank: int = 0, **kw):
+        self.x = x
+        # warm-up: first-call kernel attributes, workspace sizes, side stream
+        pipeline(x, B, eps, max_rank, **kw)
+        torch.cuda.synchronize(x.device)
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self.out, self.stages = pipeline(x, B, eps, max_rank, **kw)
+        torch.cuda.synchronize(x.device)
+
+    def run(self) -> torch.Tensor:
+        self.graph.replay()
+        return self.out
+
+
 # ------------------------------------------------------------------ adjoint
 def toeplitz_apply(w: QTT, x: torch.Tensor, transpose: bool = False,
                    out: torch.Tensor | None = None) -> torch.Tensor:

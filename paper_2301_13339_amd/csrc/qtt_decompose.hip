@@ -840,6 +840,12 @@ __global__ void k_scale_last(T* cores, long long off, const int32_t* ranks, int 
   for (int e = threadIdx.x; e < 2 * rp; e += blockDim.x) cores[off + e] = (T)((double)cores[off + e] * s);
 }
 
+// clears the per-call flag words (a kernel rather than a memset node, so
+// that a captured graph replays it reliably)
+__global__ void k_zero_flags(int32_t* iflags, int n) {
+  if ((int)threadIdx.x < n) iflags[threadIdx.x] = 0;
+}
+
 __global__ void k_flag_status(const int32_t* iflags, int32_t* status) {
   if (threadIdx.x == 0 && status && iflags[0]) atomicOr(status, QTT_STATUS_NONFINITE);
 }
@@ -1216,7 +1222,11 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
     meta.caps[k] = k <= D ? P.cap[k] : 0;
     meta.offs[k] = k <= D ? out.off[k] : 0;
   }
-  QTT_HIP_CHECK(hipMemsetAsync(P.iflags, 0, sizeof(int32_t) * 16, stream));
+  {
+    ProbeScope _ps(QTT_K_OTHER, stream);
+    k_zero_flags<<<1, 64, 0, stream>>>(P.iflags, 16);
+  }
+  QTT_LAUNCH_CHECK();
   if (D == 1) {
     {
       ProbeScope _ps(QTT_K_OTHER, stream);

@@ -348,6 +348,29 @@ def test_pipeline_repeatable():
     assert torch.equal(a, b)
 
 
+def test_pipeline_graph_replays():
+    """The pipeline captured into a graph: every replay equals the eager result bitwise,
+    with eager pipelines between the replays, and new samples copied into the captured
+    input are picked up."""
+    announce("pipeline graph")
+    x = torch.tensor(G.scatterers_1d(16, 2)[0], device=DEV)
+    ref, _ = q.pipeline(x, 500.0, 1e-4, 32)
+    pg = q.PipelineGraph(x, 500.0, 1e-4, 32)
+    for _ in range(3):
+        out = pg.run()
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref)
+        q.pipeline(x, 500.0, 1e-4, 32)
+        torch.cuda.synchronize()
+    x2 = torch.tensor(G.scatterers_1d(16, 7)[0], device=DEV)
+    ref2, st2 = q.pipeline(x2, 500.0, 1e-4, 32)
+    x.copy_(x2)
+    out = pg.run()
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref2)
+    assert pg.stages["z"].ranks_host() == st2["z"].ranks_host()
+
+
 # ------------------------------------------------------------- error paths
 
 def test_binding_raises_on_bad_arguments():
