@@ -16,7 +16,11 @@ data tolerance.  Written as plain definitions:
 
 Readings: the kernel tolerance is ``eps_w = eps / 10`` unless given, the
 kernel decomposition is uncapped, and rounding is uncapped unless a cap is
-given.  For 2-D the image is row-major, the kernel separable, and each axis
+given.  With the singular-value drop-off of modification (3) (``delta > 0``)
+the cut applies to the data decomposition and to the rounding, the
+rounding standing in for the truncations inside QTT-FFT/QTT-iFFT that
+Section 5 gives the same threshold; the kernel decomposition keeps its
+tolerance rule.  For 2-D the image is row-major, the kernel separable, and each axis
 has its own generator (column axis first in the QTT index order).
 """
 
@@ -40,14 +44,15 @@ def _toeplitz(f, w, fft):
 
 def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None = None,
                 round_max_rank: int = 0, fft: bool | None = None, sketch_ell: int = 0,
-                sketch_seed: int = 0):
+                sketch_seed: int = 0, delta: float = 0.0):
     """Run the composed pipeline on a 1-D signal of length ``2**d``.
 
     ``fft`` selects the DFT route for the exact convolution (default: on for
     ``d > 14``); both routes compute the same sum.  ``sketch_ell > 0`` takes
     the rounding's truncated SVDs from Algorithms 4 and 5 (``ell`` columns,
-    ``sketch_seed``).  Returns a dict with the cores, the intermediate full
-    arrays, ranks and the output.
+    ``sketch_seed``); ``delta > 0`` adds the drop-off cut (exact rounding
+    only).  Returns a dict with the cores, the intermediate full arrays,
+    ranks and the output.
     """
     x = np.asarray(x, dtype=np.float64).ravel()
     d = tt.log2_exact(x.size)
@@ -55,7 +60,7 @@ def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None 
         eps_w = eps / 10.0
     if fft is None:
         fft = d > 14
-    F, finfo = tt.tt_svd(x, eps, max_rank, return_info=True)
+    F, finfo = tt.tt_svd(x, eps, max_rank, return_info=True, delta=delta)
     f_t = tt.tt_full(F)
     w = conv.toeplitz_generator(d, B)
     W, winfo = tt.tt_svd(w, eps_w, 0, return_info=True)
@@ -65,7 +70,7 @@ def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None 
         Z, zinfo = rsvd.tt_svd_sketch(y, eps, round_max_rank, sketch_ell, sketch_seed,
                                       return_info=True)
     else:
-        Z, zinfo = tt.tt_svd(y, eps, round_max_rank, return_info=True)
+        Z, zinfo = tt.tt_svd(y, eps, round_max_rank, return_info=True, delta=delta)
     out = tt.tt_full(Z)
     return dict(F=F, W=W, Z=Z, f_tilde=f_t, w=w, w_tilde=w_t, y=y, out=out,
                 F_ranks=finfo["ranks"], W_ranks=winfo["ranks"], Z_ranks=zinfo["ranks"],

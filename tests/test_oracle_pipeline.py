@@ -120,3 +120,22 @@ def test_generator_dB_central_differences():
     d, B, h = 7, 30.0, 1e-6
     fd = (conv.toeplitz_generator(d, B + h) - conv.toeplitz_generator(d, B - h)) / (2 * h)
     assert np.allclose(grads.generator_dB(d, B), fd, rtol=0, atol=1e-8)
+
+
+def test_pipeline_dropoff_composition():
+    """Modification (3) in the pipeline: the data decomposition and the rounding take the
+    drop-off cut (their ranks are the rule applied to their own spectra), the kernel keeps
+    the tolerance rule, and delta = 0 is the plain pipeline."""
+    K = 12
+    noisy, clean, _, _ = G.paper_example1(K, 0, full_grid=True)
+    B = (1 << K) / 4.0
+    res = pipeline.pipeline_1d(noisy, B, 0.0, delta=0.02)
+    plain = pipeline.pipeline_1d(noisy, B, 0.0)
+    assert res["W_ranks"] == plain["W_ranks"]
+    for info, ranks in ((res["F_info"], res["F_ranks"]), (res["Z_info"], res["Z_ranks"])):
+        for k, s in enumerate(info["sv"], start=1):
+            rd = tt.dropoff_rank(s, 0.02)
+            assert ranks[k] == (rd if rd is not None else tt.truncation_rank(s, 0.0, 0))
+    same = pipeline.pipeline_1d(noisy, B, 1e-3, delta=0.0)
+    ref = pipeline.pipeline_1d(noisy, B, 1e-3)
+    assert np.array_equal(same["out"], ref["out"])
