@@ -259,12 +259,19 @@ _METHODS = {"exact": QTT_ROUND_EXACT, "sketch_f32": QTT_ROUND_SKETCH_F32,
 
 
 def round(y: QTT, eps: float, max_rank: int = 0, method: str = "exact", seed: int = 0,  # noqa: A001
-          ell: int | None = None) -> QTT:
+          ell: int | None = None, delta: float = 0.0) -> QTT:
     """TT-rounding of ``y`` at tolerance ``eps``.
 
     ``method``: ``"exact"``, ``"sketch_f32"`` or ``"sketch_bf16"`` (the
     randomised form; ``ell`` columns, default ``QTT_SKETCH_ELL``).
+    ``delta > 0`` (exact method only) adds the singular-value drop-off cut:
+    Full of ``y`` followed by ``qtt_decompose_dropoff``, the same two stages
+    ``qtt_round`` runs.
     """
+    if delta:
+        if method != "exact":
+            raise ValueError("the drop-off cut is available for the exact rounding only")
+        return decompose(full(y), eps, max_rank, delta=delta)
     m = _METHODS[method]
     ycap = (ctypes.c_int32 * (y.d + 1))(*y.cap)
     zcap = (ctypes.c_int32 * (y.d + 1))()
@@ -310,11 +317,13 @@ def full(t: QTT, out: torch.Tensor | None = None) -> torch.Tensor:
 
 def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | None = None,
              round_method: str = "exact", round_max_rank: int = 0, shape2d=None,
-             sketch_ell: int | None = None, sketch_seed: int = 0):
+             sketch_ell: int | None = None, sketch_seed: int = 0, delta: float = 0.0):
     """Decompose, build the kernel QTT, convolve, round and reconstruct.
 
     ``B`` is one bandwidth (signal) or ``(Bx, By)`` with ``shape2d = (ny, nx)``
-    for a row-major image.  Returns ``(out, stages)``.
+    for a row-major image.  ``delta > 0`` applies the singular-value drop-off
+    cut to the data decomposition and to the rounding.  Returns ``(out,
+    stages)``.
     """
     if eps_w is None:
         eps_w = eps / 10.0
@@ -327,7 +336,7 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
     main = torch.cuda.current_stream(x.device)
     side = _side_stream(x.device)
     side.wait_stream(main)
-    f = decompose(x, eps, max_rank)
+    f = decompose(x, eps, max_rank, delta=delta)
     with torch.cuda.stream(side):
         if shape2d is None:
             w = [kernel_sinc(int(x.numel()).bit_length() - 1, float(B), eps_w, dt, x.device)]
@@ -342,7 +351,7 @@ def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | N
         t.record_stream(main)
     am = [f.d] if shape2d is None else [dx, dy]
     y = conv(f, w, am)
-    z = round(y, eps, round_max_rank, round_method, sketch_seed, sketch_ell)
+    z = round(y, eps, round_max_rank, round_method, sketch_seed, sketch_ell, delta=delta)
     out = full(z)
     if shape2d is not None:
         out = out.reshape(shape2d)
