@@ -230,10 +230,13 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
 #ifdef QTT_EIG_TIMING
   tt[3] = wall_clock64();
 #endif
-  // pv .. pv + 7 kMaxM (pv, e2, la and the arrays after) are free now
+  // pv .. sx + kEigNrmSlot (pv, e2, la and the arrays after) are free now
   if (E <= 64) {
-    // A holds Q^T of the reduction (sy_tridiag64)
-    const bool done = mgs_backtr64(A, E, lda, V, lda, r, pv, iscr + 3);
+    // A holds Q^T of the reduction (sy_tridiag64); vectors that are
+    // orthonormal to first order take one polishing step, others (or more
+    // than 32) Gram-Schmidt
+    const bool done = (r <= 32 && polish_backtr64(A, E, lda, V, r, pv)) ||
+                      mgs_backtr64(A, E, lda, V, lda, r, pv, iscr + 3);
 #ifdef QTT_EIG_TIMING
     tt[4] = wall_clock64();
 #endif

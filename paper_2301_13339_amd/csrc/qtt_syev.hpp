@@ -466,6 +466,89 @@ __device__ void backtr_gemm64(MP X, int E, int lda, MP Z, int r) {
 // x summed over the four DPP rows at the same position, in every lane
 __device__ __forceinline__ double sum_rows4(double x) { return sum_halves(sum_row_pairs(x)); }
 
+// Orthonormalisation of the r <= 32 kept eigenvectors of T (columns of Z,
+// E <= 64 rows) when they are already orthonormal to first order, then
+// Z <- Q Z (backtr_gemm64).  Vectors from the twisted factorisation are
+// orthogonal to about u ||T|| / gap; with C = Z^T Z and D = C - I, one
+// Newton-Schulz step Z <- Z (3I - C) / 2 leaves an error of order ||D||^2,
+// so for max |D| <= 1e-8 it restores orthonormality to rounding level at the
+// cost of two small products on the matrix cores.  Otherwise (clustered
+// eigenvalues) the routine returns false with Z untouched and the caller
+// takes the Gram-Schmidt path.  All threads; cs: >= 32 * 32 + 8 doubles.
+template <class MP>
+__device__ bool polish_backtr64(MP A, int E, int lda, MP Z, int r, ldsd cs) {
+  constexpr int LC = 32;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  ldsd S = cs;               // C, then (3I - C) / 2, r x r (stride LC)
+  ldsd dev = cs + 32 * LC;  // per-wave max |C - I|
+  const int nb = (r + 15) >> 4;  // <= 2
+  double dmax = 0.0;
+  for (int blk = w; blk < nb * nb; blk += 4) {  // <= 4 blocks: one per wave
+    const int bi = blk / nb, bj = blk - bi * nb;
+    syev_f64x4 acc = syev_f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < E; k0 += 4) {
+      const int c = k0 + lk;
+      const bool cin = c < E;
+      const int cc = cin ? c : 0;
+      const double a = Z[cc * lda + 16 * bi + lr], bz = Z[cc * lda + 16 * bj + lr];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cin ? a : 0.0, cin ? bz : 0.0, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * bi + 4 * e + lk, j = 16 * bj + lr;
+      if (i < r && j < r) {
+        const double d = acc[e] - (i == j ? 1.0 : 0.0);
+        dmax = fmax(dmax, fabs(d));
+        if (!(d == d)) dmax = 1.0;  // NaN
+        S[i * LC + j] = (i == j ? 1.0 : 0.0) - 0.5 * d;
+      }
+    }
+  }
+  dmax = max64(dmax);
+  if (l == 0) dev[w] = dmax;
+  __syncthreads();
+  const double dm = fmax(fmax(dev[0], dev[1]), fmax(dev[2], dev[3]));
+  if (!(dm <= 1e-8)) return false;  // uniform; Z untouched
+  // Z' = Z S: 16 x 16 blocks (row block rb < 4, column block cb < nb) over the waves
+  syev_f64x4 zo[2];
+  const int nrb = (E + 15) >> 4;
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    zo[t] = syev_f64x4{0.0, 0.0, 0.0, 0.0};
+    const int blk = w + 4 * t;
+    if (blk >= nrb * nb) continue;  // uniform
+    const int rb = blk / nb, cb = blk - rb * nb;
+    const int row = 16 * rb + lr;
+    const bool rin = row < E;
+    const int rr = rin ? row : 0;
+    for (int k0 = 0; k0 < r; k0 += 4) {
+      const int kk = k0 + lk;
+      const bool kin = kk < r;
+      const int kc = kin ? kk : 0;
+      const double a = Z[rr * lda + kc];
+      const double b = S[kc * LC + 16 * cb + lr];
+      zo[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((rin & kin) ? a : 0.0, kin ? b : 0.0, zo[t],
+                                                   0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave has read Z
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int blk = w + 4 * t;
+    if (blk >= nrb * nb) continue;
+    const int rb = blk / nb, cb = blk - rb * nb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * rb + 4 * e + lk, j = 16 * cb + lr;
+      if (i < E && j < r) Z[i * lda + j] = zo[t][e];
+    }
+  }
+  __syncthreads();
+  backtr_gemm64(A, E, lda, Z, r);
+  return true;
+}
+
 // Modified Gram-Schmidt of the r kept eigenvectors of T (columns 0..r-1 of
 // Z, E <= 64 rows, r <= 64) in registers, followed by Z <- Q Z with the
 // accumulated Q^T of sy_tridiag64 in A.  Column b lives in wave b / 16, in the
