@@ -312,7 +312,7 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
 #endif
     const int r =
         solve_and_truncate<NT>(lds(A), lds(V), m, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
-                               tau2, meta.caps[k], k, so);
+                               tau2, meta.caps[k], k, so, true);
 #ifdef QTT_EIG_TIMING
     const long long ls2 = wall_clock64();
 #endif
@@ -578,7 +578,7 @@ __device__ int eig_step_solve(MP A, MP V, int lda, ldsd lam, ldsd sx, ldsi perm,
   const int tid = threadIdx.x;
   const int rp = M / 2;
   const int r =
-      solve_and_truncate<NT, true>(A, V, M, lda, sx, iscr, lam, perm, tau2, cap_k, k, so);
+      solve_and_truncate<NT, true>(A, V, M, lda, sx, iscr, lam, perm, tau2, cap_k, k, so, true);
   for (int e = tid; e < M * r; e += NT) {
     const int c = e / r, b = e - c * r;
     umat[e] = V[c * lda + perm[b]];
@@ -728,7 +728,7 @@ __device__ void tail_steps(double* smem, const T* Xin, double B, int nk, int k0,
 #endif
     const int r =
         solve_and_truncate<NT>(lds(A), lds(V), E, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
-                               tau2, meta.caps[k], k, so);
+                               tau2, meta.caps[k], k, so, !dual);
 #ifdef QTT_EIG_TIMING
     const long long ts2 = wall_clock64();
 #endif

@@ -125,10 +125,41 @@ constexpr int kEigNrmSlot = kEigScratch - 8;  // sx[kEigNrmSlot]: Gershgorin bou
 // ~470 with 16 on gfx950, and every eigen step is barrier/latency bound
 constexpr int kEigThreads = 256;
 
+// Number of eigenvalues of T (diagonal dg, off-diagonal od) below x, by one
+// thread: the Sturm sequence of the leading minors of T - xI on T scaled by
+// 1 / nrm, rescaled by powers of two every 8 steps (as sturm_counts).
+__device__ inline int sturm_below(lds_ptr<const double> dg, lds_ptr<const double> od, int E,
+                                  double x, double nrm) {
+  const double sc = 1.0 / nrm, xs = x * sc;
+  double pm = 1.0, pc = dg[0] * sc - xs;
+  int c = sign_change(pc, 1.0);
+  for (int i = 1; i < E; ++i) {
+    const double b = od[i - 1] * sc;
+    const double pn = fma(dg[i] * sc - xs, pc, -fmax(b * b, 1e-60) * pm);
+    c += sign_change(pn, pc);
+    pm = pc;
+    pc = pn;
+    if ((i & 7) == 0) {
+      const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pc), fabs(pm)));
+      pc = ldexp(pc, -ex);
+      pm = ldexp(pm, -ex);
+    }
+  }
+  return c;
+}
+
+// any_basis: the caller uses only the kept columns of V as a basis (not the
+// eigenvalues, and not the vectors as singular vectors).  Then a step whose
+// rank is E by the rule (the smallest eigenvalue above tau2, the cap not
+// binding, no drop-off cut, no singular values wanted) keeps V = I: the
+// step is exact whatever orthonormal basis it keeps, so the eigenvalues and
+// vectors are not computed.  One Sturm count at a point a little above tau2
+// that finds no eigenvalue below it settles the rank; otherwise the full path
+// decides as usual.
 template <int NT, bool BIG = false, class MP>
 __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr, ldsd lam,
                                   ldsi perm, double tau2, int cap, int k,
-                                  const StepOut& so) {
+                                  const StepOut& so, bool any_basis = false) {
   const int tid = threadIdx.x;
   ldsd dg = sx;
   ldsd od = dg + kMaxM;
@@ -172,6 +203,26 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
     tt[1] = wall_clock64();
 #endif
     tnrm = tridiag_gersh(dg, od, E, sx + kEigNrmSlot);
+    if (any_basis && !so.sv && !(so.delta2 > 0.0) && cap >= E && tnrm > 0.0) {
+      if (tid == 0) iscr[4] = sturm_below(dg, od, E, tau2 * (1.0 + 1e-6) + 1e-12 * tnrm, tnrm);
+      __syncthreads();
+      if (iscr[4] == 0) {  // uniform: rank E, any orthonormal basis
+        for (int i = tid; i < E; i += NT) {
+          lam[i] = 0.0;
+          perm[i] = i;
+        }
+        for (int idx = tid; idx < E * E; idx += NT) {
+          const int a = idx / E, c = idx - a * E;
+          V[a * lda + c] = (a == c) ? 1.0 : 0.0;
+        }
+        if (tid == 0) {
+          iscr[2] = E;
+          so.ranks[k] = E;
+        }
+        __syncthreads();
+        return E;
+      }
+    }
     tridiag_eigvals<NT>(dg, od, E, la, e2, pv, tnrm, K);
   }
 #ifdef QTT_EIG_TIMING
