@@ -4,17 +4,22 @@
 //
 //   1. Householder tridiagonalisation G = Q T Q^T (the reflector of step j
 //      annihilates column j below the subdiagonal; two barriers per step);
-//   2. all eigenvalues of T by parallel multisection: a 16-lane group brackets
-//      one eigenvalue and narrows it 17-fold per iteration with Sturm counts
-//      (sign changes of the leading principal minors of T - x I), to an
-//      absolute width of 1e-15 ||T||;
+//      for orders up to 64 Q^T is accumulated alongside in registers;
+//   2. eigenvalues of T by parallel multisection with Sturm counts (sign
+//      changes of the leading principal minors of T - x I): a lane group
+//      brackets one eigenvalue and narrows it (G+1)-fold per pass, to a
+//      width of about 1e-16 ||T||; when the rank cap binds only the cap
+//      largest are computed;
 //   3. the caller picks the rank from the eigenvalues;
-//   4. eigenvectors of T for the kept eigenvalues only, one lane each, by a
-//      twisted factorisation of T - lambda I (top-down and bottom-up LDL^T
-//      sweeps; the twist index minimises |gamma_r|; the vector follows from
-//      the two bidiagonal factors), then modified Gram-Schmidt;
-//   5. back-transformation by the stored reflectors: U = Q Z.
-// All work is on the 2^m-entry LDS arrays of one workgroup; no global memory.
+//   4. eigenvectors of T for the kept eigenvalues only by a twisted
+//      factorisation of T - lambda I (top-down and bottom-up LDL^T sweeps;
+//      the twist index minimises |gamma_r|), then orthonormalised: one
+//      Newton-Schulz step on the matrix cores when they are orthonormal to
+//      first order, modified Gram-Schmidt otherwise;
+//   5. back-transformation U = Q Z (one matrix-core product for orders up to
+//      64, the stored reflectors above).
+// Orders up to 64 work on LDS arrays of one workgroup; larger ones keep A and
+// V in global scratch.
 #pragma once
 
 #include "qtt_internal.hpp"
