@@ -209,6 +209,44 @@ def test_decompose_closed_forms(kind, param, d):
     assert rel(q.full(t).cpu().numpy(), x) <= 1e-6
 
 
+@pytest.mark.parametrize("kind,d,dt", [("exp", 28, torch.float64), ("sin", 27, torch.float64),
+                                        ("exp", 28, torch.float32)])
+def test_decompose_large_closed_form(kind, d, dt):
+    """Largest sizes (2^27..2^28 samples, up to 2 GiB): the samples are made on the
+    device, the ranks are the closed-form ones (1 for exp, at most 2 for sin) and
+    sampled entries, each a product of core slices on the host, match the function
+    (sin: within the error bound of Algorithm 1)."""
+    announce("large closed form", kind, d, dt)
+    n = 1 << d
+    xs = torch.arange(n, device=DEV, dtype=torch.float64) / n
+    x = torch.exp(0.7 * xs) if kind == "exp" else torch.sin(2 * math.pi * 3 * xs + 0.3)
+    x = x.to(dt)
+    del xs
+    # Gram sums over 2^28 samples resolve singular values only down to about
+    # sqrt(u n) of the norm, so the tolerance stays well above that floor
+    eps = 1e-4
+    t = q.decompose(x, eps)
+    ranks = t.ranks_host()
+    assert t.status_host() == 0
+    cores = t.core_list()
+    idx = np.random.default_rng(d).integers(0, n, 2000)
+    xh = x[torch.tensor(idx, device=DEV)].double().cpu().numpy()
+    got = np.array([tt.tt_entry(cores, int(i)) for i in idx])
+    if kind == "exp":
+        # rank 1 at every unfolding: only rounding is discarded
+        assert max(ranks) == 1
+        tol = 1e-10 if dt == torch.float64 else 2e-5
+        assert np.max(np.abs(got - xh)) <= tol * np.max(np.abs(xh))
+    else:
+        # rank <= 2; at the finest bits sigma_2 / sigma_1 falls below eps and the
+        # rule keeps rank 1, within the bound ||x - x_TT|| <= eps ||x|| (here on
+        # the RMS of the sampled entries)
+        assert max(ranks) == 2
+        rms_err = float(np.sqrt(np.mean((got - xh) ** 2)))
+        assert rms_err <= 1.5 * eps * float(np.sqrt(np.mean(xh ** 2)))
+    del x
+
+
 def test_decompose_zero_vector():
     announce("zero vector")
     t = q.decompose(torch.zeros(1 << 15, dtype=torch.float64, device=DEV), 1e-3)
