@@ -16,6 +16,7 @@ Modules
 ``pipeline``  the composed pipeline (Algorithm 2 with an exact convolution
               and TT-rounding), the error metric (7.1).
 ``rsvd``      range finder and randomized SVD (Algorithms 4 and 5).
+``ttm``       TT-SVD and max-rank TT-RSVD for mode sizes other than 2.
 ``grads``     gradients of the convolution + reconstruction loss.
 
 Readings of passages that are ambiguous or garbled are listed in each
