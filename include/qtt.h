@@ -153,6 +153,40 @@ int qtt_decompose_dropoff(const void* x, int d, int dtype, double eps, double de
                           qtt_tensor* out, double* sv, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * TT-SVD and max-rank TT-RSVD of a tensor with K modes of size M (Section 5,
+ * modifications (1) and (2); Algorithms 1, 4 and 5), FP64.  The tensor is the
+ * vector x of M^K entries with index i = i_1 + M (i_2 + M (...)); step k
+ * unfolds the remainder column-major into m_k = M r_{k-1} rows and
+ * n_k = M^(K-k) columns.
+ *   K, M        modes (1 <= K <= QTT_MAXD) and mode size (2..64), M^K <= 2^31
+ *   max_rank    rank cap R (0 = QTT_MAX_RANK); the effective cap is lowered
+ *               to 128 / M so that every unfolding has at most 128 rows
+ *   method      0: exact truncated SVDs (Gram matrix and the FP64
+ *               eigensolver); 1: max-rank TT-RSVD, the step's SVD taken by
+ *               the range finder with ell = R + oversample columns
+ *               (R + oversample <= 64, max_rank > 0), reverting to the exact
+ *               step where min(M cap_{k-1}, n_k) <= ell
+ *   seed        Omega[row][col] of step k is the standard normal of
+ *               Philox-4x32-10 with counter (row, col, k, 0) and key
+ *               (seed mod 2^32, seed >> 32), Box-Muller of its first two words
+ * Outputs (query): cap[0..K] = min(M^k, M^(K-k), effective cap), the
+ * workspace size and the number of core elements.
+ * Call: x (device, read only); cap = the query's capacities; ranks (device,
+ * K+1 int32) receives r_0..r_K; cores (device) receives core k (1-based) as
+ * C-contiguous (r_{k-1}, M, r_k) with the actual ranks, at element offset
+ * sum_{j<k} cap[j-1] M cap[j].  The rank of step k is Algorithm 1's rule at
+ * eps (tau = eps ||x|| / sqrt(K-1)) on the step's singular values, then the
+ * cap.  Errors: QTT_EINVAL for invalid arguments or capacities other than the
+ * query's, QTT_ENOSPC for a short workspace.
+ */
+int qtt_query_decompose_modes(int K, int M, int max_rank, int method, int oversample,
+                              int32_t* cap, size_t* ws_bytes, size_t* core_elems);
+int qtt_decompose_modes(const double* x, int K, int M, double eps, int max_rank, int method,
+                        int oversample, uint64_t seed, const int32_t* cap, int32_t* ranks,
+                        double* cores, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * QTT of the Toeplitz generator of the normalised sinc kernel./*
  * QTT of the Toeplitz generator of the normalised sinc kernel.
  * For N = 2^d the kernel is g_m = sinc(B x_m)/Z on x_m = -1/2 + m/N
  * (sinc(t) = sin(pi t)/(pi t), kernel (7.2) with B = 1/Delta_x and Z the

@@ -209,6 +209,62 @@ def decompose(x: torch.Tensor, eps: float, max_rank: int = 0, return_sv: bool = 
     return (out, sv) if return_sv else out
 
 
+class TTModes:
+    """A TT with K modes of size M (FP64): flat ``cores`` at the query's
+    capacity offsets, ``ranks`` (K+1 int32) on the device."""
+
+    def __init__(self, K: int, M: int, cap, device):
+        self.K, self.M, self.cap = K, M, list(cap)
+        self.device = torch.device(device)
+        n = sum(self.cap[k] * M * self.cap[k + 1] for k in range(K))
+        self.cores = torch.zeros(n, dtype=torch.float64, device=self.device)
+        self.ranks = torch.zeros(K + 1, dtype=torch.int32, device=self.device)
+
+    def ranks_host(self):
+        return [int(v) for v in self.ranks.cpu()]
+
+    def core_list(self):
+        """Cores as CPU float64 arrays of shape ``(r_{k-1}, M, r_k)``."""
+        r = self.ranks_host()
+        flat = self.cores.cpu().numpy()
+        out, off = [], 0
+        for k in range(self.K):
+            n = r[k] * self.M * r[k + 1]
+            out.append(flat[off:off + n].reshape(r[k], self.M, r[k + 1]).copy())
+            off += self.cap[k] * self.M * self.cap[k + 1]
+        return out
+
+
+def decompose_modes(x: torch.Tensor, M: int, eps: float, max_rank: int = 0, method: str = "svd",
+                    oversample: int = 10, seed: int = 0) -> TTModes:
+    """TT-SVD (``method="svd"``) or max-rank TT-RSVD (``"rsvd"``) of ``x`` read as a
+    tensor with modes of size ``M`` (``x.numel() == M**K``, first mode fastest)."""
+    if not x.is_cuda or x.dtype != torch.float64:
+        raise ValueError("decompose_modes expects a float64 device tensor")
+    x = x.contiguous().reshape(-1)
+    K, n = 0, 1
+    while n < x.numel():
+        n *= M
+        K += 1
+    if n != x.numel() or K < 1:
+        raise ValueError("the length must be a power of the mode size")
+    meth = {"svd": 0, "rsvd": 1}[method]
+    cap = (ctypes.c_int32 * (K + 1))()
+    ws = ctypes.c_size_t()
+    _check(lib().qtt_query_decompose_modes(K, int(M), int(max_rank), meth, int(oversample), cap,
+                                           ctypes.byref(ws), None), "qtt_query_decompose_modes")
+    out = TTModes(K, int(M), list(cap), x.device)
+    w = _workspace(ws.value, x.device)
+    _check(lib().qtt_decompose_modes(ctypes.c_void_p(x.data_ptr()), K, int(M), float(eps),
+                                     int(max_rank), meth, int(oversample), ctypes.c_uint64(seed),
+                                     cap, ctypes.c_void_p(out.ranks.data_ptr()),
+                                     ctypes.c_void_p(out.cores.data_ptr()),
+                                     ctypes.c_void_p(w.data_ptr()), ws.value, _stream(x.device)),
+           "qtt_decompose_modes")
+    out._keep = [w, x]
+    return out
+
+
 def kernel_sinc(d: int, B: float, eps_w: float, dtype=torch.float64, device="cuda") -> QTT:
     """QTT (``d+1`` modes) of the normalised sinc Toeplitz generator of a ``2**d`` grid."""
     dt = _DT[dtype]

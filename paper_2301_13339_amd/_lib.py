@@ -23,6 +23,7 @@ lib_path = os.path.join(HERE, "libqtt.so")
 EXPORTS = [
     "qtt_core_elems", "qtt_strerror", "qtt_last_hip_error",
     "qtt_query_decompose", "qtt_decompose", "qtt_decompose_dropoff", "qtt_kernel_sinc",
+    "qtt_query_decompose_modes", "qtt_decompose_modes",
     "qtt_query_conv", "qtt_conv",
     "qtt_query_round", "qtt_round", "qtt_query_round_sketch", "qtt_round_sketch",
     "qtt_query_full", "qtt_full",
@@ -84,6 +85,13 @@ def _declare(L):
     L.qtt_decompose_dropoff.argtypes = [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                         ctypes.c_double, ctypes.c_int, _TP, _VP, _VP,
                                         ctypes.c_size_t, _VP]
+    L.qtt_query_decompose_modes.restype = ctypes.c_int
+    L.qtt_query_decompose_modes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                            ctypes.c_int, _I32P, _SZP, _SZP]
+    L.qtt_decompose_modes.restype = ctypes.c_int
+    L.qtt_decompose_modes.argtypes = [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
+                                      _I32P, _VP, _VP, _VP, ctypes.c_size_t, _VP]
     L.qtt_kernel_sinc.restype = ctypes.c_int
     L.qtt_kernel_sinc.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   _TP, _VP, ctypes.c_size_t, _VP]

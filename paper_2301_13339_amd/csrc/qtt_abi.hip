@@ -200,6 +200,54 @@ int qtt_decompose_dropoff(const void* x, int d, int dtype, double eps, double de
   return decompose_common(src, d, dtype, eps, max_rank, out, sv, ws, ws_bytes, stream, delta);
 }
 
+// ------------------------------------------------------ general mode sizes
+static int modes_args_ok(int K, int M, int max_rank, int method, int oversample) {
+  if (K < 1 || M < 2 || M > kModesMaxM || max_rank < 0 || (method != 0 && method != 1))
+    return 0;
+  double n = 1.0;
+  for (int k = 0; k < K; ++k) n *= M;
+  if (n > 2147483648.0) return 0;  // at most 2^31 entries
+  if (method == 1) {
+    int32_t cap[QTT_MAXD + 1];
+    if (K > QTT_MAXD) return 0;
+    const int R = modes_caps(K, M, max_rank, cap);
+    if (max_rank <= 0 || oversample < 0 || R + oversample > 64) return 0;
+  }
+  return K <= QTT_MAXD;
+}
+
+int qtt_query_decompose_modes(int K, int M, int max_rank, int method, int oversample,
+                              int32_t* cap, size_t* ws_bytes, size_t* core_elems) {
+  if (!modes_args_ok(K, M, max_rank, method, oversample)) return QTT_EINVAL;
+  int32_t c[QTT_MAXD + 1];
+  modes_caps(K, M, max_rank, c);
+  if (cap) memcpy(cap, c, sizeof(int32_t) * (K + 1));
+  if (ws_bytes) *ws_bytes = modes_ws_bytes(K, M, method, oversample);
+  if (core_elems) {
+    size_t e = 0;
+    for (int k = 0; k < K; ++k) e += (size_t)c[k] * M * c[k + 1];
+    *core_elems = e;
+  }
+  return QTT_OK;
+}
+
+int qtt_decompose_modes(const double* x, int K, int M, double eps, int max_rank, int method,
+                        int oversample, uint64_t seed, const int32_t* cap, int32_t* ranks,
+                        double* cores, void* ws, size_t ws_bytes, void* stream) {
+  if (!x || !cap || !ranks || !cores || !ws || !(eps >= 0.0) || !isfinite(eps) ||
+      !modes_args_ok(K, M, max_rank, method, oversample))
+    return QTT_EINVAL;
+  if (ws_bytes < modes_ws_bytes(K, M, method, oversample)) return QTT_ENOSPC;
+  int32_t need[QTT_MAXD + 1];
+  modes_caps(K, M, max_rank, need);
+  for (int k = 0; k <= K; ++k)
+    if (cap[k] < need[k]) return QTT_ENOSPC;
+  for (int k = 0; k <= K; ++k)
+    if (cap[k] != need[k]) return QTT_EINVAL;  // the core offsets follow the query's capacities
+  return run_decompose_modes(x, K, M, eps, method, oversample, seed, cap, ranks, cores, ws,
+                             static_cast<hipStream_t>(stream));
+}
+
 int qtt_kernel_sinc(int d, double B, double eps_w, int dtype, qtt_tensor* w_out, void* ws,
                     size_t ws_bytes, void* stream) {
   if (d < 1 || d > kMaxModes || !(B > 0.0) || !isfinite(B)) return QTT_EINVAL;

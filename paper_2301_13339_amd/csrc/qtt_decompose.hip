@@ -199,6 +199,15 @@ __global__ void __launch_bounds__(256) k_reduce(const double* partials, int pstr
   }
 }
 
+// k_reduce for other translation units (out[e] = sum_b partials[b * pstride + e])
+int launch_reduce(const double* partials, int pstride, int nparts, int count, double* out,
+                  hipStream_t s) {
+  k_reduce<<<(count + 63) / 64, 256, 0, s>>>(partials, pstride, nparts, count, out, nullptr,
+                                             nullptr);
+  QTT_LAUNCH_CHECK();
+  return QTT_OK;
+}
+
 // ------------------------------------------------------ small LDS products
 // C (M x N) = A (M x K) B (K x N) with all operands in LDS: A(i, k) =
 // A[i*ai + k*ak], B(k, j) = B[k*bk + j*bj].  The 256 threads form a 16 x 16

@@ -182,6 +182,18 @@ int run_batch_decompose(int dtype, int gen, const void* x, const BatchTask* task
                         char* wscr, long long wstride, long long nmax, int nwg, hipStream_t s);
 size_t batch_decompose_lds();
 
+int launch_reduce(const double* partials, int pstride, int nparts, int count, double* out,
+                  hipStream_t s);
+
+// ------------------------------------------------------ general mode sizes
+// TT-SVD / max-rank TT-RSVD of a tensor with K modes of size M (FP64)
+constexpr int kModesMaxM = 64;    // largest mode size
+int modes_caps(int K, int M, int max_rank, int32_t* cap);
+size_t modes_ws_bytes(int K, int M, int method, int oversample);
+int run_decompose_modes(const double* x, int K, int M, double eps, int method, int oversample,
+                        uint64_t seed, const int32_t* cap, int32_t* ranks, double* cores,
+                        void* ws, hipStream_t s);
+
 // --------------------------------------------------------------- other ops
 int plan_full(int d, const int32_t* cap, int dtype, void* ws, size_t* ws_bytes, void** bufs);
 int run_full(const TensorDev& t, int dtype, void* out, void* ws, hipStream_t stream);

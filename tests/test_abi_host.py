@@ -98,6 +98,39 @@ def test_calls_validate_before_launching():
                               None) == -1
 
 
+def test_modes_query_and_validation():
+    L = _lib()
+    so = L.lib()
+    cap = (ctypes.c_int32 * 9)()
+    ws = ctypes.c_size_t()
+    ne = ctypes.c_size_t()
+    assert so.qtt_query_decompose_modes(8, 10, 10, 1, 10, cap, ctypes.byref(ws),
+                                        ctypes.byref(ne)) == 0
+    assert list(cap) == [1, 10, 10, 10, 10, 10, 10, 10, 1]
+    assert ne.value == 2 * 10 * 10 + 6 * 10 * 10 * 10
+    assert ws.value >= 2 * 10 ** 8 * 8            # two remainder buffers of 10^8 doubles
+    # the cap is lowered so that unfoldings keep <= 128 rows
+    assert so.qtt_query_decompose_modes(4, 6, 0, 0, 0, cap, None, None) == 0
+    assert list(cap)[:5] == [1, 6, 21, 6, 1]
+    bad = [(0, 10, 10, 0, 0), (8, 1, 10, 0, 0), (8, 65, 10, 0, 0), (8, 10, 0, 1, 10),
+           (8, 10, 10, 1, 60), (8, 10, 10, 2, 0), (10, 10, 10, 0, 0)]   # 10^10 > 2^31
+    for K, M, R, meth, p in bad:
+        assert so.qtt_query_decompose_modes(K, M, R, meth, p, cap, None, None) == -1, (K, M)
+    fake = ctypes.c_void_p(0x1000)
+    so.qtt_query_decompose_modes(3, 4, 0, 0, 0, cap, ctypes.byref(ws), None)
+    # null input, NaN tolerance, short workspace, capacities other than the query's
+    assert so.qtt_decompose_modes(None, 3, 4, 1e-3, 0, 0, 0, 0, cap, fake, fake, fake,
+                                  ws.value, None) == -1
+    assert so.qtt_decompose_modes(fake, 3, 4, float("nan"), 0, 0, 0, 0, cap, fake, fake, fake,
+                                  ws.value, None) == -1
+    assert so.qtt_decompose_modes(fake, 3, 4, 1e-3, 0, 0, 0, 0, cap, fake, fake, fake,
+                                  ws.value - 1, None) == -2
+    cap2 = (ctypes.c_int32 * 4)(*cap[:4])
+    cap2[1] = cap[1] + 1
+    assert so.qtt_decompose_modes(fake, 3, 4, 1e-3, 0, 0, 0, 0, cap2, fake, fake, fake,
+                                  ws.value, None) == -1
+
+
 def test_conv_and_round_validation():
     L = _lib()
     so = L.lib()

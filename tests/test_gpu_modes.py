@@ -1,0 +1,86 @@
+"""GPU parity of the general-mode TT-SVD and max-rank TT-RSVD (Section 5,
+modifications (1) and (2)) against the FP64 oracle on the same inputs and the
+same Gaussian test matrices: ranks exact, reconstruction to 1e-10 (exact
+steps) or 1e-9 (randomised steps), left-orthonormal cores."""
+
+import numpy as np
+import pytest
+
+from oracle import ttm
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2301_13339_amd as q  # noqa: E402
+
+
+def _low_rank(modes, nterms, seed):
+    rng = np.random.default_rng(seed)
+    a = np.zeros(modes)
+    for _ in range(nterms):
+        t = rng.standard_normal(modes[0])
+        for m in modes[1:]:
+            t = np.multiply.outer(t, rng.standard_normal(m))
+        a += t
+    return a.ravel(order="F")
+
+
+CASES = [
+    # name, K, M, data, eps, R, method, p
+    ("uniform_K4_M6", 4, 6, "uniform", 1e-3, 0, "svd", 0),        # m up to 126: global eigensolver
+    ("uniform_K5_M10_R10", 5, 10, "uniform", 0.0, 10, "svd", 0),
+    ("uniform_K5_M10_R10_rsvd", 5, 10, "uniform", 0.0, 10, "rsvd", 10),
+    ("uniform_K6_M7_R8_rsvd", 6, 7, "uniform", 1e-2, 8, "rsvd", 6),
+    ("lowrank3_K6_M5", 6, 5, "lowrank", 1e-6, 0, "svd", 0),  # eps above the Gram floor
+    ("lowrank3_K6_M5_rsvd", 6, 5, "lowrank", 1e-6, 8, "rsvd", 4),
+    ("binary_K12", 12, 2, "uniform", 1e-2, 0, "svd", 0),
+]
+
+
+@pytest.mark.parametrize("name,K,M,data,eps,R,method,p", CASES, ids=[c[0] for c in CASES])
+def test_modes_match_oracle(name, K, M, data, eps, R, method, p):
+    print("case: modes", name, flush=True)
+    modes = [M] * K
+    if data == "uniform":
+        x = np.random.default_rng(K * 100 + M).random(M ** K)
+    else:
+        x = _low_rank(modes, 3, K + M)
+    # the library keeps every unfolding at <= 128 rows: cap min(R, 128 // M)
+    reff = min(R if R > 0 else q.QTT_MAX_RANK, 128 // M)
+    ref, info = ttm.tt_svd_modes(x, modes, eps, reff, True, method=method, oversample=p,
+                                 seed=17)
+    t = q.decompose_modes(torch.tensor(x, device="cuda"), M, eps, R, method=method,
+                          oversample=p, seed=17)
+    assert t.ranks_host() == info["ranks"]
+    cores = t.core_list()
+    full = ttm.tt_full_modes(cores)
+    want = ttm.tt_full_modes(ref)
+    tol = 1e-9 if method == "rsvd" else 1e-10
+    assert np.linalg.norm(full - want) <= tol * np.linalg.norm(want)
+    for c in cores[:-1]:
+        U = c.reshape(-1, c.shape[2], order="F")
+        assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= 1e-10
+
+
+def test_modes_binary_equals_qtt_path():
+    """M = 2: the same ranks and tensor as qtt_decompose."""
+    x = np.random.default_rng(3).standard_normal(1 << 14)
+    a = q.decompose_modes(torch.tensor(x, device="cuda"), 2, 1e-2)
+    b = q.decompose(torch.tensor(x, device="cuda"), 1e-2)
+    assert a.ranks_host() == b.ranks_host()
+    fa = ttm.tt_full_modes(a.core_list())
+    fb = q.full(b).cpu().numpy()
+    assert np.linalg.norm(fa - fb) <= 1e-10 * np.linalg.norm(fb)
+
+
+def test_modes_arguments_rejected():
+    x = torch.zeros(1000, dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        q.decompose_modes(x[:999], 10, 1e-3)
+    with pytest.raises(q.QttError):
+        q.decompose_modes(x, 10, 1e-3, 0, method="rsvd")        # rsvd needs a cap
+    with pytest.raises(q.QttError):
+        q.decompose_modes(x, 10, 1e-3, 10, method="rsvd", oversample=60)  # ell > 64
