@@ -21,7 +21,13 @@
 
 namespace qtt {
 
-constexpr int kMcTile = 32;      // columns of A per streaming tile
+constexpr int kMcTile = 32;      // columns of A per tile of the projection and G_B passes
+// columns per tile of the Gram and sketch passes: about 256 / UT, so that a
+// tile carries several KB whatever the row count
+template <int UT>
+constexpr int gram_tile() {
+  return UT >= 8 ? 32 : 256 / UT;
+}
 constexpr int kMsMaxEll = 64;    // sketch width limit (ell = R + p)
 
 // ------------------------------------------------------------- Gram pass
@@ -31,7 +37,8 @@ template <int UT>
 __global__ void __launch_bounds__(256) k_mgram(const double* R, int M, const int32_t* ranks, int k,
                                                long long n, double* partials, int pstride) {
   constexpr int LDA = 16 * UT + 1;
-  __shared__ double As[kMcTile * LDA];
+  constexpr int TC = gram_tile<UT>();
+  __shared__ double As[TC * LDA];
   const int m = M * ranks[k - 1];
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   double acc[UT][UT];
@@ -40,18 +47,18 @@ __global__ void __launch_bounds__(256) k_mgram(const double* R, int M, const int
 #pragma unroll
     for (int v = 0; v < UT; ++v) acc[u][v] = 0.0;
   // rows m .. 16 UT - 1 of the tile stay zero
-  for (int e = tid; e < kMcTile * LDA; e += 256) As[e] = 0.0;
-  const long long ntile = (n + kMcTile - 1) / kMcTile;
+  for (int e = tid; e < TC * LDA; e += 256) As[e] = 0.0;
+  const long long ntile = (n + TC - 1) / TC;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long c0 = t * kMcTile;
-    const int nc = (int)((n - c0) < kMcTile ? (n - c0) : kMcTile);
+    const long long c0 = t * TC;
+    const int nc = (int)((n - c0) < TC ? (n - c0) : TC);
     __syncthreads();
-    for (int e = tid; e < m * kMcTile; e += 256) {
+    for (int e = tid; e < m * TC; e += 256) {
       const int c = e / m, a = e - c * m;
       As[c * LDA + a] = (c < nc) ? R[(long long)m * c0 + e] : 0.0;
     }
     __syncthreads();
-    for (int c = 0; c < kMcTile; ++c) {
+    for (int c = 0; c < TC; ++c) {
       double xa[UT], xb[UT];
 #pragma unroll
       for (int u = 0; u < UT; ++u) {
@@ -82,8 +89,9 @@ __global__ void __launch_bounds__(256) k_msketch(const double* R, int M, const i
                                                  long long n, int ell, uint32_t s0, uint32_t s1,
                                                  double* partials, int pstride) {
   constexpr int LDA = 16 * UT + 1;
-  __shared__ double As[kMcTile * LDA];
-  __shared__ double Om[kMcTile * kMsMaxEll];
+  constexpr int TC = gram_tile<UT>() < 64 ? gram_tile<UT>() : 64;
+  __shared__ double As[TC * LDA];
+  __shared__ double Om[TC * kMsMaxEll];
   const int m = M * ranks[k - 1];
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   double acc[UT][4];
@@ -91,22 +99,22 @@ __global__ void __launch_bounds__(256) k_msketch(const double* R, int M, const i
   for (int u = 0; u < UT; ++u)
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int e = tid; e < kMcTile * LDA; e += 256) As[e] = 0.0;
-  const long long ntile = (n + kMcTile - 1) / kMcTile;
+  for (int e = tid; e < TC * LDA; e += 256) As[e] = 0.0;
+  const long long ntile = (n + TC - 1) / TC;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long c0 = t * kMcTile;
-    const int nc = (int)((n - c0) < kMcTile ? (n - c0) : kMcTile);
+    const long long c0 = t * TC;
+    const int nc = (int)((n - c0) < TC ? (n - c0) : TC);
     __syncthreads();
-    for (int e = tid; e < m * kMcTile; e += 256) {
+    for (int e = tid; e < m * TC; e += 256) {
       const int c = e / m, a = e - c * m;
       As[c * LDA + a] = (c < nc) ? R[(long long)m * c0 + e] : 0.0;
     }
-    for (int e = tid; e < kMcTile * kMsMaxEll; e += 256) {
+    for (int e = tid; e < TC * kMsMaxEll; e += 256) {
       const int c = e / kMsMaxEll, j = e - c * kMsMaxEll;
       Om[e] = (c < nc && j < ell) ? omega_entry(c0 + c, j, k, s0, s1) : 0.0;
     }
     __syncthreads();
-    for (int c = 0; c < kMcTile; ++c) {
+    for (int c = 0; c < TC; ++c) {
       double xa[UT], om[4];
 #pragma unroll
       for (int u = 0; u < UT; ++u) xa[u] = As[c * LDA + ty + 16 * u];
@@ -334,19 +342,19 @@ __global__ void __launch_bounds__(kEigThreads) k_mqr(const double* Y, int M, con
 // ------------------------------------------------------------ projection
 // R_{k+1}[b + r c] = sum_a U[a][b] A(a, c); U (m x r, row-major) in LDS.
 __global__ void __launch_bounds__(256) k_mproj(const double* R, int M, const int32_t* ranks, int k,
-                                               long long n, const double* U, double* Rn) {
+                                               long long n, const double* U, double* Rn, int TC) {
   extern __shared__ double sm[];
   const int m = M * ranks[k - 1];
   const int r = ranks[k];
   const int LDA = m + 1;
   double* Us = sm;                   // m x r
-  double* As = Us + kMaxM * kMaxRank;  // kMcTile x LDA
+  double* As = Us + kMaxM * kMaxRank;  // TC x LDA
   const int tid = threadIdx.x;
   for (int e = tid; e < m * r; e += 256) Us[e] = U[e];
-  const long long ntile = (n + kMcTile - 1) / kMcTile;
+  const long long ntile = (n + TC - 1) / TC;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long c0 = t * kMcTile;
-    const int nc = (int)((n - c0) < kMcTile ? (n - c0) : kMcTile);
+    const long long c0 = t * TC;
+    const int nc = (int)((n - c0) < TC ? (n - c0) : TC);
     __syncthreads();
     for (int e = tid; e < m * nc; e += 256) {
       const int c = e / m, a = e - c * m;
@@ -446,8 +454,11 @@ static size_t lds_meig() {
          sizeof(int) * (kMaxM + 8 + 8 + 256);
 }
 
+// projection tile: more columns when the unfolding has few rows
+static int proj_tile(int mcap) { return mcap <= 16 ? 256 : (mcap <= 32 ? 128 : (mcap <= 64 ? 64 : 32)); }
+
 static size_t lds_mproj() {
-  return sizeof(double) * ((size_t)kMaxM * kMaxRank + (size_t)kMcTile * (kMaxM + 1));
+  return sizeof(double) * ((size_t)kMaxM * kMaxRank + (size_t)256 * 17);
 }
 
 template <int UT>
@@ -477,21 +488,30 @@ static void launch_stream_passes(int which, const double* R, int M, int32_t* ran
 }
 
 static int stream_pass(int which, const double* R, int M, int mcap, int32_t* ranks, int k,
-                       long long n, int* nparts, int ell, uint64_t seed, const ModesPlan& P,
-                       hipStream_t s) {
+                       long long n, int* nparts, int* pstride, int ell, uint64_t seed,
+                       const ModesPlan& P, hipStream_t s) {
+  // partials of sz doubles each, as many as the partials buffer holds (<= 1024)
+  const long long sz = which == 0 ? (long long)mcap * mcap
+                                  : (which == 1 ? (long long)mcap * ell : (long long)ell * ell);
+  const long long cap_parts = (long long)kMaxPartials * P.pstride / sz;
   const long long ntile = (n + kMcTile - 1) / kMcTile;
-  const int blocks = (int)(ntile < kMaxPartials ? ntile : kMaxPartials);
+  long long b = ntile < 1024 ? ntile : 1024;
+  if (b > cap_parts) b = cap_parts;
+  const int blocks = (int)(b < 1 ? 1 : b);
   *nparts = blocks;
+  *pstride = (int)sz;
+  ModesPlan Q = P;
+  Q.pstride = (int)sz;
   const int ut = (mcap + 15) / 16;
   switch (ut) {
-    case 1: launch_stream_passes<1>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
-    case 2: launch_stream_passes<2>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
-    case 3: launch_stream_passes<3>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
-    case 4: launch_stream_passes<4>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
-    case 5: launch_stream_passes<5>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
-    case 6: launch_stream_passes<6>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
-    case 7: launch_stream_passes<7>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
-    default: launch_stream_passes<8>(which, R, M, ranks, k, n, blocks, ell, seed, P, s); break;
+    case 1: launch_stream_passes<1>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+    case 2: launch_stream_passes<2>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+    case 3: launch_stream_passes<3>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+    case 4: launch_stream_passes<4>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+    case 5: launch_stream_passes<5>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+    case 6: launch_stream_passes<6>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+    case 7: launch_stream_passes<7>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+    default: launch_stream_passes<8>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
   }
   QTT_LAUNCH_CHECK();
   return QTT_OK;
@@ -537,34 +557,35 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
     n /= M;  // columns of A_k
     const int mcap = M * cap[k - 1];
     const bool rs = (method == 1) && ((long long)mcap < n ? (long long)mcap : n) > ell;
-    int np = 0;
+    int np = 0, ps = 0;
     if (!rs) {
-      rc = stream_pass(0, cur, M, mcap, ranks, k, n, &np, 0, seed, P, s);
+      rc = stream_pass(0, cur, M, mcap, ranks, k, n, &np, &ps, 0, seed, P, s);
       if (rc) return rc;
-      rc = launch_reduce(P.partials, P.pstride, np, mcap * mcap, P.gram, s);
+      rc = launch_reduce(P.partials, ps, np, mcap * mcap, P.gram, s);
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gram, M, ranks, k, 0, nullptr, P.iq, P.scal,
                                                 cap[k], cores, off, P.umat, P.gA, P.gV);
       QTT_LAUNCH_CHECK();
     } else {
-      rc = stream_pass(1, cur, M, mcap, ranks, k, n, &np, ell, seed, P, s);
+      rc = stream_pass(1, cur, M, mcap, ranks, k, n, &np, &ps, ell, seed, P, s);
       if (rc) return rc;
-      rc = launch_reduce(P.partials, P.pstride, np, mcap * ell, P.y, s);
+      rc = launch_reduce(P.partials, ps, np, mcap * ell, P.y, s);
       if (rc) return rc;
       k_mqr<<<1, kEigThreads, lds_meig(), s>>>(P.y, M, ranks, k, ell, P.q1, P.q, P.iq);
       QTT_LAUNCH_CHECK();
-      rc = stream_pass(2, cur, M, mcap, ranks, k, n, &np, ell, seed, P, s);
+      rc = stream_pass(2, cur, M, mcap, ranks, k, n, &np, &ps, ell, seed, P, s);
       if (rc) return rc;
-      rc = launch_reduce(P.partials, P.pstride, np, ell * ell, P.gramb, s);
+      rc = launch_reduce(P.partials, ps, np, ell * ell, P.gramb, s);
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gramb, M, ranks, k, 1, P.q, P.iq, P.scal,
                                                 cap[k], cores, off, P.umat, P.gA, P.gV);
       QTT_LAUNCH_CHECK();
     }
     {
-      const long long ntile = (n + kMcTile - 1) / kMcTile;
-      const int blocks = (int)(ntile < 1024 ? ntile : 1024);
-      k_mproj<<<blocks, 256, lds_mproj(), s>>>(cur, M, ranks, k, n, P.umat, P.rbuf[bi]);
+      const int tc = proj_tile(mcap);
+      const long long ntile = (n + tc - 1) / tc;
+      const int blocks = (int)(ntile < 2048 ? ntile : 2048);
+      k_mproj<<<blocks, 256, lds_mproj(), s>>>(cur, M, ranks, k, n, P.umat, P.rbuf[bi], tc);
       QTT_LAUNCH_CHECK();
     }
     cur = P.rbuf[bi];
