@@ -245,9 +245,10 @@ __device__ int meig_solve(const MEig& L, MP A, MP V, int E, double tau2, int cap
 // U = Q V[:, :r].  Writes ranks[k], core k and U (m x r, row-major) to umat.
 __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, int32_t* ranks,
                                                       int k, int use_q, const double* Q,
-                                                      const int32_t* iq, const double* scal,
+                                                      const int32_t* iq, double* scal,
                                                       int cap_k, double* cores, long long off_k,
-                                                      double* umat, double* gA, double* gV) {
+                                                      double* umat, double* gA, double* gV,
+                                                      int set_tau, double eps, int K) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int rp = ranks[k - 1];
@@ -258,6 +259,13 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
   for (int e = tid; e < E * E; e += kEigThreads) {
     const int a = e / E, b = e - a * E;
     L.A[a * L.lda + b] = G[e];
+  }
+  if (set_tau && tid == 0) {
+    // exact first step: ||x||^2 is the trace of its Gram
+    double tr = 0.0;
+    for (int a = 0; a < E; ++a) tr += G[a * E + a];
+    scal[0] = tr;
+    scal[1] = (K > 1) ? eps * eps * tr / (double)(K - 1) : 0.0;
   }
   __syncthreads();
   int r;
@@ -376,9 +384,9 @@ __global__ void __launch_bounds__(256) k_mproj(const double* R, int M, const int
 }
 
 // ------------------------------------------------------------ bookkeeping
-__global__ void k_mstart(double* scal, double eps, int K, int32_t* ranks) {
+__global__ void k_mstart(double* scal, double eps, int K, int32_t* ranks, int have_norm) {
   if (threadIdx.x == 0) {
-    scal[1] = (K > 1) ? eps * eps * scal[0] / (double)(K - 1) : 0.0;
+    if (have_norm) scal[1] = (K > 1) ? eps * eps * scal[0] / (double)(K - 1) : 0.0;
     ranks[0] = 1;
     ranks[K] = 1;
   }
@@ -541,18 +549,25 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
   const ModesPlan P = modes_plan(ws, K, M);
   long long N = 1;
   for (int k = 0; k < K; ++k) N *= M;
-  int rc = run_dot(QTT_F64, x, x, N, P.dotp, P.scal, s);
-  if (rc) return rc;
-  k_mstart<<<1, 64, 0, s>>>(P.scal, eps, K, ranks);
+  int Rmax = 0;
+  for (int k = 1; k <= K; ++k)
+    if (cap[k] > Rmax) Rmax = cap[k];
+  const int ell0 = (method == 1) ? Rmax + oversample : 0;
+  // ||x||^2: the trace of the first step's Gram when that step is exact,
+  // else one dot pass
+  const bool first_exact = !(method == 1 && ((long long)M < N / M ? (long long)M : N / M) > ell0);
+  int rc = QTT_OK;
+  if (!first_exact || K == 1) {
+    rc = run_dot(QTT_F64, x, x, N, P.dotp, P.scal, s);
+    if (rc) return rc;
+  }
+  k_mstart<<<1, 64, 0, s>>>(P.scal, eps, K, ranks, (!first_exact || K == 1) ? 1 : 0);
   QTT_LAUNCH_CHECK();
   long long off = 0;
   const double* cur = x;
   int bi = 0;
   long long n = N;
-  int R = 0;
-  for (int k = 1; k <= K; ++k)
-    if (cap[k] > R) R = cap[k];
-  const int ell = (method == 1) ? R + oversample : 0;
+  const int ell = ell0;
   for (int k = 1; k < K; ++k) {
     n /= M;  // columns of A_k
     const int mcap = M * cap[k - 1];
@@ -564,7 +579,8 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       rc = launch_reduce(P.partials, ps, np, mcap * mcap, P.gram, s);
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gram, M, ranks, k, 0, nullptr, P.iq, P.scal,
-                                                cap[k], cores, off, P.umat, P.gA, P.gV);
+                                                cap[k], cores, off, P.umat, P.gA, P.gV,
+                                                (k == 1 && first_exact) ? 1 : 0, eps, K);
       QTT_LAUNCH_CHECK();
     } else {
       rc = stream_pass(1, cur, M, mcap, ranks, k, n, &np, &ps, ell, seed, P, s);
@@ -578,7 +594,8 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       rc = launch_reduce(P.partials, ps, np, ell * ell, P.gramb, s);
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gramb, M, ranks, k, 1, P.q, P.iq, P.scal,
-                                                cap[k], cores, off, P.umat, P.gA, P.gV);
+                                                cap[k], cores, off, P.umat, P.gA, P.gV, 0, eps,
+                                                K);
       QTT_LAUNCH_CHECK();
     }
     {
