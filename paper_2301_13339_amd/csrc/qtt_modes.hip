@@ -154,6 +154,8 @@ __global__ void __launch_bounds__(256) k_mbgram(const double* R, int M, const in
   const int q = iq[0];
   const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
   for (int e = tid; e < m * q; e += 256) Qs[e] = Q[e];
+  // rows q .. 63 of B stay zero
+  for (int e = tid; e < kMsMaxEll * LB; e += 256) Bt[e] = 0.0;
   double acc[4][4];
 #pragma unroll
   for (int u = 0; u < 4; ++u)
@@ -169,12 +171,16 @@ __global__ void __launch_bounds__(256) k_mbgram(const double* R, int M, const in
       As[c * LDA + a] = (c < nc) ? R[(long long)m * c0 + e] : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < kMsMaxEll * kMcTile; e += 256) {
+    for (int e = tid; e < q * kMcTile; e += 256) {
       const int j = e / kMcTile, c = e - j * kMcTile;
-      double s = 0.0;
-      if (j < q)
-        for (int a = 0; a < m; ++a) s = fma(Qs[a * q + j], As[c * LDA + a], s);
-      Bt[j * LB + c] = s;  // zero for j >= q
+      double s0 = 0.0, s1 = 0.0;
+      int a = 0;
+      for (; a + 1 < m; a += 2) {
+        s0 = fma(Qs[a * q + j], As[c * LDA + a], s0);
+        s1 = fma(Qs[(a + 1) * q + j], As[c * LDA + a + 1], s1);
+      }
+      if (a < m) s0 = fma(Qs[a * q + j], As[c * LDA + a], s0);
+      Bt[j * LB + c] = s0 + s1;
     }
     __syncthreads();
     for (int c = 0; c < kMcTile; ++c) {
