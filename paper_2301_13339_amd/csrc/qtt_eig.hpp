@@ -5,6 +5,8 @@
 #pragma once
 
 #include "qtt_internal.hpp"
+#include <type_traits>
+
 #include "qtt_syev.hpp"
 
 namespace qtt {
@@ -156,8 +158,8 @@ __device__ inline int sturm_below(lds_ptr<const double> dg, lds_ptr<const double
 // vectors are not computed.  One Sturm count at a point a little above tau2
 // that finds no eigenvalue below it settles the rank; otherwise the full path
 // decides as usual.
-template <int NT, bool BIG = false, class MP>
-__device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr, ldsd lam,
+template <int NT, bool BIG = false, class MP, class MPV>
+__device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi iscr, ldsd lam,
                                   ldsi perm, double tau2, int cap, int k,
                                   const StepOut& so, bool any_basis = false) {
   const int tid = threadIdx.x;
@@ -192,7 +194,9 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   const int K = (so.sv || cap >= E || !(tau2 > 0.0)) ? E : cap;
   if (finite) {
     if constexpr (BIG) {
-      if (E > 64)
+      // the E <= 64 reduction leaves Q^T in A, which the back transformation
+      // of split storage (A and V in different memories) does not take
+      if (E > 64 || !std::is_same<MP, MPV>::value)
         sy_tridiag<NT, 8>(A, E, lda, dg, od, bt, pv);
       else
         sy_tridiag64(A, E, lda, dg, od, bt, pv);
@@ -282,20 +286,25 @@ __device__ int solve_and_truncate(MP A, MP V, int E, int lda, ldsd sx, ldsi iscr
   tt[3] = wall_clock64();
 #endif
   // pv .. sx + kEigNrmSlot (pv, e2, la and the arrays after) are free now
-  if (E <= 64) {
-    // A holds Q^T of the reduction (sy_tridiag64); vectors that are
-    // orthonormal to first order take one polishing step, others (or more
-    // than 32) Gram-Schmidt
-    const bool done = (r <= 32 && polish_backtr64(A, E, lda, V, r, pv)) ||
-                      mgs_backtr64(A, E, lda, V, lda, r, pv, iscr + 3);
+  bool small_done = false;
+  if constexpr (std::is_same<MP, MPV>::value) {
+    if (E <= 64) {
+      // A holds Q^T of the reduction (sy_tridiag64); vectors that are
+      // orthonormal to first order take one polishing step, others (or more
+      // than 32) Gram-Schmidt
+      const bool done = (r <= 32 && polish_backtr64(A, E, lda, V, r, pv)) ||
+                        mgs_backtr64(A, E, lda, V, lda, r, pv, iscr + 3);
 #ifdef QTT_EIG_TIMING
-    tt[4] = wall_clock64();
+      tt[4] = wall_clock64();
 #endif
-    if (!done) {
-      mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
-      backtr_gemm64(A, E, lda, V, r);
+      if (!done) {
+        mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
+        backtr_gemm64(A, E, lda, V, r);
+      }
+      small_done = true;
     }
-  } else {
+  }
+  if (!small_done) {
     mgs_cols<NT>(V, E, lda, r, dg, od, lam, pv);
 #ifdef QTT_EIG_TIMING
     tt[4] = wall_clock64();

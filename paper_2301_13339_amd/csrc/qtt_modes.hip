@@ -21,189 +21,315 @@
 
 namespace qtt {
 
-constexpr int kMcTile = 32;      // columns of A per tile of the projection and G_B passes
-// columns per tile of the Gram and sketch passes: about 256 / UT, so that a
-// tile carries several KB whatever the row count
-template <int UT>
-constexpr int gram_tile() {
-  return UT >= 8 ? 32 : 256 / UT;
-}
-constexpr int kMsMaxEll = 64;    // sketch width limit (ell = R + p)
+constexpr int kMsMaxEll = 64;        // sketch width limit (ell = R + p)
+constexpr int kModesPartials = 512;  // partial results per streaming pass (kMaxM^2 doubles each)
+constexpr int kTileElems = 4096;     // doubles of A per tile of the streaming passes
+constexpr int kWaveSumElems = 3 * 3 * 256;  // LDS for the cross-wave sum of <= 3 accumulators
 
-// ------------------------------------------------------------- Gram pass
-// Partial G = A A^T over the column tiles of this block (grid-stride).
-// Thread (ty, tx) owns rows ty + 16u, columns tx + 16v (u, v < UT).
-template <int UT>
-__global__ void __launch_bounds__(256) k_mgram(const double* R, int M, const int32_t* ranks, int k,
-                                               long long n, double* partials, int pstride) {
-  constexpr int LDA = 16 * UT + 1;
-  constexpr int TC = gram_tile<UT>();
-  __shared__ double As[TC * LDA];
-  const int m = M * ranks[k - 1];
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  double acc[UT][UT];
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+
+// All streaming passes run on the FP64 matrix cores.  v_mfma_f64_16x16x4f64:
+// lane l supplies A entry (row l % 16, k l / 16) and B entry (k l / 16,
+// column l % 16); element i of the result is D[4i + l / 16][l % 16].
+__device__ __forceinline__ mf64x4 mfma4(double a, double b, mf64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// The tile of columns c0 .. c0 + nc - 1 of A_k is the contiguous block
+// R[m c0 .. m (c0 + nc)); it is copied to As[c m + a] as it is.
+__device__ __forceinline__ void mload_tile(const double* __restrict__ R, int m, long long c0,
+                                           int nc, double* As) {
+  const double* src = R + (long long)m * c0;
+  const int tot = m * nc;
+  if ((reinterpret_cast<uintptr_t>(src) & 15) == 0) {
+    const double2* s2 = reinterpret_cast<const double2*>(src);
+    double2* d2 = reinterpret_cast<double2*>(As);
+    for (int e = threadIdx.x; e < (tot >> 1); e += 256) d2[e] = s2[e];
+    if ((tot & 1) && threadIdx.x == 0) As[tot - 1] = src[tot - 1];
+  } else {
+    for (int e = threadIdx.x; e < tot; e += 256) As[e] = src[e];
+  }
+}
+
+// Upper-triangle block idx (< nb (nb + 1) / 2) of an nb x nb block grid, in
+// the order (0,0), (0,1), ..., (0,nb-1), (1,1), ...
+__device__ __forceinline__ void tri_block(int idx, int nb, int& bi, int& bj) {
+  int a = 0;
+  while (a < nb && idx >= nb - a) {
+    idx -= nb - a;
+    ++a;
+  }
+  bi = a;
+  bj = a + idx;
+}
+
+// G += T T^T for the column groups gr = g0, g0 + gs, ... (4 columns each) of
+// the LDS tile T (column c at T + c ldt, rows < m, nc columns): accumulator t
+// holds the 16 x 16 block (bi[t], bj[t]) when on[t].
+template <int NA>
+__device__ __forceinline__ void mfma_gram_tile(const double* T, int ldt, int m, int nc,
+                                               const int* bi, const int* bj, const bool* on,
+                                               int g0, int gs, mf64x4* g) {
+  const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+  const int ng = (nc + 3) >> 2;
+  for (int gr = g0; gr < ng; gr += gs) {
+    const int c = 4 * gr + lk;
+    const bool cin = c < nc;
 #pragma unroll
-  for (int u = 0; u < UT; ++u)
-#pragma unroll
-    for (int v = 0; v < UT; ++v) acc[u][v] = 0.0;
-  // rows m .. 16 UT - 1 of the tile stay zero
-  for (int e = tid; e < TC * LDA; e += 256) As[e] = 0.0;
-  const long long ntile = (n + TC - 1) / TC;
-  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long c0 = t * TC;
-    const int nc = (int)((n - c0) < TC ? (n - c0) : TC);
-    __syncthreads();
-    for (int e = tid; e < m * TC; e += 256) {
-      const int c = e / m, a = e - c * m;
-      As[c * LDA + a] = (c < nc) ? R[(long long)m * c0 + e] : 0.0;
-    }
-    __syncthreads();
-    for (int c = 0; c < TC; ++c) {
-      double xa[UT], xb[UT];
-#pragma unroll
-      for (int u = 0; u < UT; ++u) {
-        xa[u] = As[c * LDA + ty + 16 * u];
-        xb[u] = As[c * LDA + tx + 16 * u];
-      }
-#pragma unroll
-      for (int u = 0; u < UT; ++u)
-#pragma unroll
-        for (int v = 0; v < UT; ++v) acc[u][v] = fma(xa[u], xb[v], acc[u][v]);
+    for (int t = 0; t < NA; ++t) {
+      if (!on[t]) continue;  // wave-uniform
+      const int ra = 16 * bi[t] + lr, rb = 16 * bj[t] + lr;
+      const double x = (cin && ra < m) ? T[c * ldt + ra] : 0.0;
+      const double y = (cin && rb < m) ? T[c * ldt + rb] : 0.0;
+      g[t] = mfma4(x, y, g[t]);
     }
   }
-  double* P = partials + (size_t)blockIdx.x * pstride;
+}
+
+// Waves 1..3 hand their first na (<= 3) accumulators to wave 0 through LDS
+// (buf: kWaveSumElems doubles); wave 0 adds them in wave order.  Every thread
+// of the block calls it.
+template <int NA>
+__device__ __forceinline__ void mfma_wave_sum(double* buf, int na, mf64x4* g) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  __syncthreads();
+  if (w > 0) {
 #pragma unroll
-  for (int u = 0; u < UT; ++u)
+    for (int t = 0; t < NA; ++t)
+      if (t < na && t < 3)
 #pragma unroll
-    for (int v = 0; v < UT; ++v) {
-      const int a = ty + 16 * u, b = tx + 16 * v;
-      if (a < m && b < m) P[a * m + b] = acc[u][v];
+        for (int i = 0; i < 4; ++i) buf[(((w - 1) * 3 + t) * 4 + i) * 64 + l] = g[t][i];
+  }
+  __syncthreads();
+  if (w == 0) {
+    for (int ww = 1; ww < 4; ++ww)
+#pragma unroll
+      for (int t = 0; t < NA; ++t)
+        if (t < na && t < 3)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) g[t][i] += buf[(((ww - 1) * 3 + t) * 4 + i) * 64 + l];
+  }
+}
+
+// Symmetric partial Gram (m x m, row-major) from the upper-triangle blocks.
+template <int NA>
+__device__ __forceinline__ void mfma_gram_store(double* P, int m, const int* bi, const int* bj,
+                                                const bool* on, const mf64x4* g) {
+  const int l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+#pragma unroll
+  for (int t = 0; t < NA; ++t) {
+    if (!on[t]) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int row = 16 * bi[t] + 4 * i + lk, col = 16 * bj[t] + lr;
+      if (row < m && col < m) {
+        P[row * m + col] = g[t][i];
+        if (bi[t] != bj[t]) P[col * m + row] = g[t][i];
+      }
     }
+  }
+}
+
+// ------------------------------------------------------------- Gram pass
+// Partial G = A A^T over this block's column tiles (grid-stride), m <= 16 MB.
+// With at least 4 upper-triangle blocks the waves split the blocks, else the
+// column groups (and are summed at the end).
+template <int MB>
+__global__ void __launch_bounds__(256) k_mgram(const double* __restrict__ R, int M,
+                                               const int32_t* __restrict__ ranks, int k,
+                                               long long n, int tc, double* __restrict__ partials,
+                                               int pstride) {
+  constexpr int NB = MB * (MB + 1) / 2;
+  constexpr bool SPLIT = NB >= 4;
+  constexpr int NA = SPLIT ? (NB + 3) / 4 : NB;
+  extern __shared__ double As[];  // tc x m, at least kWaveSumElems
+  const int m = M * ranks[k - 1];
+  const int w = threadIdx.x >> 6;
+  int bi[NA], bj[NA];
+  bool on[NA];
+  mf64x4 g[NA];
+#pragma unroll
+  for (int t = 0; t < NA; ++t) {
+    const int idx = SPLIT ? w + 4 * t : t;
+    on[t] = idx < NB;
+    bi[t] = 0;
+    bj[t] = 0;
+    if (on[t]) tri_block(idx, MB, bi[t], bj[t]);
+    g[t] = mf64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  const long long ntile = (n + tc - 1) / tc;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const long long c0 = t * tc;
+    const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
+    __syncthreads();
+    mload_tile(R, m, c0, nc, As);
+    __syncthreads();
+    mfma_gram_tile<NA>(As, m, m, nc, bi, bj, on, SPLIT ? 0 : w, SPLIT ? 1 : 4, g);
+  }
+  if (!SPLIT) {
+    mfma_wave_sum<NA>(As, NB, g);
+    if (w != 0) return;
+  }
+  mfma_gram_store<NA>(partials + (size_t)blockIdx.x * pstride, m, bi, bj, on, g);
 }
 
 // ----------------------------------------------------------- sketch pass
 // Partial Y = A Omega (m x ell, row-major) over this block's column tiles;
-// Omega[c][j] = omega_entry(c, j, k, seed) for the global column c.
-template <int UT>
-__global__ void __launch_bounds__(256) k_msketch(const double* R, int M, const int32_t* ranks, int k,
-                                                 long long n, int ell, uint32_t s0, uint32_t s1,
-                                                 double* partials, int pstride) {
-  constexpr int LDA = 16 * UT + 1;
-  constexpr int TC = gram_tile<UT>() < 64 ? gram_tile<UT>() : 64;
-  __shared__ double As[TC * LDA];
-  __shared__ double Om[TC * kMsMaxEll];
+// Omega[c][j] = omega_entry(c, j, k, seed) for the global column c, drawn
+// into LDS per tile (Om: tc x EL, EL = ell rounded up to 16, zero padded).
+template <int MB>
+__global__ void __launch_bounds__(256) k_msketch(const double* __restrict__ R, int M,
+                                                 const int32_t* __restrict__ ranks, int k,
+                                                 long long n, int tc, int as_cap, int ell,
+                                                 uint32_t s0, uint32_t s1,
+                                                 double* __restrict__ partials, int pstride) {
+  constexpr int NA = MB < 3 ? 3 : MB;
+  extern __shared__ double As[];  // tc x m (as_cap doubles), then Om
   const int m = M * ranks[k - 1];
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
-  double acc[UT][4];
+  const int EB = (ell + 15) >> 4, EL = 16 * EB;
+  double* Om = As + as_cap;
+  const int NB = MB * EB;
+  const bool split = NB >= 4;  // block-uniform
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  int bi[NA], bj[NA];
+  bool on[NA];
+  mf64x4 g[NA];
 #pragma unroll
-  for (int u = 0; u < UT; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  for (int e = tid; e < TC * LDA; e += 256) As[e] = 0.0;
-  const long long ntile = (n + TC - 1) / TC;
+  for (int t = 0; t < NA; ++t) {
+    const int idx = split ? w + 4 * t : t;
+    on[t] = idx < NB;
+    bi[t] = on[t] ? idx / EB : 0;
+    bj[t] = on[t] ? idx - (idx / EB) * EB : 0;
+    g[t] = mf64x4{0.0, 0.0, 0.0, 0.0};
+  }
+  const long long ntile = (n + tc - 1) / tc;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long c0 = t * TC;
-    const int nc = (int)((n - c0) < TC ? (n - c0) : TC);
+    const long long c0 = t * tc;
+    const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
     __syncthreads();
-    for (int e = tid; e < m * TC; e += 256) {
-      const int c = e / m, a = e - c * m;
-      As[c * LDA + a] = (c < nc) ? R[(long long)m * c0 + e] : 0.0;
-    }
-    for (int e = tid; e < TC * kMsMaxEll; e += 256) {
-      const int c = e / kMsMaxEll, j = e - c * kMsMaxEll;
+    mload_tile(R, m, c0, nc, As);
+    for (int e = tid; e < tc * EL; e += 256) {
+      const int c = e / EL, j = e - c * EL;
       Om[e] = (c < nc && j < ell) ? omega_entry(c0 + c, j, k, s0, s1) : 0.0;
     }
     __syncthreads();
-    for (int c = 0; c < TC; ++c) {
-      double xa[UT], om[4];
+    const int ng = (nc + 3) >> 2;
+    for (int gr = split ? 0 : w; gr < ng; gr += split ? 1 : 4) {
+      const int c = 4 * gr + lk;
+      const bool cin = c < nc;
 #pragma unroll
-      for (int u = 0; u < UT; ++u) xa[u] = As[c * LDA + ty + 16 * u];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) om[v] = Om[c * kMsMaxEll + tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < UT; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(xa[u], om[v], acc[u][v]);
+      for (int u = 0; u < NA; ++u) {
+        if (!on[u]) continue;
+        const int ra = 16 * bi[u] + lr;
+        const double x = (cin && ra < m) ? As[c * m + ra] : 0.0;
+        const double y = Om[c * EL + 16 * bj[u] + lr];
+        g[u] = mfma4(x, y, g[u]);
+      }
     }
+  }
+  if (!split) {
+    mfma_wave_sum<NA>(As, NB, g);
+    if (w != 0) return;
   }
   double* P = partials + (size_t)blockIdx.x * pstride;
 #pragma unroll
-  for (int u = 0; u < UT; ++u)
+  for (int u = 0; u < NA; ++u) {
+    if (!on[u]) continue;
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = ty + 16 * u, j = tx + 16 * v;
-      if (a < m && j < ell) P[a * ell + j] = acc[u][v];
+    for (int i = 0; i < 4; ++i) {
+      const int a = 16 * bi[u] + 4 * i + lk, j = 16 * bj[u] + lr;
+      if (a < m && j < ell) P[a * ell + j] = g[u][i];
     }
+  }
+}
+
+// Y^T = A^T W for a tile (W: m x q row-major in LDS): work items (column
+// block cb, basis block qb) round-robin over the waves, the k loop over the
+// m rows of A.  Result entry (tile column c, basis vector j) goes to
+// put(c, j, value) for j < q (tile columns >= nc come out zero).
+template <class Put>
+__device__ __forceinline__ void mfma_tile_times(const double* As, int m, int nc, int tc,
+                                                const double* Ws, int q, Put put) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+  const int QB = (q + 15) >> 4, items = (tc >> 4) * QB;
+  for (int it = w; it < items; it += 4) {
+    const int cb = it / QB, qb = it - cb * QB;
+    const int c = 16 * cb + lr, j = 16 * qb + lr;
+    const bool cin = c < nc, jin = j < q;
+    // four k steps per batch: their operands are read first, then the
+    // products go to two accumulators in turn
+    mf64x4 acc = mf64x4{0.0, 0.0, 0.0, 0.0}, acc1 = acc;
+    for (int a0 = 0; a0 < m; a0 += 16) {
+      double x[4], y[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int a = a0 + 4 * u + lk;
+        const bool ain = a < m;
+        x[u] = (ain && cin) ? As[c * m + a] : 0.0;
+        y[u] = (ain && jin) ? Ws[a * q + j] : 0.0;
+      }
+      acc = mfma4(x[0], y[0], acc);
+      acc1 = mfma4(x[1], y[1], acc1);
+      acc = mfma4(x[2], y[2], acc);
+      acc1 = mfma4(x[3], y[3], acc1);
+    }
+    acc += acc1;
+    if (jin) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) put(16 * cb + 4 * i + lk, j, acc[i]);
+    }
+  }
 }
 
 // ---------------------------------------------------- G_B = (Q^T A)(Q^T A)^T
-// Q: m x q row-major (q = iq[0] <= 64).  Per tile B = Q^T A (q x 32) in LDS,
-// then the partial q x q Gram; thread (ty, tx) owns rows ty + 16u, columns
-// tx + 16v (u, v < 4).
-template <int UT>
-__global__ void __launch_bounds__(256) k_mbgram(const double* R, int M, const int32_t* ranks, int k,
-                                                long long n, const double* Q, const int32_t* iq,
-                                                double* partials, int pstride) {
-  constexpr int LDA = 16 * UT + 1;
-  constexpr int LB = kMcTile + 1;
+// Q: m x q row-major (q = iq[0] <= ell).  Per tile B = Q^T A (q x tc) goes to
+// LDS (column c at Bs + c q), then the partial q x q Gram of its columns.
+__global__ void __launch_bounds__(256) k_mbgram(const double* __restrict__ R, int M,
+                                                const int32_t* __restrict__ ranks, int k,
+                                                long long n, int tc, int as_cap, int mcap,
+                                                int ell, const double* __restrict__ Q,
+                                                const int32_t* __restrict__ iq,
+                                                double* __restrict__ partials, int pstride) {
+  constexpr int NA = 3;
   extern __shared__ double sm[];
-  double* As = sm;                        // kMcTile x LDA
-  double* Qs = As + kMcTile * LDA;        // m x q
-  double* Bt = Qs + 16 * UT * kMsMaxEll;  // q x LB
   const int m = M * ranks[k - 1];
   const int q = iq[0];
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  double* As = sm;                     // tc x m (as_cap doubles)
+  double* Qs = As + as_cap;            // m x q
+  double* Bs = Qs + mcap * ell;        // tc x q
+  const int tid = threadIdx.x, w = tid >> 6;
   for (int e = tid; e < m * q; e += 256) Qs[e] = Q[e];
-  // rows q .. 63 of B stay zero
-  for (int e = tid; e < kMsMaxEll * LB; e += 256) Bt[e] = 0.0;
-  double acc[4][4];
+  const int QB = (q + 15) >> 4;
+  const int NB = QB * (QB + 1) / 2;  // <= 10
+  const bool split = NB >= 4;
+  int bi[NA], bj[NA];
+  bool on[NA];
+  mf64x4 g[NA];
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[u][v] = 0.0;
-  const long long ntile = (n + kMcTile - 1) / kMcTile;
-  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long c0 = t * kMcTile;
-    const int nc = (int)((n - c0) < kMcTile ? (n - c0) : kMcTile);
-    __syncthreads();
-    for (int e = tid; e < m * kMcTile; e += 256) {
-      const int c = e / m, a = e - c * m;
-      As[c * LDA + a] = (c < nc) ? R[(long long)m * c0 + e] : 0.0;
-    }
-    __syncthreads();
-    for (int e = tid; e < q * kMcTile; e += 256) {
-      const int j = e / kMcTile, c = e - j * kMcTile;
-      double s0 = 0.0, s1 = 0.0;
-      int a = 0;
-      for (; a + 1 < m; a += 2) {
-        s0 = fma(Qs[a * q + j], As[c * LDA + a], s0);
-        s1 = fma(Qs[(a + 1) * q + j], As[c * LDA + a + 1], s1);
-      }
-      if (a < m) s0 = fma(Qs[a * q + j], As[c * LDA + a], s0);
-      Bt[j * LB + c] = s0 + s1;
-    }
-    __syncthreads();
-    for (int c = 0; c < kMcTile; ++c) {
-      double xa[4], xb[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        xa[u] = Bt[(ty + 16 * u) * LB + c];
-        xb[u] = Bt[(tx + 16 * u) * LB + c];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] = fma(xa[u], xb[v], acc[u][v]);
-    }
+  for (int t = 0; t < NA; ++t) {
+    const int idx = split ? w + 4 * t : t;
+    on[t] = idx < NB;
+    bi[t] = 0;
+    bj[t] = 0;
+    if (on[t]) tri_block(idx, QB, bi[t], bj[t]);
+    g[t] = mf64x4{0.0, 0.0, 0.0, 0.0};
   }
-  double* P = partials + (size_t)blockIdx.x * pstride;
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int a = ty + 16 * u, b = tx + 16 * v;
-      if (a < q && b < q) P[a * q + b] = acc[u][v];
-    }
+  const long long ntile = (n + tc - 1) / tc;
+  for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
+    const long long c0 = t * tc;
+    const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
+    __syncthreads();
+    mload_tile(R, m, c0, nc, As);
+    __syncthreads();
+    mfma_tile_times(As, m, nc, tc, Qs, q, [&](int c, int j, double v) { Bs[c * q + j] = v; });
+    __syncthreads();
+    mfma_gram_tile<NA>(Bs, q, q, nc, bi, bj, on, split ? 0 : w, split ? 1 : 4, g);
+  }
+  if (!split) {
+    mfma_wave_sum<NA>(As, NB, g);
+    if (w != 0) return;
+  }
+  mfma_gram_store<NA>(partials + (size_t)blockIdx.x * pstride, q, bi, bj, on, g);
 }
 
 // -------------------------------------------------------- eigen problems
@@ -213,7 +339,7 @@ struct MEig {
   int lda;
 };
 
-__device__ __forceinline__ MEig meig_layout(double* smem, int E, double* gA, double* gV) {
+__device__ __forceinline__ MEig meig_layout(double* smem, int E, double* gV) {
   MEig L;
   if (E <= kEigLds) {
     L.lda = kEigLds + 1;
@@ -221,10 +347,11 @@ __device__ __forceinline__ MEig meig_layout(double* smem, int E, double* gA, dou
     L.V = L.A + L.lda * L.lda;
     L.lam = L.V + L.lda * L.lda;
   } else {
+    // orders 65..128: the matrix in LDS, the eigenvectors in global memory
     L.lda = kMaxM + 1;
-    L.A = gA;
+    L.A = smem;
     L.V = gV;
-    L.lam = smem;
+    L.lam = L.A + L.lda * L.lda;
   }
   L.sx = L.lam + kMaxM + 8;
   L.perm = (int*)(L.sx + kEigScratch);
@@ -232,8 +359,8 @@ __device__ __forceinline__ MEig meig_layout(double* smem, int E, double* gA, dou
   return L;
 }
 
-template <class MP>
-__device__ int meig_solve(const MEig& L, MP A, MP V, int E, double tau2, int cap, int32_t* rk,
+template <class MP, class MPV>
+__device__ int meig_solve(const MEig& L, MP A, MPV V, int E, double tau2, int cap, int32_t* rk,
                           int k) {
   StepOut so;
   so.ranks = rk;
@@ -253,7 +380,7 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
                                                       int k, int use_q, const double* Q,
                                                       const int32_t* iq, double* scal,
                                                       int cap_k, double* cores, long long off_k,
-                                                      double* umat, double* gA, double* gV,
+                                                      double* umat, double* gV,
                                                       int set_tau, double eps, int K) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
@@ -261,7 +388,7 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
   const int m = M * rp;
   const int q = use_q ? iq[0] : m;
   const int E = q;
-  const MEig L = meig_layout(smem, E, gA, gV);
+  const MEig L = meig_layout(smem, E, gV);
   for (int e = tid; e < E * E; e += kEigThreads) {
     const int a = e / E, b = e - a * E;
     L.A[a * L.lda + b] = G[e];
@@ -278,7 +405,7 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
   if (E <= kEigLds)
     r = meig_solve(L, lds(L.A), lds(L.V), E, scal[1], cap_k, ranks, k);
   else
-    r = meig_solve(L, L.A, L.V, E, scal[1], cap_k, ranks, k);
+    r = meig_solve(L, lds(L.A), L.V, E, scal[1], cap_k, ranks, k);
   // U (m x r) and core k
   for (int e = tid; e < m * r; e += kEigThreads) {
     const int b = e % r, t = e / r;
@@ -309,7 +436,7 @@ __global__ void __launch_bounds__(kEigThreads) k_mqr(const double* Y, int M, con
   const int tid = threadIdx.x;
   const int m = M * ranks[k - 1];
   const int E = ell;  // <= 64: LDS
-  const MEig L = meig_layout(smem, E, nullptr, nullptr);
+  const MEig L = meig_layout(smem, E, nullptr);
   for (int e = tid; e < E * E; e += kEigThreads) {
     const int a = e / E, b = e - a * E;
     double s = 0.0;
@@ -354,38 +481,30 @@ __global__ void __launch_bounds__(kEigThreads) k_mqr(const double* Y, int M, con
 }
 
 // ------------------------------------------------------------ projection
-// R_{k+1}[b + r c] = sum_a U[a][b] A(a, c); U (m x r, row-major) in LDS.
-__global__ void __launch_bounds__(256) k_mproj(const double* R, int M, const int32_t* ranks, int k,
-                                               long long n, const double* U, double* Rn, int TC) {
+// R_{k+1}[b + r c] = sum_a U[a][b] A(a, c): U (m x r, row-major) in LDS
+// after the tile (as_cap doubles).
+__global__ void __launch_bounds__(256) k_mproj(const double* __restrict__ R, int M,
+                                               const int32_t* __restrict__ ranks, int k,
+                                               long long n, int tc, int as_cap,
+                                               const double* __restrict__ U,
+                                               double* __restrict__ Rn) {
   extern __shared__ double sm[];
   const int m = M * ranks[k - 1];
   const int r = ranks[k];
-  const int LDA = m + 1;
-  double* Us = sm;                   // m x r
-  double* As = Us + kMaxM * kMaxRank;  // TC x LDA
-  const int tid = threadIdx.x;
-  for (int e = tid; e < m * r; e += 256) Us[e] = U[e];
-  const long long ntile = (n + TC - 1) / TC;
+  double* As = sm;
+  double* Us = sm + as_cap;
+  for (int e = threadIdx.x; e < m * r; e += 256) Us[e] = U[e];
+  const long long ntile = (n + tc - 1) / tc;
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
-    const long long c0 = t * TC;
-    const int nc = (int)((n - c0) < TC ? (n - c0) : TC);
+    const long long c0 = t * tc;
+    const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
     __syncthreads();
-    for (int e = tid; e < m * nc; e += 256) {
-      const int c = e / m, a = e - c * m;
-      As[c * LDA + a] = R[(long long)m * c0 + e];
-    }
+    mload_tile(R, m, c0, nc, As);
     __syncthreads();
-    for (int e = tid; e < r * nc; e += 256) {
-      const int c = e / r, b = e - c * r;
-      double s0 = 0.0, s1 = 0.0;
-      int a = 0;
-      for (; a + 1 < m; a += 2) {
-        s0 = fma(Us[a * r + b], As[c * LDA + a], s0);
-        s1 = fma(Us[(a + 1) * r + b], As[c * LDA + a + 1], s1);
-      }
-      if (a < m) s0 = fma(Us[a * r + b], As[c * LDA + a], s0);
-      Rn[(long long)r * c0 + e] = s0 + s1;
-    }
+    double* dst = Rn + (long long)r * c0;
+    mfma_tile_times(As, m, nc, tc, Us, r, [&](int c, int b, double v) {
+      if (c < nc) dst[(long long)r * c + b] = v;
+    });
   }
 }
 
@@ -426,7 +545,7 @@ int modes_caps(int K, int M, int max_rank, int32_t* cap) {
 }
 
 struct ModesPlan {
-  double *scal, *dotp, *partials, *gram, *gramb, *y, *umat, *q1, *q, *gA, *gV, *rbuf[2];
+  double *scal, *dotp, *partials, *gram, *gramb, *y, *umat, *q1, *q, *gV, *rbuf[2];
   int32_t* iq;
   int pstride;
   size_t bytes;
@@ -441,14 +560,13 @@ static ModesPlan modes_plan(void* ws, int K, int M) {
   p.scal = ar.take<double>(16);
   p.dotp = ar.take<double>(kDotPartials);
   p.iq = ar.take<int32_t>(16);
-  p.partials = ar.take<double>((size_t)kMaxPartials * p.pstride);
+  p.partials = ar.take<double>((size_t)kModesPartials * p.pstride);
   p.gram = ar.take<double>((size_t)kMaxM * kMaxM);
   p.gramb = ar.take<double>((size_t)kMsMaxEll * kMsMaxEll);
   p.y = ar.take<double>((size_t)kMaxM * kMsMaxEll);
   p.umat = ar.take<double>((size_t)kMaxM * kMaxRank);
   p.q1 = ar.take<double>((size_t)kMaxM * kMsMaxEll);
   p.q = ar.take<double>((size_t)kMaxM * kMsMaxEll);
-  p.gA = ar.take<double>((size_t)(kMaxM + 1) * (kMaxM + 1));
   p.gV = ar.take<double>((size_t)(kMaxM + 1) * (kMaxM + 1));
   p.rbuf[0] = ar.take<double>((size_t)N);
   p.rbuf[1] = ar.take<double>((size_t)N);
@@ -462,70 +580,106 @@ size_t modes_ws_bytes(int K, int M, int method, int oversample) {
   return modes_plan(nullptr, K, M).bytes;
 }
 
-static size_t lds_meig() {
+// LDS of the eigen kernels: two matrices of order <= 64, or one of order
+// <= 128 (k_meig only), plus the solver's vectors
+static size_t lds_meig_small() {
   const int lda = kEigLds + 1;
   return sizeof(double) * (2 * lda * lda + (kMaxM + 8) + kEigScratch) +
          sizeof(int) * (kMaxM + 8 + 8 + 256);
 }
-
-// projection tile: more columns when the unfolding has few rows
-static int proj_tile(int mcap) { return mcap <= 16 ? 256 : (mcap <= 32 ? 128 : (mcap <= 64 ? 64 : 32)); }
-
-static size_t lds_mproj() {
-  return sizeof(double) * ((size_t)kMaxM * kMaxRank + (size_t)256 * 17);
+static size_t lds_meig() {
+  const int lda = kMaxM + 1;
+  const size_t big = sizeof(double) * (lda * lda + (kMaxM + 8) + kEigScratch) +
+                     sizeof(int) * (kMaxM + 8 + 8 + 256);
+  return big > lds_meig_small() ? big : lds_meig_small();
 }
 
-template <int UT>
-static size_t lds_mbgram() {
-  return sizeof(double) * ((size_t)kMcTile * (16 * UT + 1) + (size_t)16 * UT * kMsMaxEll +
-                           (size_t)kMsMaxEll * (kMcTile + 1));
+// Columns per tile: about kTileElems doubles of A, a multiple of 16 in
+// [lo, hi].
+static int mtile(int mcap, int lo, int hi) {
+  int tc = (kTileElems / mcap) & ~15;
+  return tc < lo ? lo : (tc > hi ? hi : tc);
+}
+static int as_elems(int tc, int mcap) {
+  return tc * mcap > kWaveSumElems ? tc * mcap : kWaveSumElems;
 }
 
-template <int UT>
-static void set_mbgram_attr() {
-  (void)hipFuncSetAttribute((const void*)k_mbgram<UT>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_mbgram<UT>());
+constexpr int kMaxStreamLds = 150 * 1024;
+
+template <int MB>
+static void set_stream_attrs() {
+  (void)hipFuncSetAttribute((const void*)k_mgram<MB>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kMaxStreamLds);
+  (void)hipFuncSetAttribute((const void*)k_msketch<MB>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxStreamLds);
 }
 
-template <int UT>
-static void launch_stream_passes(int which, const double* R, int M, int32_t* ranks, int k,
-                                 long long n, int blocks, int ell, uint64_t seed,
-                                 const ModesPlan& P, hipStream_t s) {
-  if (which == 0) {
-    k_mgram<UT><<<blocks, 256, 0, s>>>(R, M, ranks, k, n, P.partials, P.pstride);
-  } else if (which == 1) {
-    k_msketch<UT><<<blocks, 256, 0, s>>>(R, M, ranks, k, n, ell, (uint32_t)(seed & 0xFFFFFFFFu),
-                                         (uint32_t)(seed >> 32), P.partials, P.pstride);
-  } else {
-    k_mbgram<UT><<<blocks, 256, lds_mbgram<UT>(), s>>>(R, M, ranks, k, n, P.q, P.iq, P.partials, P.pstride);
-  }
+template <int MB>
+static void launch_stream_mb(int which, const double* R, int M, const int32_t* ranks, int k,
+                             long long n, int blocks, int tc, int as_cap, int ell, uint64_t seed,
+                             double* partials, int pstride, size_t lds, hipStream_t s) {
+  if (which == 0)
+    k_mgram<MB><<<blocks, 256, lds, s>>>(R, M, ranks, k, n, tc, partials, pstride);
+  else
+    k_msketch<MB><<<blocks, 256, lds, s>>>(R, M, ranks, k, n, tc, as_cap, ell,
+                                           (uint32_t)(seed & 0xFFFFFFFFu),
+                                           (uint32_t)(seed >> 32), partials, pstride);
 }
 
+// One streaming pass over A_k: 0 = Gram (m x m partials), 1 = sketch
+// (m x ell), 2 = G_B (ell x ell at most).  Sets the number of partials and
+// their stride for the fixed-order reduction.
 static int stream_pass(int which, const double* R, int M, int mcap, int32_t* ranks, int k,
                        long long n, int* nparts, int* pstride, int ell, uint64_t seed,
                        const ModesPlan& P, hipStream_t s) {
-  // partials of sz doubles each, as many as the partials buffer holds (<= 1024)
   const long long sz = which == 0 ? (long long)mcap * mcap
                                   : (which == 1 ? (long long)mcap * ell : (long long)ell * ell);
-  const long long cap_parts = (long long)kMaxPartials * P.pstride / sz;
-  const long long ntile = (n + kMcTile - 1) / kMcTile;
+  int tc, as_cap;
+  size_t lds;
+  if (which == 0) {
+    tc = mtile(mcap, 16, 1024);
+    as_cap = as_elems(tc, mcap);
+    lds = sizeof(double) * (size_t)as_cap;
+  } else if (which == 1) {
+    tc = mtile(mcap, 16, 256);
+    as_cap = as_elems(tc, mcap);
+    lds = sizeof(double) * ((size_t)as_cap + (size_t)tc * (16 * ((ell + 15) / 16)));
+  } else {
+    tc = mtile(mcap, 32, 512);
+    as_cap = as_elems(tc, mcap);
+    lds = sizeof(double) * ((size_t)as_cap + (size_t)mcap * ell + (size_t)tc * ell);
+  }
+  if (lds > (size_t)kMaxStreamLds) return QTT_EINVAL;
+  const long long ntile = (n + tc - 1) / tc;
+  const long long cap_parts = (long long)kModesPartials * P.pstride / sz;
   long long b = ntile < 1024 ? ntile : 1024;
+  if (sz >= 4096 && b > 512) b = 512;  // the reduction reads every partial once
   if (b > cap_parts) b = cap_parts;
   const int blocks = (int)(b < 1 ? 1 : b);
   *nparts = blocks;
   *pstride = (int)sz;
-  ModesPlan Q = P;
-  Q.pstride = (int)sz;
-  const int ut = (mcap + 15) / 16;
-  switch (ut) {
-    case 1: launch_stream_passes<1>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
-    case 2: launch_stream_passes<2>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
-    case 3: launch_stream_passes<3>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
-    case 4: launch_stream_passes<4>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
-    case 5: launch_stream_passes<5>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
-    case 6: launch_stream_passes<6>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
-    case 7: launch_stream_passes<7>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
-    default: launch_stream_passes<8>(which, R, M, ranks, k, n, blocks, ell, seed, Q, s); break;
+  if (which == 2) {
+    k_mbgram<<<blocks, 256, lds, s>>>(R, M, ranks, k, n, tc, as_cap, mcap, ell, P.q, P.iq,
+                                      P.partials, (int)sz);
+  } else {
+    const int mb = (mcap + 15) / 16;
+    switch (mb) {
+#define QTT_MB_CASE(X)                                                                         \
+  case X:                                                                                      \
+    launch_stream_mb<X>(which, R, M, ranks, k, n, blocks, tc, as_cap, ell, seed, P.partials,   \
+                        (int)sz, lds, s);                                                      \
+    break;
+      QTT_MB_CASE(1)
+      QTT_MB_CASE(2)
+      QTT_MB_CASE(3)
+      QTT_MB_CASE(4)
+      QTT_MB_CASE(5)
+      QTT_MB_CASE(6)
+      QTT_MB_CASE(7)
+      QTT_MB_CASE(8)
+#undef QTT_MB_CASE
+      default: return QTT_EINVAL;
+    }
   }
   QTT_LAUNCH_CHECK();
   return QTT_OK;
@@ -539,17 +693,19 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
     (void)hipFuncSetAttribute((const void*)k_meig, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds_meig());
     (void)hipFuncSetAttribute((const void*)k_mqr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds_meig());
+                        (int)lds_meig_small());
     (void)hipFuncSetAttribute((const void*)k_mproj, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds_mproj());
-    set_mbgram_attr<1>();
-    set_mbgram_attr<2>();
-    set_mbgram_attr<3>();
-    set_mbgram_attr<4>();
-    set_mbgram_attr<5>();
-    set_mbgram_attr<6>();
-    set_mbgram_attr<7>();
-    set_mbgram_attr<8>();
+                              kMaxStreamLds);
+    (void)hipFuncSetAttribute((const void*)k_mbgram, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kMaxStreamLds);
+    set_stream_attrs<1>();
+    set_stream_attrs<2>();
+    set_stream_attrs<3>();
+    set_stream_attrs<4>();
+    set_stream_attrs<5>();
+    set_stream_attrs<6>();
+    set_stream_attrs<7>();
+    set_stream_attrs<8>();
     attrs = true;
   }
   const ModesPlan P = modes_plan(ws, K, M);
@@ -585,7 +741,7 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       rc = launch_reduce(P.partials, ps, np, mcap * mcap, P.gram, s);
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gram, M, ranks, k, 0, nullptr, P.iq, P.scal,
-                                                cap[k], cores, off, P.umat, P.gA, P.gV,
+                                                cap[k], cores, off, P.umat, P.gV,
                                                 (k == 1 && first_exact) ? 1 : 0, eps, K);
       QTT_LAUNCH_CHECK();
     } else {
@@ -593,22 +749,26 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       if (rc) return rc;
       rc = launch_reduce(P.partials, ps, np, mcap * ell, P.y, s);
       if (rc) return rc;
-      k_mqr<<<1, kEigThreads, lds_meig(), s>>>(P.y, M, ranks, k, ell, P.q1, P.q, P.iq);
+      k_mqr<<<1, kEigThreads, lds_meig_small(), s>>>(P.y, M, ranks, k, ell, P.q1, P.q, P.iq);
       QTT_LAUNCH_CHECK();
       rc = stream_pass(2, cur, M, mcap, ranks, k, n, &np, &ps, ell, seed, P, s);
       if (rc) return rc;
       rc = launch_reduce(P.partials, ps, np, ell * ell, P.gramb, s);
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gramb, M, ranks, k, 1, P.q, P.iq, P.scal,
-                                                cap[k], cores, off, P.umat, P.gA, P.gV, 0, eps,
+                                                cap[k], cores, off, P.umat, P.gV, 0, eps,
                                                 K);
       QTT_LAUNCH_CHECK();
     }
     {
-      const int tc = proj_tile(mcap);
+      const int rcap = cap[k] < mcap ? cap[k] : mcap;  // bound on r_k
+      int tc = mtile(mcap, 64, 512);
+      const int as_cap = tc * mcap;
+      const size_t lds = sizeof(double) * ((size_t)as_cap + (size_t)mcap * rcap);
+      if (lds > (size_t)kMaxStreamLds) return QTT_EINVAL;
       const long long ntile = (n + tc - 1) / tc;
       const int blocks = (int)(ntile < 2048 ? ntile : 2048);
-      k_mproj<<<blocks, 256, lds_mproj(), s>>>(cur, M, ranks, k, n, P.umat, P.rbuf[bi], tc);
+      k_mproj<<<blocks, 256, lds, s>>>(cur, M, ranks, k, n, tc, as_cap, P.umat, P.rbuf[bi]);
       QTT_LAUNCH_CHECK();
     }
     cur = P.rbuf[bi];

@@ -1164,8 +1164,8 @@ __device__ void mgs_cols(MP Z, int E, int ldz, int r, lds_ptr<const double> dg,
 // Z <- Q Z for the r columns of Z, Q = H_0 H_1 ... H_{E-3} (reflectors in A).
 // A 16-lane group owns columns g, g + NT/16, ...; it applies every reflector
 // to them in turn (no barrier between reflectors).
-template <int NT, class MP>
-__device__ void back_transform(MP A, lds_ptr<const double> bt, int E, int lda, MP Z,
+template <int NT, class MP, class MPZ>
+__device__ void back_transform(MP A, lds_ptr<const double> bt, int E, int lda, MPZ Z,
                                int ldz, int r) {
   const int tid = threadIdx.x;
   const int l16 = tid & 15, g16 = tid >> 4;
