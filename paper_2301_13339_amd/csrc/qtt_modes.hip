@@ -373,32 +373,107 @@ __device__ int meig_solve(const MEig& L, MP A, MPV V, int E, double tau2, int ca
                                               lds(L.perm), tau2, cap, k, so);
 }
 
-// Step k's truncated eigendecomposition.  Exact step (use_q = 0): G is m x m
-// and U = V[:, :r].  Randomised step (use_q = 1): G is G_B (q x q) and
-// U = Q V[:, :r].  Writes ranks[k], core k and U (m x r, row-major) to umat.
+// Step k's truncated eigendecomposition.  Writes ranks[k], core k and U
+// (m x r, row-major) to umat.
+//   use_q = 0, exact step:      G is m x m and U = V[:, :r];
+//   use_q = 1, randomised step: G is G_B (q x q) and U = Q V[:, :r];
+//   use_q = 2, exact step on a short unfolding (Q = A_k itself, n = ncol
+//   columns, n <= 64): for m > n, A = Q_A R_A by Gram-Schmidt (applied
+//   twice) in LDS, G = R_A R_A^T (n x n, the same nonzero eigenvalues as
+//   A A^T) and U = Q_A V[:, :r]; for m <= n, G = A A^T formed here.
 __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, int32_t* ranks,
                                                       int k, int use_q, const double* Q,
                                                       const int32_t* iq, double* scal,
                                                       int cap_k, double* cores, long long off_k,
                                                       double* umat, double* gV,
-                                                      int set_tau, double eps, int K) {
+                                                      int set_tau, double eps, int K, int ncol) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int rp = ranks[k - 1];
   const int m = M * rp;
-  const int q = use_q ? iq[0] : m;
+  const bool tall = use_q == 2 && m > ncol;  // uniform
+  const int q = use_q == 1 ? iq[0] : (tall ? ncol : m);
   const int E = q;
   const MEig L = meig_layout(smem, E, gV);
-  for (int e = tid; e < E * E; e += kEigThreads) {
-    const int a = e / E, b = e - a * E;
-    L.A[a * L.lda + b] = G[e];
-  }
-  if (set_tau && tid == 0) {
-    // exact first step: ||x||^2 is the trace of its Gram
-    double tr = 0.0;
-    for (int a = 0; a < E; ++a) tr += G[a * E + a];
-    scal[0] = tr;
-    scal[1] = (K > 1) ? eps * eps * tr / (double)(K - 1) : 0.0;
+  const double* Qsrc = Q;  // the basis U is taken in (use_q != 0)
+  if (use_q == 2) {
+    const int n = ncol;
+    const double* A = Q;  // A(a, c) = A[a + m c]
+    if (!tall) {
+      for (int e = tid; e < m * m; e += kEigThreads) {
+        const int a = e / m, b = e - a * m;
+        double t = 0.0;
+        for (int c = 0; c < n; ++c) t = fma(A[a + m * c], A[b + m * c], t);
+        L.A[a * L.lda + b] = t;
+      }
+    } else {
+      // Q_A (m x n, row-major) after the solver's arrays
+      double* Qa = reinterpret_cast<double*>(L.iscr + 8 + 256);
+      ldsd cn = lds(L.sx), al = lds(L.sx + 64), fr = lds(L.sx + 128);
+      for (int e = tid; e < m * n; e += kEigThreads) {
+        const int c = e / m, a = e - c * m;
+        Qa[a * n + c] = A[e];
+      }
+      __syncthreads();
+      if (tid < 64) {
+        double t = 0.0;
+        for (int e = tid; e < m * n; e += 64) t = fma(Qa[e], Qa[e], t);
+        t = sum64(t);
+        if (tid == 0) fr[0] = t;
+      }
+      __syncthreads();
+      const double fro2 = fr[0];
+      for (int j = 0; j < n; ++j) {
+        cgs2_col<kEigThreads>(lds(Qa), m, n, j, cn, al);
+        double t = col_norm2(lds(Qa), m, n, j);
+        if (!(t > 1e-28 * fro2)) {
+          // (numerically) dependent column: any unit vector orthogonal to
+          // the earlier ones; a dense deterministic start (an integer hash
+          // of (i, j)) has a component outside their span (j < n < m)
+          __syncthreads();
+          for (int i = tid; i < m; i += kEigThreads) {
+            const unsigned int h =
+                (unsigned int)(i + 1) * 2654435761u ^ (unsigned int)(j + 7) * 40503u;
+            Qa[i * n + j] = (double)(h >> 8) * (1.0 / 8388608.0) - 1.0;
+          }
+          __syncthreads();
+          cgs2_col<kEigThreads>(lds(Qa), m, n, j, cn, al);
+          t = col_norm2(lds(Qa), m, n, j);
+        }
+        const double inv = t > 0.0 ? 1.0 / sqrt(t) : 0.0;
+        __syncthreads();
+        for (int i = tid; i < m; i += kEigThreads) Qa[i * n + j] *= inv;
+        if (tid == 0) cn[j] = 1.0;
+        __syncthreads();
+      }
+      // R_A = Q_A^T A (in V), then G = R_A R_A^T
+      for (int e = tid; e < n * n; e += kEigThreads) {
+        const int c = e / n, c2 = e - c * n;
+        double t = 0.0;
+        for (int a = 0; a < m; ++a) t = fma(Qa[a * n + c], A[a + m * c2], t);
+        L.V[c * L.lda + c2] = t;
+      }
+      __syncthreads();
+      for (int e = tid; e < n * n; e += kEigThreads) {
+        const int i = e / n, j = e - i * n;
+        double t = 0.0;
+        for (int c = 0; c < n; ++c) t = fma(L.V[i * L.lda + c], L.V[j * L.lda + c], t);
+        L.A[i * L.lda + j] = t;
+      }
+      Qsrc = Qa;
+    }
+  } else {
+    for (int e = tid; e < E * E; e += kEigThreads) {
+      const int a = e / E, b = e - a * E;
+      L.A[a * L.lda + b] = G[e];
+    }
+    if (set_tau && tid == 0) {
+      // exact first step: ||x||^2 is the trace of its Gram
+      double tr = 0.0;
+      for (int a = 0; a < E; ++a) tr += G[a * E + a];
+      scal[0] = tr;
+      scal[1] = (K > 1) ? eps * eps * tr / (double)(K - 1) : 0.0;
+    }
   }
   __syncthreads();
   int r;
@@ -407,15 +482,16 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
   else
     r = meig_solve(L, lds(L.A), L.V, E, scal[1], cap_k, ranks, k);
   // U (m x r) and core k
+  const bool basis = use_q == 1 || tall;
   for (int e = tid; e < m * r; e += kEigThreads) {
     const int b = e % r, t = e / r;
     const int i = t % M, ai = t / M;   // core order (r_{k-1}, M, r_k)
     const int row = ai + rp * i;       // unfolding row of that entry
     const int col = L.perm[b];
     double u;
-    if (use_q) {
+    if (basis) {
       u = 0.0;
-      for (int c = 0; c < q; ++c) u = fma(Q[row * q + c], L.V[c * L.lda + col], u);
+      for (int c = 0; c < q; ++c) u = fma(Qsrc[row * q + c], L.V[c * L.lda + col], u);
     } else {
       u = L.V[row * L.lda + col];
     }
@@ -591,7 +667,9 @@ static size_t lds_meig() {
   const int lda = kMaxM + 1;
   const size_t big = sizeof(double) * (lda * lda + (kMaxM + 8) + kEigScratch) +
                      sizeof(int) * (kMaxM + 8 + 8 + 256);
-  return big > lds_meig_small() ? big : lds_meig_small();
+  // the short-unfolding step keeps Q_A (<= kMaxM x kEigLds) after the small layout
+  const size_t tall = lds_meig_small() + sizeof(double) * kMaxM * kEigLds;
+  return big > tall ? big : tall;
 }
 
 // Columns per tile: about kTileElems doubles of A, a multiple of 16 in
@@ -735,14 +813,21 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
     const int mcap = M * cap[k - 1];
     const bool rs = (method == 1) && ((long long)mcap < n ? (long long)mcap : n) > ell;
     int np = 0, ps = 0;
-    if (!rs) {
+    // an exact step on an unfolding with few columns works from A_k itself
+    const bool short_unf = !rs && k > 1 && n <= kEigLds && n < mcap;
+    if (short_unf) {
+      k_meig<<<1, kEigThreads, lds_meig(), s>>>(nullptr, M, ranks, k, 2, cur, P.iq, P.scal,
+                                                cap[k], cores, off, P.umat, P.gV, 0, eps, K,
+                                                (int)n);
+      QTT_LAUNCH_CHECK();
+    } else if (!rs) {
       rc = stream_pass(0, cur, M, mcap, ranks, k, n, &np, &ps, 0, seed, P, s);
       if (rc) return rc;
       rc = launch_reduce(P.partials, ps, np, mcap * mcap, P.gram, s);
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gram, M, ranks, k, 0, nullptr, P.iq, P.scal,
                                                 cap[k], cores, off, P.umat, P.gV,
-                                                (k == 1 && first_exact) ? 1 : 0, eps, K);
+                                                (k == 1 && first_exact) ? 1 : 0, eps, K, 0);
       QTT_LAUNCH_CHECK();
     } else {
       rc = stream_pass(1, cur, M, mcap, ranks, k, n, &np, &ps, ell, seed, P, s);
@@ -757,7 +842,7 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gramb, M, ranks, k, 1, P.q, P.iq, P.scal,
                                                 cap[k], cores, off, P.umat, P.gV, 0, eps,
-                                                K);
+                                                K, 0);
       QTT_LAUNCH_CHECK();
     }
     {
