@@ -51,6 +51,60 @@ __device__ __forceinline__ void mload_tile(const double* __restrict__ R, int m, 
   }
 }
 
+// Register staging of the next tile (at most 8 double2 per thread, so
+// tiles of <= kTileElems doubles): its loads are issued before the current
+// tile's products and land in LDS after them.  Needs R + m c0 16-byte
+// aligned for every tile (R aligned, tc even).
+struct TileStage {
+  double2 v[kTileElems / 512];
+  int tot;
+  __device__ __forceinline__ void load(const double* __restrict__ R, int m, long long c0,
+                                       int nc) {
+    const double2* s2 = reinterpret_cast<const double2*>(R + (long long)m * c0);
+    tot = m * nc;
+#pragma unroll
+    for (int p = 0; p < kTileElems / 512; ++p) {
+      const int e = threadIdx.x + 256 * p;
+      v[p] = e < (tot >> 1) ? s2[e] : make_double2(0.0, 0.0);
+    }
+  }
+  __device__ __forceinline__ void store(const double* __restrict__ R, int m, long long c0,
+                                        double* As) const {
+    double2* d2 = reinterpret_cast<double2*>(As);
+#pragma unroll
+    for (int p = 0; p < kTileElems / 512; ++p) {
+      const int e = threadIdx.x + 256 * p;
+      if (e < (tot >> 1)) d2[e] = v[p];
+    }
+    if ((tot & 1) && threadIdx.x == 0) As[tot - 1] = R[(long long)m * c0 + tot - 1];
+  }
+};
+
+// Tile t of the grid-stride loop into As: from the registers staged during
+// the previous tile when aligned (then the next tile is staged), else loaded
+// directly.
+__device__ __forceinline__ void next_tile(const double* __restrict__ R, int m, long long n,
+                                          int tc, long long t, bool aligned, TileStage& st,
+                                          double* As) {
+  const long long c0 = t * tc;
+  const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
+  if (aligned) {
+    st.store(R, m, c0, As);
+    const long long tn = t + gridDim.x;
+    if (tn * tc < n) {
+      const long long cn0 = tn * tc;
+      st.load(R, m, cn0, (int)((n - cn0) < tc ? (n - cn0) : tc));
+    }
+  } else {
+    mload_tile(R, m, c0, nc, As);
+  }
+}
+
+__device__ __forceinline__ bool stage_ok(const double* R, int m, int tc) {
+  return (reinterpret_cast<uintptr_t>(R) & 15) == 0 && (tc & 1) == 0 &&
+         (long long)m * tc <= kTileElems;
+}
+
 // Upper-triangle block idx (< nb (nb + 1) / 2) of an nb x nb block grid, in
 // the order (0,0), (0,1), ..., (0,nb-1), (1,1), ...
 __device__ __forceinline__ void tri_block(int idx, int nb, int& bi, int& bj) {
@@ -158,11 +212,17 @@ __global__ void __launch_bounds__(256) k_mgram(const double* __restrict__ R, int
     g[t] = mf64x4{0.0, 0.0, 0.0, 0.0};
   }
   const long long ntile = (n + tc - 1) / tc;
+  const bool aligned = stage_ok(R, m, tc);
+  TileStage st;
+  if (aligned && blockIdx.x < ntile) {
+    const long long c0 = (long long)blockIdx.x * tc;
+    st.load(R, m, c0, (int)((n - c0) < tc ? (n - c0) : tc));
+  }
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
     const long long c0 = t * tc;
     const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
     __syncthreads();
-    mload_tile(R, m, c0, nc, As);
+    next_tile(R, m, n, tc, t, aligned, st, As);
     __syncthreads();
     mfma_gram_tile<NA>(As, m, m, nc, bi, bj, on, SPLIT ? 0 : w, SPLIT ? 1 : 4, g);
   }
@@ -202,15 +262,23 @@ __global__ void __launch_bounds__(256) k_msketch(const double* __restrict__ R, i
     bj[t] = on[t] ? idx - (idx / EB) * EB : 0;
     g[t] = mf64x4{0.0, 0.0, 0.0, 0.0};
   }
+  // the padding columns ell .. EL - 1 of Om stay zero
+  for (int e = tid; e < tc * EL; e += 256) Om[e] = 0.0;
   const long long ntile = (n + tc - 1) / tc;
+  const bool aligned = stage_ok(R, m, tc);
+  TileStage st;
+  if (aligned && blockIdx.x < ntile) {
+    const long long c0 = (long long)blockIdx.x * tc;
+    st.load(R, m, c0, (int)((n - c0) < tc ? (n - c0) : tc));
+  }
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
     const long long c0 = t * tc;
     const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
     __syncthreads();
-    mload_tile(R, m, c0, nc, As);
-    for (int e = tid; e < tc * EL; e += 256) {
-      const int c = e / EL, j = e - c * EL;
-      Om[e] = (c < nc && j < ell) ? omega_entry(c0 + c, j, k, s0, s1) : 0.0;
+    next_tile(R, m, n, tc, t, aligned, st, As);
+    for (int e = tid; e < tc * ell; e += 256) {
+      const int c = e / ell, j = e - c * ell;
+      Om[c * EL + j] = c < nc ? omega_entry(c0 + c, j, k, s0, s1) : 0.0;
     }
     __syncthreads();
     const int ng = (nc + 3) >> 2;
@@ -315,11 +383,17 @@ __global__ void __launch_bounds__(256) k_mbgram(const double* __restrict__ R, in
     g[t] = mf64x4{0.0, 0.0, 0.0, 0.0};
   }
   const long long ntile = (n + tc - 1) / tc;
+  const bool aligned = stage_ok(R, m, tc);
+  TileStage st;
+  if (aligned && blockIdx.x < ntile) {
+    const long long c0 = (long long)blockIdx.x * tc;
+    st.load(R, m, c0, (int)((n - c0) < tc ? (n - c0) : tc));
+  }
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
     const long long c0 = t * tc;
     const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
     __syncthreads();
-    mload_tile(R, m, c0, nc, As);
+    next_tile(R, m, n, tc, t, aligned, st, As);
     __syncthreads();
     mfma_tile_times(As, m, nc, tc, Qs, q, [&](int c, int j, double v) { Bs[c * q + j] = v; });
     __syncthreads();
@@ -731,7 +805,6 @@ static int stream_pass(int which, const double* R, int M, int mcap, int32_t* ran
   const long long ntile = (n + tc - 1) / tc;
   const long long cap_parts = (long long)kModesPartials * P.pstride / sz;
   long long b = ntile < 1024 ? ntile : 1024;
-  if (sz >= 4096 && b > 512) b = 512;  // the reduction reads every partial once
   if (b > cap_parts) b = cap_parts;
   const int blocks = (int)(b < 1 ? 1 : b);
   *nparts = blocks;
