@@ -577,20 +577,24 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
 // Orthonormal basis of range(Y) (Y: m x ell, row-major): eigenvectors W of
 // C = Y^T Y with eigenvalues above 1e-24 of the largest, Q1 = Y W L^-1/2,
 // then Q = Q1 (3I - Q1^T Q1) / 2.  Writes Q (m x q, row-major) and iq[0] = q.
+// Y, and later Q1, are read from LDS (after the solver's arrays); Q1 passes
+// through global memory once, since it is formed from Y in place.
 __global__ void __launch_bounds__(kEigThreads) k_mqr(const double* Y, int M, const int32_t* ranks,
                                                      int k, int ell, double* Q1, double* Q,
                                                      int32_t* iq) {
   extern __shared__ double smem[];
   __shared__ int32_t rk[4];
-  __shared__ double Sq[kMsMaxEll * kMsMaxEll];
   const int tid = threadIdx.x;
   const int m = M * ranks[k - 1];
   const int E = ell;  // <= 64: LDS
   const MEig L = meig_layout(smem, E, nullptr);
+  double* Ys = reinterpret_cast<double*>(L.iscr + 8 + 256);  // <= kMaxM x kMsMaxEll
+  for (int e = tid; e < m * ell; e += kEigThreads) Ys[e] = Y[e];
+  __syncthreads();
   for (int e = tid; e < E * E; e += kEigThreads) {
     const int a = e / E, b = e - a * E;
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s = fma(Y[i * ell + a], Y[i * ell + b], s);
+    for (int i = 0; i < m; ++i) s = fma(Ys[i * ell + a], Ys[i * ell + b], s);
     L.A[a * L.lda + b] = s;
   }
   __syncthreads();
@@ -608,23 +612,26 @@ __global__ void __launch_bounds__(kEigThreads) k_mqr(const double* Y, int M, con
     for (int e = tid; e < m * qn; e += kEigThreads) {
       const int i = e / qn, b = e - i * qn;
       double s = 0.0;
-      for (int c = 0; c < ell; ++c) s = fma(Y[i * ell + c], L.V[c * L.lda + L.perm[b]], s);
+      for (int c = 0; c < ell; ++c) s = fma(Ys[i * ell + c], L.V[c * L.lda + L.perm[b]], s);
       Q1[e] = s / sqrt(L.lam[b]);
     }
   }
   __syncthreads();
-  // S = (3I - Q1^T Q1) / 2
+  for (int e = tid; e < m * qn; e += kEigThreads) Ys[e] = Q1[e];
+  __syncthreads();
+  // S = (3I - Q1^T Q1) / 2 in the matrix area (free after the solve)
+  double* Sq = L.A;
   for (int e = tid; e < qn * qn; e += kEigThreads) {
     const int a = e / qn, b = e - a * qn;
     double s = 0.0;
-    for (int i = 0; i < m; ++i) s = fma(Q1[i * qn + a], Q1[i * qn + b], s);
+    for (int i = 0; i < m; ++i) s = fma(Ys[i * qn + a], Ys[i * qn + b], s);
     Sq[e] = (a == b ? 1.5 : 0.0) - 0.5 * s;
   }
   __syncthreads();
   for (int e = tid; e < m * qn; e += kEigThreads) {
     const int i = e / qn, b = e - i * qn;
     double s = 0.0;
-    for (int c = 0; c < qn; ++c) s = fma(Q1[i * qn + c], Sq[c * qn + b], s);
+    for (int c = 0; c < qn; ++c) s = fma(Ys[i * qn + c], Sq[c * qn + b], s);
     Q[e] = s;
   }
   if (tid == 0) iq[0] = qn;
@@ -737,6 +744,7 @@ static size_t lds_meig_small() {
   return sizeof(double) * (2 * lda * lda + (kMaxM + 8) + kEigScratch) +
          sizeof(int) * (kMaxM + 8 + 8 + 256);
 }
+static size_t lds_mqr() { return lds_meig_small() + sizeof(double) * kMaxM * kMsMaxEll; }
 static size_t lds_meig() {
   const int lda = kMaxM + 1;
   const size_t big = sizeof(double) * (lda * lda + (kMaxM + 8) + kEigScratch) +
@@ -844,7 +852,7 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
     (void)hipFuncSetAttribute((const void*)k_meig, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds_meig());
     (void)hipFuncSetAttribute((const void*)k_mqr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds_meig_small());
+                        (int)lds_mqr());
     (void)hipFuncSetAttribute((const void*)k_mproj, hipFuncAttributeMaxDynamicSharedMemorySize,
                               kMaxStreamLds);
     (void)hipFuncSetAttribute((const void*)k_mbgram, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -907,7 +915,7 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       if (rc) return rc;
       rc = launch_reduce(P.partials, ps, np, mcap * ell, P.y, s);
       if (rc) return rc;
-      k_mqr<<<1, kEigThreads, lds_meig_small(), s>>>(P.y, M, ranks, k, ell, P.q1, P.q, P.iq);
+      k_mqr<<<1, kEigThreads, lds_mqr(), s>>>(P.y, M, ranks, k, ell, P.q1, P.q, P.iq);
       QTT_LAUNCH_CHECK();
       rc = stream_pass(2, cur, M, mcap, ranks, k, n, &np, &ps, ell, seed, P, s);
       if (rc) return rc;
