@@ -248,13 +248,13 @@ __global__ void __launch_bounds__(256) k_chain_gemm(const T* A, const T* B, T* C
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 template <int MODE, int SZ, int TK>
-__global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const double* B, double* C,
-                                                    const int32_t* ranks, int k, int Mh, int Nh) {
-  // SZ x SZ tile per workgroup; each wave an (SZ/2) x (SZ/2) quarter made of
-  // NB x NB blocks of 16 x 16
-  constexpr int LD = SZ + 4, NB = SZ / 32, PA = SZ * TK / 256;
-  __shared__ double As[2][TK][LD];
-  __shared__ double Bs[2][TK][LD];
+__device__ __forceinline__ void chain_tile(const double* A, const double* B, double* C,
+                                           const int32_t* ranks, int k, int Mh, int Nh,
+                                           int bx, int by, double (*As)[TK][SZ + 4],
+                                           double (*Bs)[TK][SZ + 4]) {
+  // SZ x SZ tile (bx, by) per workgroup; each wave an (SZ/2) x (SZ/2)
+  // quarter made of NB x NB blocks of 16 x 16
+  constexpr int NB = SZ / 32, PA = SZ * TK / 256;
   int M, N, K, rk = 0;
   if (MODE == GEMM_LEFT) {
     K = ranks[k - 1];
@@ -270,8 +270,8 @@ __global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const doubl
     K = ranks[k];
     N = Nh;
   }
-  const int row0 = blockIdx.y * SZ, col0 = blockIdx.x * SZ;
-  if (row0 >= M || col0 >= N) return;
+  const int row0 = by * SZ, col0 = bx * SZ;
+  if (row0 >= M || col0 >= N) return;  // uniform
   const int tid = threadIdx.x;
   const int w = tid >> 6, l = tid & 63;
   const int wr = (w >> 1) * (SZ / 2), wc = (w & 1) * (SZ / 2);
@@ -351,6 +351,33 @@ __global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const doubl
       }
 }
 
+template <int MODE, int SZ, int TK>
+__global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const double* B, double* C,
+                                                    const int32_t* ranks, int k, int Mh, int Nh) {
+  __shared__ double As[2][TK][SZ + 4];
+  __shared__ double Bs[2][TK][SZ + 4];
+  chain_tile<MODE, SZ, TK>(A, B, C, ranks, k, Mh, Nh, blockIdx.x, blockIdx.y, As, Bs);
+}
+
+// One step of the left chain and one of the right chain in a single launch
+// (they are independent until the final product): blocks 0 .. glx*gly - 1
+// take the left step's tiles, the rest the right step's.
+template <int SZ, int TK>
+__global__ void __launch_bounds__(256) k_chain_pair(const double* lamA, const double* coreL,
+                                                    double* dstL, int kl, int Mh, int glx,
+                                                    int gly, const double* coreR,
+                                                    const double* rhoB, double* dstR, int kr,
+                                                    int Nh, int grx, const int32_t* ranks) {
+  __shared__ double As[2][TK][SZ + 4];
+  __shared__ double Bs[2][TK][SZ + 4];
+  const int b = blockIdx.x, nl = glx * gly;
+  if (b < nl)
+    chain_tile<GEMM_LEFT, SZ, TK>(lamA, coreL, dstL, ranks, kl, Mh, 0, b % glx, b / glx, As, Bs);
+  else
+    chain_tile<GEMM_RIGHT, SZ, TK>(coreR, rhoB, dstR, ranks, kr, 0, Nh, (b - nl) % grx,
+                                   (b - nl) / grx, As, Bs);
+}
+
 // d == 1: out = core
 template <typename T>
 __global__ void k_copy_single(const T* core, T* out) {
@@ -406,10 +433,35 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
   int m;
   size_t le, re;
   full_sizes(d, cap, &m, &le, &re);
-  // left chain: Lam_1 = core 1 memory (2 x r_1)
+  // left chain: Lam_1 = core 1 memory (2 x r_1); right chain: Rho_d = core d
+  // memory (r_{d-1} x 2).  In FP64 the two chains advance together, one
+  // launch per pair of steps.
   const T* lam = cores + t.off[0];
   int li = 0;
-  for (int k = 2; k <= m; ++k) {
+  const T* rho = cores + t.off[d - 1];
+  int ri = 2;
+  int kl = 2, kr = d - 1;
+  if constexpr (sizeof(T) == 8) {
+    for (; kl <= m && kr >= m + 1; ++kl, --kr) {
+      T* dl = static_cast<T*>(bufs[li]);
+      T* dr = static_cast<T*>(bufs[ri]);
+      const int Mh = 1 << (kl - 1), Nh = 1 << (d - kr);
+      const int glx = (2 * cap[kl] + 31) / 32, gly = (Mh + 31) / 32;
+      const int grx = (Nh + 31) / 32, gry = (2 * cap[kr - 1] + 31) / 32;
+      {
+        ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
+        k_chain_pair<32, 32><<<glx * gly + grx * gry, 256, 0, stream>>>(
+            lam, cores + t.off[kl - 1], dl, kl, Mh, glx, gly, cores + t.off[kr - 1], rho, dr, kr,
+            Nh, grx, t.ranks);
+      }
+      QTT_LAUNCH_CHECK();
+      lam = dl;
+      li ^= 1;
+      rho = dr;
+      ri = ri == 2 ? 3 : 2;
+    }
+  }
+  for (int k = kl; k <= m; ++k) {
     T* dst = static_cast<T*>(bufs[li]);
     const int Mh = 1 << (k - 1);
     const int Ncap = 2 * cap[k];
@@ -428,10 +480,7 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     lam = dst;
     li ^= 1;
   }
-  // right chain: Rho_d = core d memory (r_{d-1} x 2)
-  const T* rho = cores + t.off[d - 1];
-  int ri = 2;
-  for (int k = d - 1; k >= m + 1; --k) {
+  for (int k = kr; k >= m + 1; --k) {
     T* dst = static_cast<T*>(bufs[ri]);
     const int Nh = 1 << (d - k);
     const int Mcap = 2 * cap[k - 1];
