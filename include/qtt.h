@@ -186,7 +186,6 @@ int qtt_decompose_modes(const double* x, int K, int M, double eps, int max_rank,
                         double* cores, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * QTT of the Toeplitz generator of the normalised sinc kernel./*
  * QTT of the Toeplitz generator of the normalised sinc kernel.
  * For N = 2^d the kernel is g_m = sinc(B x_m)/Z on x_m = -1/2 + m/N
  * (sinc(t) = sin(pi t)/(pi t), kernel (7.2) with B = 1/Delta_x and Z the
