@@ -84,3 +84,22 @@ def test_modes_arguments_rejected():
         q.decompose_modes(x, 10, 1e-3, 0, method="rsvd")        # rsvd needs a cap
     with pytest.raises(q.QttError):
         q.decompose_modes(x, 10, 1e-3, 10, method="rsvd", oversample=60)  # ell > 64
+
+
+@pytest.mark.parametrize("method,p", [("svd", 0), ("rsvd", 10)])
+def test_modes_unaligned_input_same_result(method, p):
+    """An input 8 bytes off 16-byte alignment takes the direct tile loads
+    instead of the register-staged ones: the same arithmetic, bit for bit."""
+    print("case: modes unaligned", method, flush=True)
+    K, M, R = 5, 10, 10
+    x = np.random.default_rng(5).random(M ** K)
+    buf = torch.zeros(M ** K + 1, dtype=torch.float64, device="cuda")
+    buf[1:] = torch.tensor(x, device="cuda")
+    xu = buf[1:]
+    assert xu.data_ptr() % 16 == 8
+    a = q.decompose_modes(xu, M, 0.0, R, method=method, oversample=p, seed=3)
+    b = q.decompose_modes(torch.tensor(x, device="cuda"), M, 0.0, R, method=method,
+                          oversample=p, seed=3)
+    assert a.ranks_host() == b.ranks_host()
+    for ca, cb in zip(a.core_list(), b.core_list()):
+        assert np.array_equal(ca, cb)
