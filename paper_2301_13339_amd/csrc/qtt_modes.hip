@@ -51,19 +51,20 @@ __device__ __forceinline__ void mload_tile(const double* __restrict__ R, int m, 
   }
 }
 
-// Register staging of the next tile (at most 8 double2 per thread, so
-// tiles of <= kTileElems doubles): its loads are issued before the current
-// tile's products and land in LDS after them.  Needs R + m c0 16-byte
-// aligned for every tile (R aligned, tc even).
+// Register staging of the next tile (NP double2 per thread, so tiles of
+// <= 512 NP doubles): its loads are issued before the current tile's
+// products and land in LDS after them.  Needs R + m c0 16-byte aligned for
+// every tile (R aligned, tc even).
+template <int NP = kTileElems / 512>
 struct TileStage {
-  double2 v[kTileElems / 512];
+  double2 v[NP];
   int tot;
   __device__ __forceinline__ void load(const double* __restrict__ R, int m, long long c0,
                                        int nc) {
     const double2* s2 = reinterpret_cast<const double2*>(R + (long long)m * c0);
     tot = m * nc;
 #pragma unroll
-    for (int p = 0; p < kTileElems / 512; ++p) {
+    for (int p = 0; p < NP; ++p) {
       const int e = threadIdx.x + 256 * p;
       v[p] = e < (tot >> 1) ? s2[e] : make_double2(0.0, 0.0);
     }
@@ -72,7 +73,7 @@ struct TileStage {
                                         double* As) const {
     double2* d2 = reinterpret_cast<double2*>(As);
 #pragma unroll
-    for (int p = 0; p < kTileElems / 512; ++p) {
+    for (int p = 0; p < NP; ++p) {
       const int e = threadIdx.x + 256 * p;
       if (e < (tot >> 1)) d2[e] = v[p];
     }
@@ -83,8 +84,9 @@ struct TileStage {
 // Tile t of the grid-stride loop into As: from the registers staged during
 // the previous tile when aligned (then the next tile is staged), else loaded
 // directly.
+template <int NP>
 __device__ __forceinline__ void next_tile(const double* __restrict__ R, int m, long long n,
-                                          int tc, long long t, bool aligned, TileStage& st,
+                                          int tc, long long t, bool aligned, TileStage<NP>& st,
                                           double* As) {
   const long long c0 = t * tc;
   const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
@@ -100,9 +102,10 @@ __device__ __forceinline__ void next_tile(const double* __restrict__ R, int m, l
   }
 }
 
-__device__ __forceinline__ bool stage_ok(const double* R, int m, int tc) {
+__device__ __forceinline__ bool stage_ok(const double* R, int m, int tc,
+                                         int cap = kTileElems) {
   return (reinterpret_cast<uintptr_t>(R) & 15) == 0 && (tc & 1) == 0 &&
-         (long long)m * tc <= kTileElems;
+         (long long)m * tc <= cap;
 }
 
 // Upper-triangle block idx (< nb (nb + 1) / 2) of an nb x nb block grid, in
@@ -213,7 +216,7 @@ __global__ void __launch_bounds__(256) k_mgram(const double* __restrict__ R, int
   }
   const long long ntile = (n + tc - 1) / tc;
   const bool aligned = stage_ok(R, m, tc);
-  TileStage st;
+  TileStage<> st;
   if (aligned && blockIdx.x < ntile) {
     const long long c0 = (long long)blockIdx.x * tc;
     st.load(R, m, c0, (int)((n - c0) < tc ? (n - c0) : tc));
@@ -266,7 +269,7 @@ __global__ void __launch_bounds__(256) k_msketch(const double* __restrict__ R, i
   for (int e = tid; e < tc * EL; e += 256) Om[e] = 0.0;
   const long long ntile = (n + tc - 1) / tc;
   const bool aligned = stage_ok(R, m, tc);
-  TileStage st;
+  TileStage<> st;
   if (aligned && blockIdx.x < ntile) {
     const long long c0 = (long long)blockIdx.x * tc;
     st.load(R, m, c0, (int)((n - c0) < tc ? (n - c0) : tc));
@@ -384,7 +387,7 @@ __global__ void __launch_bounds__(256) k_mbgram(const double* __restrict__ R, in
   }
   const long long ntile = (n + tc - 1) / tc;
   const bool aligned = stage_ok(R, m, tc);
-  TileStage st;
+  TileStage<> st;
   if (aligned && blockIdx.x < ntile) {
     const long long c0 = (long long)blockIdx.x * tc;
     st.load(R, m, c0, (int)((n - c0) < tc ? (n - c0) : tc));
@@ -652,11 +655,18 @@ __global__ void __launch_bounds__(256) k_mproj(const double* __restrict__ R, int
   double* Us = sm + as_cap;
   for (int e = threadIdx.x; e < m * r; e += 256) Us[e] = U[e];
   const long long ntile = (n + tc - 1) / tc;
+  constexpr int NP = 2 * kTileElems / 512;  // tiles up to 2 kTileElems doubles
+  const bool aligned = stage_ok(R, m, tc, 2 * kTileElems);
+  TileStage<NP> st;
+  if (aligned && blockIdx.x < ntile) {
+    const long long c0 = (long long)blockIdx.x * tc;
+    st.load(R, m, c0, (int)((n - c0) < tc ? (n - c0) : tc));
+  }
   for (long long t = blockIdx.x; t < ntile; t += gridDim.x) {
     const long long c0 = t * tc;
     const int nc = (int)((n - c0) < tc ? (n - c0) : tc);
     __syncthreads();
-    mload_tile(R, m, c0, nc, As);
+    next_tile(R, m, n, tc, t, aligned, st, As);
     __syncthreads();
     double* dst = Rn + (long long)r * c0;
     mfma_tile_times(As, m, nc, tc, Us, r, [&](int c, int b, double v) {
