@@ -5,14 +5,17 @@
 // m = M r_{k-1}, n = M^(K-k)) is stored contiguously, A_k(a, c) = R_k[a + m c].
 //   exact step:       one streaming pass forms G = A A^T (fixed-order sum of
 //                     per-block partials); the eigensolver gives U (m x r),
-//                     r by Algorithm 1's rule and the cap;
+//                     r by Algorithm 1's rule and the cap; on a short
+//                     unfolding (n <= 64, n < m) one workgroup takes A = Q R
+//                     and the eigenproblem of R R^T instead (k_meig);
 //   randomised step   (min(M cap_{k-1}, n) > R + p, Algorithms 4 and 5):
-//                     Y = A Omega (m x ell, Omega drawn on the fly), Q = an
+//                     Y = A Omega (m x ell, Omega drawn per tile), Q = an
 //                     orthonormal basis of range(Y) (eigenvectors of Y^T Y,
 //                     one Newton-Schulz polishing step), a second pass forms
 //                     G_B = (Q^T A)(Q^T A)^T, its eigenvectors U~ give U = Q U~;
 //   both:             R_{k+1} = U^T A (r x n), which is the next unfolding.
 // Core k is U read as (r_{k-1}, M, r_k): core[a][i][b] = U[a + r_{k-1} i][b].
+// Every streaming pass multiplies on the FP64 matrix cores.
 #include <math.h>
 
 #include "qtt_eig.hpp"
