@@ -37,6 +37,8 @@ CASES = [
     ("lowrank3_K6_M5", 6, 5, "lowrank", 1e-6, 0, "svd", 0),  # eps above the Gram floor
     ("lowrank3_K6_M5_rsvd", 6, 5, "lowrank", 1e-6, 8, "rsvd", 4),
     ("binary_K12", 12, 2, "uniform", 1e-2, 0, "svd", 0),
+    ("largest_mode_K3_M64", 3, 64, "uniform", 0.0, 0, "svd", 0),         # cap 128 // 64 = 2
+    ("K11_M3_rsvd_ell64", 11, 3, "uniform", 0.0, 40, "rsvd", 24),       # m up to 120, ell = 64
 ]
 
 
