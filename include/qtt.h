@@ -279,6 +279,23 @@ int qtt_query_full(int d, const int32_t* cap, int dtype, size_t* ws_bytes);
  */
 int qtt_full(const qtt_tensor* t, void* out, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * qtt_full without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same result as qtt_full (the same kernels); the interface
+ * matrices of the two half chains live in a fixed device array of the
+ * library, QTT_NOALLOC_SCRATCH_MIB MiB per device, held until the process
+ * ends.  Nothing is allocated or freed by the call.
+ *   t, out    as qtt_full
+ * Errors: as qtt_full; QTT_ENOSPC when the interface matrices need more than
+ * the array (qtt_query_full's workspace size above QTT_NOALLOC_SCRATCH_MIB
+ * MiB).  Every call on one device shares that device's array, so calls that
+ * overlap in time on one device (different streams or host threads without
+ * ordering) race and must be serialised by the caller.
+ */
+#define QTT_NOALLOC_SCRATCH_MIB 32
+int qtt_full_noalloc(const qtt_tensor* t, void* out, void* stream);
+
 /* --------------------------------------------------------------- adjoint */
 /*
  * Building blocks of the backward of y = T(w) full(F) (the convolution (2.2)

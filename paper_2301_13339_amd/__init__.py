@@ -371,6 +371,17 @@ def full(t: QTT, out: torch.Tensor | None = None) -> torch.Tensor:
     return out
 
 
+def full_noalloc(t: QTT, out: torch.Tensor) -> torch.Tensor:
+    """``full`` through ``qtt_full_noalloc``: no workspace, the library's fixed
+    device array holds the interface matrices (``out`` is the caller's)."""
+    if out.numel() != (1 << t.d) or out.dtype != _TORCH[t.dtype] or not out.is_contiguous():
+        raise ValueError("out must be a contiguous array of 2**d elements of the tensor's dtype")
+    tc = t._c()
+    _check(lib().qtt_full_noalloc(ctypes.byref(tc), ctypes.c_void_p(out.data_ptr()),
+                                  _stream(t.device)), "qtt_full_noalloc")
+    return out
+
+
 def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | None = None,
              round_method: str = "exact", round_max_rank: int = 0, shape2d=None,
              sketch_ell: int | None = None, sketch_seed: int = 0, delta: float = 0.0):

@@ -15,6 +15,7 @@ QTT_STATUS_RANKCAP = 2
 QTT_MAXD = 48
 QTT_MAX_RANK = 64
 QTT_BATCH_MAXD = 18
+QTT_NOALLOC_SCRATCH_MIB = 32
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(HERE, "libqtt.so")
@@ -26,7 +27,7 @@ EXPORTS = [
     "qtt_query_decompose_modes", "qtt_decompose_modes",
     "qtt_query_conv", "qtt_conv",
     "qtt_query_round", "qtt_round", "qtt_query_round_sketch", "qtt_round_sketch",
-    "qtt_query_full", "qtt_full",
+    "qtt_query_full", "qtt_full", "qtt_full_noalloc",
     "qtt_query_toeplitz", "qtt_toeplitz_apply",
     "qtt_query_kernel_sinc_dB", "qtt_kernel_sinc_dB",
     "qtt_query_full_adjoint", "qtt_full_adjoint",
@@ -116,6 +117,8 @@ def _declare(L):
     L.qtt_query_full.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _SZP]
     L.qtt_full.restype = ctypes.c_int
     L.qtt_full.argtypes = [_TP, _VP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_full_noalloc.restype = ctypes.c_int
+    L.qtt_full_noalloc.argtypes = [_TP, _VP, _VP]
     L.qtt_query_toeplitz.restype = ctypes.c_int
     L.qtt_query_toeplitz.argtypes = [ctypes.c_int, _I32P, ctypes.c_int, _SZP]
     L.qtt_toeplitz_apply.restype = ctypes.c_int
