@@ -13,10 +13,15 @@ seed >> 32)``; its first two output words ``x0, x1`` give the uniforms
 ``sqrt(-2 ln u1) cos(2 pi u2)`` gives one standard normal.
 
 Readings: Algorithm 4 is applied to the unfolding ``A`` (``m x n``) of each
-step with ``ell = k + p`` columns; with ``ell >= m`` the reduced QR of ``Y``
-gives an orthogonal ``m x m`` basis and the step is the exact SVD.  The rank
-of each step is then chosen from the singular values of ``B = Q^T A`` by the
-rule of Algorithm 1 (tolerance and cap), as in the plain sweep.
+step with ``ell = k + p`` columns.  With ``ell >= m`` the sketch ``Y``
+(``m x ell``, full row rank with probability one) spans all of ``R^m``, so
+``Q`` is an orthogonal ``m x m`` basis, ``B = Q^T A`` has the singular values
+of ``A`` and ``U = Q U~`` its left singular vectors: the step is the exact
+truncated SVD, and the sweep takes it directly without drawing ``Omega``.
+The rank of each step is then chosen from the singular values of
+``B = Q^T A`` by the rule of Algorithm 1 (tolerance and cap), as in the plain
+sweep.  ``Y = A Omega`` is accumulated over blocks of columns of ``A`` (rows
+of ``Omega``), so the test matrix is never held whole.
 """
 
 from __future__ import annotations
@@ -70,6 +75,27 @@ def gaussian_matrix(nrows: int, ncols: int, step: int, seed: int) -> np.ndarray:
     return z.reshape(nrows, ncols)
 
 
+def sketch_product(A, ell: int, step: int, seed: int, block: int = 1 << 15) -> np.ndarray:
+    """``Y = A Omega`` for the ``n x ell`` test matrix of ``step``, summed over
+    blocks of ``block`` rows of ``Omega`` (the same entries as
+    :func:`gaussian_matrix`; only one block is drawn at a time)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    Y = np.zeros((m, ell))
+    for r0 in range(0, n, block):
+        r1 = min(n, r0 + block)
+        row = np.repeat(np.arange(r0, r1, dtype=np.uint64), ell)
+        col = np.tile(np.arange(ell, dtype=np.uint64), r1 - r0)
+        zero = np.zeros_like(row)
+        x = philox4x32_10([row, col, zero + np.uint64(step), zero],
+                          [seed & _MASK, (seed >> 32) & _MASK])
+        u1 = (x[0].astype(np.float64) + 0.5) * 2.0 ** -32
+        u2 = (x[1].astype(np.float64) + 0.5) * 2.0 ** -32
+        om = (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).reshape(r1 - r0, ell)
+        Y += A[:, r0:r1] @ om
+    return Y
+
+
 def range_finder(A, omega) -> np.ndarray:
     """Algorithm 4: ``Y = A Omega``, ``Q R = Y``; returns ``Q``."""
     Y = np.asarray(A, dtype=np.float64) @ omega
@@ -89,12 +115,17 @@ def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0
     """Algorithm 1 with every truncated SVD taken by Algorithms 4 and 5.
 
     Same conventions as :func:`oracle.tt.tt_svd`; step ``k`` (1-based) draws
-    ``Omega`` of ``n_k x ell`` entries with ``step = k``.
+    ``Omega`` of ``n_k x ell`` entries with ``step = k`` when ``ell`` is below
+    the unfolding's row count ``m_k`` and takes the exact SVD otherwise (see
+    the module docstring).  ``info`` also holds ``sketched`` (the steps that
+    drew ``Omega``) and ``margin``: the smallest ``|tail^2 - tau^2| / tau^2``
+    over the decisions the threshold made (as in :func:`oracle.tt.tt_svd`),
+    which flags rank decisions that a perturbation of ``B`` can flip.
     """
     v = np.asarray(a, dtype=np.float64).ravel()
     K = tt.log2_exact(v.size)
     norm = float(np.linalg.norm(v))
-    info = {"norm": norm, "ranks": [1], "sv": []}
+    info = {"norm": norm, "ranks": [1], "sv": [], "sketched": [], "margin": math.inf}
     if K == 1:
         cores = [v.reshape(1, 2, 1).copy()]
         info["ranks"].append(1)
@@ -105,11 +136,20 @@ def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0
     rem = v.reshape((1, -1), order="F")
     for k in range(1, K):
         A = rem.reshape((2 * r_prev, -1), order="F")
-        omega = gaussian_matrix(A.shape[1], ell, k, seed)
-        Q = range_finder(A, omega)
-        U, s, Vt = rsvd(A, Q)
+        if ell >= A.shape[0]:
+            U, s, Vt = np.linalg.svd(A, full_matrices=False)
+        else:
+            Q, _ = np.linalg.qr(sketch_product(A, ell, k, seed), mode="reduced")
+            U, s, Vt = rsvd(A, Q)
+            info["sketched"].append(k)
         r = tt.truncation_rank(s, tau, max_rank)
         info["sv"].append(s.copy())
+        if tau > 0:
+            tails = np.concatenate([np.cumsum((s * s)[::-1])[::-1], [0.0]])
+            r_eps = tt.truncation_rank(s, tau, 0)
+            if max_rank <= 0 or r_eps <= max_rank:
+                for t in [tails[r_eps]] + ([tails[r_eps - 1]] if r_eps >= 1 else []):
+                    info["margin"] = min(info["margin"], abs(t - tau * tau) / (tau * tau))
         U, Vt = tt._gauge(U[:, :r].copy(), Vt[:r, :].copy())
         cores.append(U.reshape((r_prev, 2, r), order="F"))
         rem = s[:r, None] * Vt

@@ -79,3 +79,68 @@ def test_sketched_ttsvd_near_optimal_on_smooth_data():
     b = rsvd.tt_svd_sketch(x, eps, 0, ell=12, seed=5)
     err = np.linalg.norm(tt.tt_full(b) - x) / np.linalg.norm(x)
     assert err <= 2 * eps
+
+
+@pytest.mark.parametrize("block", [1, 7, 64, 1 << 15])
+def test_sketch_product_blocks_equal_the_whole_test_matrix(block):
+    """Y = A Omega summed over row blocks of Omega equals the product with the
+    whole matrix of gaussian_matrix (the same entries, another summation order)."""
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((9, 300))
+    want = A @ rsvd.gaussian_matrix(300, 11, 4, 99)
+    got = rsvd.sketch_product(A, 11, 4, 99, block=block)
+    assert np.allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+
+
+def test_range_finder_with_ell_at_least_m_is_the_exact_svd():
+    """Algorithm 4 with ell >= m: Y spans R^m, so Algorithm 5 returns the exact
+    singular values and the same leading subspaces as the SVD of A (the
+    reading that lets the sketched sweep take the exact step there)."""
+    rng = np.random.default_rng(4)
+    m, n = 12, 500
+    A = (rng.standard_normal((m, m)) * np.geomspace(1, 1e-3, m)) @ rng.standard_normal((m, n))
+    for ell in (m, m + 4, 64):
+        Q = rsvd.range_finder(A, rsvd.gaussian_matrix(n, ell, 2, 5))
+        U, s, Vt = rsvd.rsvd(A, Q)
+        U0, s0, Vt0 = np.linalg.svd(A, full_matrices=False)
+        assert np.allclose(s[:m], s0, rtol=1e-12, atol=0)
+        for r in (1, 4, 9):
+            P, P0 = U[:, :r] @ U[:, :r].T, U0[:, :r] @ U0[:, :r].T
+            assert np.abs(P - P0).max() <= 1e-10
+
+
+def _sweep_always_sketching(x, eps, ell, seed):
+    """The sketched sweep with Algorithms 4/5 at every step, Omega drawn whole."""
+    v = np.asarray(x, dtype=np.float64)
+    K = tt.log2_exact(v.size)
+    tau = eps * np.linalg.norm(v) / np.sqrt(K - 1)
+    cores, ranks, r_prev = [], [1], 1
+    rem = v.reshape((1, -1), order="F")
+    for k in range(1, K):
+        A = rem.reshape((2 * r_prev, -1), order="F")
+        Q = rsvd.range_finder(A, rsvd.gaussian_matrix(A.shape[1], ell, k, seed))
+        U, s, Vt = rsvd.rsvd(A, Q)
+        r = tt.truncation_rank(s, tau, 0)
+        cores.append(U[:, :r].reshape((r_prev, 2, r), order="F"))
+        rem = s[:r, None] * Vt[:r, :]
+        ranks.append(r)
+        r_prev = r
+    cores.append(rem.reshape((r_prev, 2, 1), order="F"))
+    return cores, ranks + [1]
+
+
+def test_sketched_sweep_matches_the_literal_algorithms():
+    """tt_svd_sketch (exact step where ell >= m, blocked sketch product
+    elsewhere) against the sweep that applies Algorithms 4/5 at every step
+    with the whole test matrix: same ranks and tensor."""
+    n = 1 << 12
+    t = np.arange(n) / n
+    rng = np.random.default_rng(6)
+    x = np.exp(-((t - 0.3) ** 2) / 0.002) + 0.4 * np.cos(50 * t) + 1e-3 * rng.standard_normal(n)
+    eps, ell, seed = 1e-3, 10, 8
+    b, info = rsvd.tt_svd_sketch(x, eps, 0, ell=ell, seed=seed, return_info=True)
+    c, ranks = _sweep_always_sketching(x, eps, ell, seed)
+    assert info["sketched"], "the case must reach steps with ell < m"
+    assert info["margin"] > 1e-6
+    assert info["ranks"] == ranks
+    assert np.linalg.norm(tt.tt_full(b) - tt.tt_full(c)) <= 1e-10 * np.linalg.norm(x)
