@@ -44,14 +44,14 @@ def _toeplitz(f, w, fft):
 
 def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None = None,
                 round_max_rank: int = 0, fft: bool | None = None, sketch_ell: int = 0,
-                sketch_seed: int = 0, delta: float = 0.0):
+                sketch_seed: int = 0, delta: float = 0.0, sketch_operands: str = "f64"):
     """Run the composed pipeline on a 1-D signal of length ``2**d``.
 
     ``fft`` selects the DFT route for the exact convolution (default: on for
     ``d > 14``); both routes compute the same sum.  ``sketch_ell > 0`` takes
     the rounding's truncated SVDs from Algorithms 4 and 5 (``ell`` columns,
-    ``sketch_seed``); ``delta > 0`` adds the drop-off cut (exact rounding
-    only).  Returns a dict with the cores, the intermediate full arrays,
+    ``sketch_seed``, sketch operands ``sketch_operands``: ``"f64"`` or
+    ``"bf16"``); ``delta > 0`` adds the drop-off cut (exact rounding only).  Returns a dict with the cores, the intermediate full arrays,
     ranks and the output.
     """
     x = np.asarray(x, dtype=np.float64).ravel()
@@ -68,7 +68,7 @@ def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None 
     y = _toeplitz(f_t, w_t, fft)
     if sketch_ell > 0:
         Z, zinfo = rsvd.tt_svd_sketch(y, eps, round_max_rank, sketch_ell, sketch_seed,
-                                      return_info=True)
+                                      return_info=True, operands=sketch_operands)
     else:
         Z, zinfo = tt.tt_svd(y, eps, round_max_rank, return_info=True, delta=delta)
     out = tt.tt_full(Z)
@@ -79,15 +79,16 @@ def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None 
 
 def pipeline_2d(img, Bx: float, By: float, eps: float, max_rank: int = 0,
                 eps_w: float | None = None, round_max_rank: int = 0, fft: bool = True,
-                sketch_ell: int = 0, sketch_seed: int = 0):
+                sketch_ell: int = 0, sketch_seed: int = 0, delta: float = 0.0,
+                sketch_operands: str = "f64"):
     """Run the composed pipeline on a row-major ``2**dy x 2**dx`` image
-    (``sketch_ell`` as in :func:`pipeline_1d`)."""
+    (``sketch_*`` and ``delta`` as in :func:`pipeline_1d`)."""
     img = np.asarray(img, dtype=np.float64)
     ny, nx = img.shape
     dy, dx = tt.log2_exact(ny), tt.log2_exact(nx)
     if eps_w is None:
         eps_w = eps / 10.0
-    F, finfo = tt.tt_svd(img.ravel(), eps, max_rank, return_info=True)
+    F, finfo = tt.tt_svd(img.ravel(), eps, max_rank, return_info=True, delta=delta)
     f_t = tt.tt_full(F).reshape(ny, nx)
     wx = conv.toeplitz_generator(dx, Bx)
     wy = conv.toeplitz_generator(dy, By)
@@ -97,13 +98,13 @@ def pipeline_2d(img, Bx: float, By: float, eps: float, max_rank: int = 0,
     y = conv.toeplitz_apply_2d(f_t, wy_t, wx_t, fft=fft)
     if sketch_ell > 0:
         Z, zinfo = rsvd.tt_svd_sketch(y.ravel(), eps, round_max_rank, sketch_ell, sketch_seed,
-                                      return_info=True)
+                                      return_info=True, operands=sketch_operands)
     else:
-        Z, zinfo = tt.tt_svd(y.ravel(), eps, round_max_rank, return_info=True)
+        Z, zinfo = tt.tt_svd(y.ravel(), eps, round_max_rank, return_info=True, delta=delta)
     out = tt.tt_full(Z).reshape(ny, nx)
     return dict(F=F, Wx=Wx, Wy=Wy, Z=Z, f_tilde=f_t, wx_tilde=wx_t, wy_tilde=wy_t, y=y,
                 out=out, F_ranks=finfo["ranks"], Wx_ranks=wxinfo["ranks"],
-                Wy_ranks=wyinfo["ranks"], Z_ranks=zinfo["ranks"], Z_info=zinfo)
+                Wy_ranks=wyinfo["ranks"], Z_ranks=zinfo["ranks"], F_info=finfo, Z_info=zinfo)
 
 
 def clean_reference_1d(clean, B: float) -> np.ndarray:

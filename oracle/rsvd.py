@@ -75,11 +75,30 @@ def gaussian_matrix(nrows: int, ncols: int, step: int, seed: int) -> np.ndarray:
     return z.reshape(nrows, ncols)
 
 
-def sketch_product(A, ell: int, step: int, seed: int, block: int = 1 << 15) -> np.ndarray:
+def round_bf16(x) -> np.ndarray:
+    """Each value rounded to single precision, then to bfloat16 (8 significant
+    bits, round to nearest, ties to even), returned as float64."""
+    f = np.ascontiguousarray(np.asarray(x, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    finite = (u & 0x7F800000) != 0x7F800000
+    u = np.where(finite, u + 0x7FFF + ((u >> 16) & 1), u) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def sketch_product(A, ell: int, step: int, seed: int, block: int = 1 << 15,
+                   operands: str = "f64") -> np.ndarray:
     """``Y = A Omega`` for the ``n x ell`` test matrix of ``step``, summed over
     blocks of ``block`` rows of ``Omega`` (the same entries as
-    :func:`gaussian_matrix`; only one block is drawn at a time)."""
+    :func:`gaussian_matrix`; only one block is drawn at a time).
+
+    ``operands="bf16"`` rounds the entries of ``A`` and ``Omega`` to bfloat16
+    (:func:`round_bf16`) before the product, which is then exact in float64:
+    the values a sketch with bfloat16 operands multiplies."""
     A = np.asarray(A, dtype=np.float64)
+    if operands == "bf16":
+        A = round_bf16(A)
+    elif operands != "f64":
+        raise ValueError(operands)
     m, n = A.shape
     Y = np.zeros((m, ell))
     for r0 in range(0, n, block):
@@ -92,6 +111,8 @@ def sketch_product(A, ell: int, step: int, seed: int, block: int = 1 << 15) -> n
         u1 = (x[0].astype(np.float64) + 0.5) * 2.0 ** -32
         u2 = (x[1].astype(np.float64) + 0.5) * 2.0 ** -32
         om = (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).reshape(r1 - r0, ell)
+        if operands == "bf16":
+            om = round_bf16(om)
         Y += A[:, r0:r1] @ om
     return Y
 
@@ -111,7 +132,7 @@ def rsvd(A, Q):
 
 
 def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0,
-                  return_info: bool = False):
+                  return_info: bool = False, operands: str = "f64"):
     """Algorithm 1 with every truncated SVD taken by Algorithms 4 and 5.
 
     Same conventions as :func:`oracle.tt.tt_svd`; step ``k`` (1-based) draws
@@ -121,6 +142,8 @@ def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0
     drew ``Omega``) and ``margin``: the smallest ``|tail^2 - tau^2| / tau^2``
     over the decisions the threshold made (as in :func:`oracle.tt.tt_svd`),
     which flags rank decisions that a perturbation of ``B`` can flip.
+    ``operands`` is passed to :func:`sketch_product` (the sketch ``Y`` only;
+    ``Q``, ``B = Q^T A`` and its SVD stay in float64).
     """
     v = np.asarray(a, dtype=np.float64).ravel()
     K = tt.log2_exact(v.size)
@@ -139,7 +162,8 @@ def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0
         if ell >= A.shape[0]:
             U, s, Vt = np.linalg.svd(A, full_matrices=False)
         else:
-            Q, _ = np.linalg.qr(sketch_product(A, ell, k, seed), mode="reduced")
+            Q, _ = np.linalg.qr(sketch_product(A, ell, k, seed, operands=operands),
+                                mode="reduced")
             U, s, Vt = rsvd(A, Q)
             info["sketched"].append(k)
         r = tt.truncation_rank(s, tau, max_rank)

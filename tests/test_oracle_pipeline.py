@@ -52,6 +52,52 @@ def test_pipeline_2d_separable():
     assert res["out"].shape == noisy.shape
 
 
+def test_pipeline_2d_dropoff_composition():
+    """The drop-off cut (modification (3) of Section 5) in the 2-D pipeline acts on
+    the data decomposition and on the rounding, as in the 1-D pipeline."""
+    _, clean, _, _ = G.paper_example3(7)
+    noisy = np.zeros((64, 64))
+    noisy[:63, :63] = clean
+    delta = 0.05
+    res = pipeline.pipeline_2d(noisy, 12.0, 12.0, 0.0, max_rank=64, round_max_rank=64,
+                               fft=False, delta=delta)
+    _, finfo = tt.tt_svd(noisy.ravel(), 0.0, 64, return_info=True, delta=delta)
+    assert res["F_ranks"] == finfo["ranks"]
+    _, zinfo = tt.tt_svd(res["y"].ravel(), 0.0, 64, return_info=True, delta=delta)
+    assert res["Z_ranks"] == zinfo["ranks"]
+    plain = pipeline.pipeline_2d(noisy, 12.0, 12.0, 0.0, max_rank=64, round_max_rank=64,
+                                 fft=False)
+    assert all(a <= b for a, b in zip(res["F_ranks"], plain["F_ranks"]))
+    assert sum(res["F_ranks"]) < sum(plain["F_ranks"])
+
+
+def test_kernel_core_gradients_central_differences_d10():
+    """dL/dW_k for the kernel cores W (d + 1 modes) of L = ||T(full(W)) full(F) - t||^2:
+    the adjoint of Full applied to dL/dw, against central differences (h = 1e-6)."""
+    d = 10
+    noisy, clean = G.gaussian_bumps_1d(d, seed=6)
+    F = tt.tt_svd(noisy, 1e-4, 6)
+    W = tt.tt_svd(conv.toeplitz_generator(d, 220.0), 1e-6)
+    target = conv.toeplitz_apply(clean, conv.toeplitz_generator(d, 200.0))
+    _, _, _, gw, _ = grads.grads(F, 220.0, target, w=tt.tt_full(W))
+    gW = grads.full_adjoint(W, gw)
+    h = 1e-6
+    rng = np.random.default_rng(1)
+
+    def lossW(Wc):
+        return grads.loss(F, 220.0, target, w=tt.tt_full(Wc))
+
+    for k in (0, 4, d - 1, d):
+        for _ in range(3):
+            idx = tuple(int(rng.integers(0, s)) for s in W[k].shape)
+            c2 = [c.copy() for c in W]
+            c2[k][idx] += h
+            lp = lossW(c2)
+            c2[k][idx] -= 2 * h
+            lm = lossW(c2)
+            assert gW[k][idx] == pytest.approx((lp - lm) / (2 * h), rel=1e-5, abs=1e-8)
+
+
 def test_grads_central_differences_d10():
     d = 10
     noisy, clean = G.gaussian_bumps_1d(d, seed=5)

@@ -144,3 +144,37 @@ def test_sketched_sweep_matches_the_literal_algorithms():
     assert info["margin"] > 1e-6
     assert info["ranks"] == ranks
     assert np.linalg.norm(tt.tt_full(b) - tt.tt_full(c)) <= 1e-10 * np.linalg.norm(x)
+
+
+def test_round_bf16_known_values():
+    """bfloat16 keeps 8 significant bits: neighbours of 1 are 1 - 2^-8 and 1 + 2^-7;
+    halfway cases go to the even significand."""
+    cases = [
+        (1.0, 1.0),
+        (1.0 + 2.0 ** -8, 1.0),                           # halfway, 1 is even
+        (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),           # halfway, round up to even
+        (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),  # above halfway
+        (-3.0, -3.0),
+        (0.1, 0.10009765625),                             # 0x3DCD in bfloat16
+        (0.0, 0.0),
+        (2.0 ** -130, 2.0 ** -130),                        # subnormal in float32, exact
+    ]
+    for x, want in cases:
+        assert rsvd.round_bf16(np.array([x]))[0] == want, x
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(10000) * 10.0 ** rng.uniform(-20, 20, 10000)
+    r = rsvd.round_bf16(v)
+    assert np.all(np.abs(r - v) <= 2.0 ** -8 * np.abs(v))
+    assert np.array_equal(rsvd.round_bf16(r), r)
+
+
+def test_sketch_product_bf16_operands_is_the_product_of_rounded_values():
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((6, 200))
+    om = rsvd.gaussian_matrix(200, 5, 3, 17)
+    want = rsvd.round_bf16(A) @ rsvd.round_bf16(om)
+    got = rsvd.sketch_product(A, 5, 3, 17, block=64, operands="bf16")
+    assert np.allclose(got, want, rtol=0, atol=1e-13 * np.abs(want).max())
+    # the rounding moves the sketch by about 2^-8 relative, not more
+    full = A @ om
+    assert np.linalg.norm(got - full) <= 2.0 ** -6 * np.linalg.norm(full)
