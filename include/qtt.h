@@ -351,20 +351,39 @@ int qtt_query_full_adjoint(int d, const int32_t* cap, int dtype, size_t* ws_byte
 int qtt_full_adjoint(const qtt_tensor* f, const void* g, qtt_tensor* grad, void* ws,
                      size_t ws_bytes, void* stream);
 
-/* Workspace of qtt_conv_full_backward (wdb_cap may be NULL). */
+/*
+ * Workspace of qtt_conv_full_backward (wdb_cap may be NULL; want_w = 1 when
+ * the kernel-core gradient grad_w will be asked for).  With want_w the
+ * workspace holds the d forward-product states Q_1..Q_d of
+ * 2 w_cap[k] 2^d doubles each, so pass a generator whose capacities equal
+ * its ranks (about 14 GB at d = 22 and ranks near 10).
+ */
 int qtt_query_conv_full_backward(int d, const int32_t* f_cap, const int32_t* w_cap,
-                                 const int32_t* wdb_cap, int dtype, size_t* ws_bytes);
+                                 const int32_t* wdb_cap, int want_w, int dtype,
+                                 size_t* ws_bytes);
 
 /*
- * Backward of y = T(w) full(f) for an upstream gradient grad_y (2^d
- * elements): grad_f = qtt_full_adjoint(f, T(w)^T grad_y); if w_dB (from
- * qtt_kernel_sinc_dB) is given, *grad_B (one device double) =
- * <grad_y, T(w_dB) full(f)>.  full(f) is recomputed, not taken from the
- * forward.  w_dB and grad_B are both NULL or both non-NULL.
+ * Backward of y = T(w) full(f) = full(qtt_conv(f, w)) for an upstream
+ * gradient grad_y = dL/dy (2^d elements), at the ranks of f and w:
+ *   grad_f  = qtt_full_adjoint(f, T(w)^T grad_y)  (every signal core);
+ *   grad_w  (optional, NULL to skip; w's d, dtype and capacities): the
+ *             gradient with respect to every core of the generator QTT w
+ *             (d+1 modes).  Core k contracts the state of the transposed
+ *             product before mode k (grad_y pushed through modes 1..k-1 of
+ *             T(w)^T) with the state of the forward product after it (full(f)
+ *             pushed through modes k+1..d of T(w) from the top), through the
+ *             carry structure of the binary adder of mode k; ranks copied
+ *             from w;
+ *   *grad_B  (one device double, with w_dB from qtt_kernel_sinc_dB) =
+ *             <grad_y, T(w_dB) full(f)>.
+ * full(f) is recomputed, not taken from the forward; every sum is FP64 in a
+ * fixed order.  w_dB and grad_B are both NULL or both non-NULL.  The paper
+ * gives no derivative: these follow from the chain rule applied to the
+ * convolution (2.2) and Algorithm 3.
  */
 int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_tensor* w_dB,
-                           const void* grad_y, qtt_tensor* grad_f, double* grad_B, void* ws,
-                           size_t ws_bytes, void* stream);
+                           const void* grad_y, qtt_tensor* grad_f, qtt_tensor* grad_w,
+                           double* grad_B, void* ws, size_t ws_bytes, void* stream);
 
 /* ---------------------------------------------------------------- batched */
 /*

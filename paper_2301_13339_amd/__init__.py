@@ -141,6 +141,20 @@ class QTT:
             o += self.cap[k] * 2 * self.cap[k + 1]
         return offs
 
+    def compact(self) -> "QTT":
+        """A copy whose capacities equal the actual ranks (reads the ranks once)."""
+        r = self.ranks_host()
+        t = QTT(self.d, self.dtype, r, self.device)
+        offs = self.core_offsets()
+        o = 0
+        for k in range(self.d):
+            n = r[k] * 2 * r[k + 1]
+            t.cores[o:o + n].copy_(self.cores[offs[k]:offs[k] + n])
+            o += n
+        t.ranks.copy_(self.ranks)
+        t.status.copy_(self.status)
+        return t
+
     def core_list(self):
         """Cores as CPU float64 numpy arrays of shape ``(r_{k-1}, 2, r_k)``."""
         r = self.ranks_host()
@@ -511,8 +525,12 @@ def full_adjoint(f: QTT, g: torch.Tensor) -> QTT:
     return gr
 
 
-def conv_full_backward(f: QTT, w: QTT, w_dB: QTT | None, grad_y: torch.Tensor):
-    """``(grad_f, grad_B)`` of ``y = T(w) full(f)`` for the upstream gradient ``grad_y``."""
+def conv_full_backward(f: QTT, w: QTT, w_dB: QTT | None, grad_y: torch.Tensor,
+                       grad_w: bool = False):
+    """``(grad_f, grad_w, grad_B)`` of ``y = T(w) full(f) = full(conv(f, w))`` for the
+    upstream gradient ``grad_y``; ``grad_w`` (the kernel cores) only when asked
+    for, ``grad_B`` only with ``w_dB``.  For ``grad_w`` pass a compact ``w``
+    (``w.compact()``): the workspace keeps d states sized by its capacities."""
     if grad_y.dtype != _TORCH[f.dtype] or grad_y.numel() != (1 << f.d):
         raise QttError(-1, "conv_full_backward: grad_y must have 2^d entries of f's dtype")
     grad_y = grad_y.contiguous()
@@ -520,19 +538,23 @@ def conv_full_backward(f: QTT, w: QTT, w_dB: QTT | None, grad_y: torch.Tensor):
     wcap = (ctypes.c_int32 * (w.d + 1))(*w.cap)
     bcap = (ctypes.c_int32 * (w_dB.d + 1))(*w_dB.cap) if w_dB is not None else None
     wsb = ctypes.c_size_t()
-    _check(lib().qtt_query_conv_full_backward(f.d, fcap, wcap, bcap, f.dtype, ctypes.byref(wsb)),
+    _check(lib().qtt_query_conv_full_backward(f.d, fcap, wcap, bcap, int(bool(grad_w)), f.dtype,
+                                              ctypes.byref(wsb)),
            "qtt_query_conv_full_backward")
     gr = _grad_like(f)
+    gw = _grad_like(w) if grad_w else None
     gB = torch.zeros(1, dtype=torch.float64, device=f.device) if w_dB is not None else None
     ws = _workspace(wsb.value, f.device)
     fc, wc, gc = f._c(), w._c(), gr._c()
+    gwc = gw._c() if gw is not None else None
     bc = w_dB._c() if w_dB is not None else None
     _check(lib().qtt_conv_full_backward(
         ctypes.byref(fc), ctypes.byref(wc), ctypes.byref(bc) if bc is not None else None,
         ctypes.c_void_p(grad_y.data_ptr()), ctypes.byref(gc),
+        ctypes.byref(gwc) if gwc is not None else None,
         ctypes.c_void_p(gB.data_ptr()) if gB is not None else None,
         ctypes.c_void_p(ws.data_ptr()), wsb.value, _stream(f.device)), "qtt_conv_full_backward")
-    return gr, gB
+    return gr, gw, gB
 
 
 def _with_cores(template: QTT, cores: torch.Tensor) -> QTT:
@@ -546,43 +568,54 @@ def _with_cores(template: QTT, cores: torch.Tensor) -> QTT:
 
 
 class ConvFull(torch.autograd.Function):
-    """``y = T(w(B)) full(F)`` at fixed ranks, differentiable in the cores and ``B``.
+    """``y = full(conv(F, W)) = T(w) full(F)`` at fixed ranks, differentiable in the
+    signal cores, the kernel cores and the bandwidth ``B``.
 
-    ``forward(cores, B, template, eps_w, eps_dB)``: ``cores`` is the flat
-    capacity-strided core array of ``template`` (a QTT whose ranks are kept);
-    ``B`` a one-element tensor.  The kernel QTT ``w(B)`` is built at
-    ``eps_w``; the backward builds the QTT of ``dw/dB`` at ``eps_dB`` and
-    recomputes ``full(F)`` instead of storing it.
+    ``forward(cores, wcores, B, template, wtemplate, eps_dB)``: ``cores`` and
+    ``wcores`` are the flat capacity-strided core arrays of ``template`` (the
+    signal QTT) and ``wtemplate`` (the kernel generator QTT, d+1 modes), whose
+    ranks are kept; ``B`` is a one-element tensor.  The forward convolves in
+    QTT format (``qtt_conv``) and reconstructs (``qtt_full``).  The backward
+    recomputes ``full(F)`` instead of storing it; ``dL/dB`` takes the QTT of
+    ``dw/dB`` built at ``eps_dB`` (the kernel cores are treated as the
+    generator they approximate).
     """
 
     @staticmethod
-    def forward(ctx, cores, B, template, eps_w, eps_dB):
+    def forward(ctx, cores, wcores, B, template, wtemplate, eps_dB):
         f = _with_cores(template, cores)
-        dt = _TORCH[f.dtype]
-        w = kernel_sinc(f.d, float(B), eps_w, dt, f.device)
-        x = full(f)
-        y = toeplitz_apply(w, x)
-        ctx.save_for_backward(cores, B)
-        ctx.template, ctx.w, ctx.eps_dB = template, w, eps_dB
+        w = _with_cores(wtemplate, wcores)
+        y = full(conv(f, [w], [f.d]))
+        ctx.save_for_backward(cores, wcores, B)
+        ctx.template, ctx.wtemplate, ctx.eps_dB = template, wtemplate, eps_dB
         return y
 
     @staticmethod
     def backward(ctx, gy):
-        cores, B = ctx.saved_tensors
+        cores, wcores, B = ctx.saved_tensors
         f = _with_cores(ctx.template, cores)
-        need_b = ctx.needs_input_grad[1]
+        w = _with_cores(ctx.wtemplate, wcores)
+        need_w, need_b = ctx.needs_input_grad[1], ctx.needs_input_grad[2]
         wdb = kernel_sinc_dB(f.d, float(B), ctx.eps_dB, _TORCH[f.dtype], f.device) if need_b \
             else None
-        gr, gB = conv_full_backward(f, ctx.w, wdb, gy.to(_TORCH[f.dtype]))
+        gr, gw, gB = conv_full_backward(f, w, wdb, gy.contiguous().to(_TORCH[f.dtype]),
+                                        grad_w=need_w)
         gcores = gr.cores if ctx.needs_input_grad[0] else None
+        gwcores = gw.cores if need_w else None
         gb = gB.to(device=B.device, dtype=B.dtype).reshape(B.shape) if need_b else None
-        return gcores, gb, None, None, None
+        return gcores, gwcores, gb, None, None, None
 
 
 def conv_full(f: QTT, B: torch.Tensor, cores: torch.Tensor | None = None, eps_w: float = 1e-12,
-              eps_dB: float = 1e-12) -> torch.Tensor:
-    """Differentiable ``T(w(B)) full(F)``; ``cores`` defaults to ``f.cores``."""
-    return ConvFull.apply(f.cores if cores is None else cores, B, f, eps_w, eps_dB)
+              eps_dB: float = 1e-12, w: QTT | None = None,
+              wcores: torch.Tensor | None = None) -> torch.Tensor:
+    """Differentiable ``full(conv(F, W))``; ``cores`` defaults to ``f.cores``; the
+    kernel ``w`` defaults to ``kernel_sinc(d, B, eps_w)`` (compacted to its
+    ranks) and ``wcores`` to ``w.cores``."""
+    if w is None:
+        w = kernel_sinc(f.d, float(B), eps_w, _TORCH[f.dtype], f.device).compact()
+    return ConvFull.apply(f.cores if cores is None else cores,
+                          w.cores if wcores is None else wcores, B, f, w, eps_dB)
 
 
 # ------------------------------------------------------------------ batched

@@ -134,9 +134,10 @@ def _declare(L):
     L.qtt_full_adjoint.argtypes = [_TP, _VP, _TP, _VP, ctypes.c_size_t, _VP]
     L.qtt_query_conv_full_backward.restype = ctypes.c_int
     L.qtt_query_conv_full_backward.argtypes = [ctypes.c_int, _I32P, _I32P, _I32P, ctypes.c_int,
-                                               _SZP]
+                                               ctypes.c_int, _SZP]
     L.qtt_conv_full_backward.restype = ctypes.c_int
-    L.qtt_conv_full_backward.argtypes = [_TP, _TP, _TP, _VP, _TP, _VP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_conv_full_backward.argtypes = [_TP, _TP, _TP, _VP, _TP, _TP, _VP, _VP, ctypes.c_size_t,
+                                         _VP]
     L.qtt_batch_create.restype = ctypes.c_int
     L.qtt_batch_create.argtypes = [ctypes.c_int, _I32P, ctypes.POINTER(ctypes.c_double),
                                    ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double,

@@ -536,12 +536,13 @@ struct BwdPlan {
   void* toep_ws;
   void* full_ws;
   void* adj_ws;
+  void* wg_ws;
   double* dot_part;
   size_t total;
 };
 
 static void plan_backward(int d, const int32_t* f_cap, const int32_t* w_cap,
-                          const int32_t* wdb_cap, int dtype, void* ws, BwdPlan* p) {
+                          const int32_t* wdb_cap, int want_w, int dtype, void* ws, BwdPlan* p) {
   Arena ar(ws);
   const size_t es = elem_size(dtype);
   const size_t N = (size_t)1 << d;
@@ -559,26 +560,28 @@ static void plan_backward(int d, const int32_t* f_cap, const int32_t* w_cap,
   plan_full(d, f_cap, dtype, nullptr, &fb, bufs);
   p->full_ws = ar.take<char>(fb > 0 ? fb : 1);
   p->adj_ws = ar.take<char>(full_adjoint_ws_bytes(d, f_cap, dtype));
+  p->wg_ws = want_w ? ar.take<char>(wgrad_ws_bytes(d, w_cap)) : nullptr;
   p->dot_part = ar.take<double>(kDotPartials + 8);
   p->total = ar.size();
 }
 
 int qtt_query_conv_full_backward(int d, const int32_t* f_cap, const int32_t* w_cap,
-                                 const int32_t* wdb_cap, int dtype, size_t* ws_bytes) {
+                                 const int32_t* wdb_cap, int want_w, int dtype,
+                                 size_t* ws_bytes) {
   if (d < 1 || d > kMaxModes || !f_cap || !dtype_ok(dtype) || !wcap_ok(w_cap, d + 1) ||
-      (wdb_cap && !wcap_ok(wdb_cap, d + 1)))
+      (wdb_cap && !wcap_ok(wdb_cap, d + 1)) || (want_w != 0 && want_w != 1))
     return QTT_EINVAL;
   for (int k = 0; k <= d; ++k)
     if (f_cap[k] < 1 || f_cap[k] > QTT_MAX_RANK) return QTT_EINVAL;
   BwdPlan p;
-  plan_backward(d, f_cap, w_cap, wdb_cap, dtype, nullptr, &p);
+  plan_backward(d, f_cap, w_cap, wdb_cap, want_w, dtype, nullptr, &p);
   if (ws_bytes) *ws_bytes = p.total;
   return QTT_OK;
 }
 
 int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_tensor* w_dB,
-                           const void* grad_y, qtt_tensor* grad_f, double* grad_B, void* ws,
-                           size_t ws_bytes, void* stream) {
+                           const void* grad_y, qtt_tensor* grad_f, qtt_tensor* grad_w,
+                           double* grad_B, void* ws, size_t ws_bytes, void* stream) {
   if (check_tensor_in(f) || f->d > kMaxModes || check_tensor_in(w) || !grad_y ||
       grad_tensor_ok(f, grad_f))
     return QTT_EINVAL;
@@ -588,18 +591,26 @@ int qtt_conv_full_backward(const qtt_tensor* f, const qtt_tensor* w, const qtt_t
                !wcap_ok(w_dB->cap, d + 1)))
     return QTT_EINVAL;
   if ((w_dB == nullptr) != (grad_B == nullptr)) return QTT_EINVAL;
+  if (grad_w && grad_tensor_ok(w, grad_w)) return QTT_EINVAL;
   for (int k = 0; k <= d; ++k)
     if (f->cap[k] > QTT_MAX_RANK) return QTT_ENOTSUP;
+  const int want_w = grad_w ? 1 : 0;
   BwdPlan p;
-  plan_backward(d, f->cap, w->cap, w_dB ? w_dB->cap : nullptr, f->dtype, nullptr, &p);
+  plan_backward(d, f->cap, w->cap, w_dB ? w_dB->cap : nullptr, want_w, f->dtype, nullptr, &p);
   if (!ws || ws_bytes < p.total) return ws ? QTT_ENOSPC : QTT_EINVAL;
-  plan_backward(d, f->cap, w->cap, w_dB ? w_dB->cap : nullptr, f->dtype, ws, &p);
+  plan_backward(d, f->cap, w->cap, w_dB ? w_dB->cap : nullptr, want_w, f->dtype, ws, &p);
   hipStream_t st = static_cast<hipStream_t>(stream);
   TensorDev fd = make_dev(f), wd = make_dev(w), gd = make_dev(grad_f);
   // the core chain is recomputed here rather than kept from the forward
   int rc = run_full(fd, f->dtype, p.ffull, p.full_ws, st);
   if (rc) return rc;
-  rc = run_toeplitz(wd, f->dtype, grad_y, p.gf, 1, p.toep_ws, st);
+  if (grad_w) {
+    // T(w)^T grad_y and the kernel-core gradients in one pair of sweeps
+    TensorDev gwd = make_dev(grad_w);
+    rc = run_conv_backward_w(wd, f->dtype, p.ffull, grad_y, p.gf, gwd, p.wg_ws, st);
+  } else {
+    rc = run_toeplitz(wd, f->dtype, grad_y, p.gf, 1, p.toep_ws, st);
+  }
   if (rc) return rc;
   rc = run_full_adjoint(fd, f->dtype, p.gf, gd, p.adj_ws, st);
   if (rc) return rc;

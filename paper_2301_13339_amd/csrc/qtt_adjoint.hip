@@ -15,6 +15,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "qtt_internal.hpp"
 #include "qtt_sinc.hpp"
 
@@ -212,6 +214,349 @@ int run_toeplitz(const TensorDev& w, int dtype, const void* x, void* y, int tran
                            static_cast<double*>(ws), s);
 }
 
+__global__ void k_copy_ranks(const int32_t* src, int32_t* dst, int n) {
+  const int i = threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+// ================================================ kernel-core gradients
+// For L with upstream gradient g = dL/dy of y = T(w) f, the gradient with
+// respect to core k of the generator (k = 1..d+1) contracts the transposed
+// product's state before mode k with the forward product's state after it:
+//   P_{k-1}[(a,c)][pos]: g pushed through modes 1..k-1 of T^T (bits < k of
+//     pos are i, bits >= k are j; P_0 = g with a = 0 and carry-in 1);
+//   Q_k[(b,c')][pos]: f pushed through modes k+1..d of T from the top, the
+//     top bit u_{d+1} = c_d contracted with W_{d+1} (bits <= k of pos are i,
+//     bits > k are j; Q_d = W_{d+1}[b, c', 0] f);
+//   dL/dW_k[a, u, b] = sum_{pos'} sum_{o, n, c} P_{k-1}[(a,c)][pos'|o]
+//       Q_k[(b,c')][pos'|n] [u = (o + 1 - n + c) mod 2, c' = (o + 1 - n + c) div 2]
+// where pos' runs over the positions without bit k, o = j_k and n = i_k.
+// Core d+1 (u = c_d): dL/dW_{d+1}[a, c, 0] = sum_pos P_d[(a,c)][pos] f[pos].
+// The Q states are computed top-down and kept (the P states run bottom-up);
+// every sum is FP64 in a fixed order.
+
+// Q_d = W_{d+1}[b, c', 0] f, b2 = 2 b + c' < 2 rho_d
+template <typename T>
+__global__ void __launch_bounds__(256) k_toep_qfirst(const T* f, double* out, const T* wc,
+                                                     const int32_t* wr, ToepMeta tm, int d,
+                                                     long long N) {
+  const long long pos = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (pos >= N) return;
+  const int nb = 2 * wr[d];
+  const T* Wl = wc + tm.woff[d];  // (rho_d, 2, 1): entry b2 = 2 b + c'
+  const double fv = (double)f[pos];
+  for (int b2 = 0; b2 < nb; ++b2) out[(long long)b2 * N + pos] = (double)Wl[b2] * fv;
+}
+
+// Q_{k-1} from Q_k: Q_{k-1}[(a,c)][..o..] = sum_{n,b} W_k[a, u, b] Q_k[(b,c')][..n..]
+// (bit k-1 of pos, 0-based: o on the output, n on the input)
+template <typename T>
+__global__ void __launch_bounds__(256) k_toep_qstep(const double* in, double* out, const T* wc,
+                                                    const int32_t* wr, ToepMeta tm, int k,
+                                                    long long N) {
+  const long long half = N >> 1;
+  const long long q = (long long)blockIdx.x * 64 + (threadIdx.x & 63);
+  const int w = threadIdx.x >> 6;
+  const int rin = wr[k];       // bond of Q_k (right rank of W_k)
+  const int rout = wr[k - 1];  // bond of Q_{k-1} (left rank of W_k)
+  const int b0 = (blockIdx.y * 4 + w) * kToepNB;  // first output bond of this thread
+  if (b0 >= 2 * rout || q >= half) return;
+  const T* Wk = wc + tm.woff[k - 1];  // W_k[a][u][b] at (a*2 + u)*rin + b
+  const int bit = k - 1;
+  const long long p0 = ins_bit(q, bit, 0), p1 = ins_bit(q, bit, 1);
+  double acc[kToepNB][2];
+#pragma unroll
+  for (int t = 0; t < kToepNB; ++t) acc[t][0] = acc[t][1] = 0.0;
+  for (int b = 0; b < rin; ++b) {
+#pragma unroll
+    for (int c1 = 0; c1 < 2; ++c1) {
+      const long long row = (long long)(2 * b + c1) * N;
+      const double x0 = in[row + p0], x1 = in[row + p1];
+#pragma unroll
+      for (int t = 0; t < kToepNB; ++t) {
+        const int bo = b0 + t;
+        if (bo < 2 * rout) {
+          const int a = bo >> 1, c = bo & 1;
+#pragma unroll
+          for (int o = 0; o < 2; ++o) {
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+              const int v = o + (1 - n) + c;
+              if ((v >> 1) == c1) {
+                const double wv = (double)Wk[(a * 2 + (v & 1)) * rin + b];
+                acc[t][o] = fma(wv, n ? x1 : x0, acc[t][o]);
+              }
+            }
+          }
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < kToepNB; ++t) {
+    const int bo = b0 + t;
+    if (bo < 2 * rout) {
+      out[(long long)bo * N + p0] = acc[t][0];
+      out[(long long)bo * N + p1] = acc[t][1];
+    }
+  }
+}
+
+constexpr int kWgChunk = 16;   // positions pos' staged per pass
+constexpr int kWgBlocks = 256; // partial sums per core
+
+// partial dL/dW_k (k = 1..d) over chunks of pos': part[blk][(a*2 + u)*rb + b].
+// P is the transposed product's state P_{k-1} (FP64), or g itself when FIRST.
+template <typename T, int FIRST>
+__global__ void __launch_bounds__(256) k_wgrad_part(const void* pin, const double* qin,
+                                                    const int32_t* wr, int k, long long N,
+                                                    double* part, int max_out) {
+  extern __shared__ double wg_lds[];
+  const int ra = FIRST ? 1 : wr[k - 1], rb = wr[k];
+  const int npa = 2 * ra, npb = 2 * rb;
+  // Ps[(2a + c)][o][cc], Qs[(2b + c')][n][cc]
+  double* Ps = wg_lds;
+  double* Qs = wg_lds + (size_t)npa * 2 * kWgChunk;
+  const int nout = ra * 2 * rb;
+  const int tid = threadIdx.x;
+  const long long half = N >> 1;
+  const int bit = k - 1;
+  double acc[32];
+#pragma unroll
+  for (int t = 0; t < 32; ++t) acc[t] = 0.0;
+  const long long nch = (half + kWgChunk - 1) / kWgChunk;
+  for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
+    const long long base = ch * kWgChunk;
+    for (int e = tid; e < npa * 2 * kWgChunk; e += 256) {
+      const int row = e / (2 * kWgChunk), rem = e - row * (2 * kWgChunk);
+      const int o = rem / kWgChunk, cc = rem - o * kWgChunk;
+      const long long qq = base + cc;
+      double v = 0.0;
+      if (qq < half) {
+        const long long p = ins_bit(qq, bit, o);
+        if (FIRST)
+          v = (row == 1) ? (double)static_cast<const T*>(pin)[p] : 0.0;  // a = 0, carry-in 1
+        else
+          v = static_cast<const double*>(pin)[(long long)row * N + p];
+      }
+      Ps[e] = v;
+    }
+    for (int e = tid; e < npb * 2 * kWgChunk; e += 256) {
+      const int row = e / (2 * kWgChunk), rem = e - row * (2 * kWgChunk);
+      const int n = rem / kWgChunk, cc = rem - n * kWgChunk;
+      const long long qq = base + cc;
+      Qs[e] = qq < half ? qin[(long long)row * N + ins_bit(qq, bit, n)] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 32; ++t) {
+      const int oi = tid + 256 * t;
+      if (oi < nout) {
+        const int a = oi / (2 * rb), rem = oi - a * 2 * rb;
+        const int u = rem / rb, b = rem - u * rb;
+        double s = acc[t];
+#pragma unroll
+        for (int o = 0; o < 2; ++o) {
+#pragma unroll
+          for (int c = 0; c < 2; ++c) {
+            const int n = (o + 1 + c + u) & 1;
+            const int c1 = (o + 1 - n + c) >> 1;
+            const double* pp = Ps + ((2 * a + c) * 2 + o) * kWgChunk;
+            const double* qp = Qs + ((2 * b + c1) * 2 + n) * kWgChunk;
+#pragma unroll
+            for (int cc = 0; cc < kWgChunk; ++cc) s = fma(pp[cc], qp[cc], s);
+          }
+        }
+        acc[t] = s;
+      }
+    }
+    __syncthreads();
+  }
+  double* P = part + (size_t)blockIdx.x * max_out;
+#pragma unroll
+  for (int t = 0; t < 32; ++t) {
+    const int oi = tid + 256 * t;
+    if (oi < nout) P[oi] = acc[t];
+  }
+}
+
+// partial dL/dW_{d+1}[a, c, 0] = sum_pos P_d[(a,c)][pos] f[pos]: block (x, b2)
+template <typename T>
+__global__ void __launch_bounds__(256) k_wgrad_top_part(const double* pd, const T* f,
+                                                        long long N, double* part,
+                                                        int max_out) {
+  __shared__ double red[256];
+  const int b2 = blockIdx.y;
+  double s = 0.0;
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < N;
+       e += (long long)gridDim.x * 256)
+    s = fma(pd[(long long)b2 * N + e], (double)f[e], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(size_t)blockIdx.x * max_out + b2] = red[0];
+}
+
+template <typename T>
+__global__ void k_wgcore_sum(const double* part, int nblk, int max_out, const int32_t* ranks,
+                             int k, T* gcores, long long off) {
+  const int nout = 2 * ranks[k - 1] * ranks[k];
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= nout) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[(size_t)b * max_out + o];
+  gcores[off + o] = (T)s;
+}
+
+struct WgPlan {
+  long long qoff[QTT_MAXD + 2];  // element offset of the stored Q_k (k = 1..d)
+  size_t q_elems;
+  size_t p_elems;                // one P buffer: 2 max_{k=1..d} cap_k N
+  int max_out;                   // max_k 2 cap_{k-1} cap_k over the d+1 cores
+};
+
+static void wg_plan(int d, const int32_t* wcap, WgPlan* p) {
+  const long long N = 1LL << d;
+  long long o = 0;
+  int rmax = 1, mo = 1;
+  for (int k = 1; k <= d; ++k) {
+    p->qoff[k] = o;
+    o += 2LL * wcap[k] * N;
+    if (wcap[k] > rmax) rmax = wcap[k];
+  }
+  for (int k = 1; k <= d + 1; ++k) {
+    const int oc = 2 * wcap[k - 1] * wcap[k];
+    if (oc > mo) mo = oc;
+  }
+  p->q_elems = (size_t)o;
+  p->p_elems = (size_t)(2 * rmax) * (size_t)N;
+  p->max_out = mo;
+}
+
+size_t wgrad_ws_bytes(int d, const int32_t* w_cap) {
+  WgPlan p;
+  wg_plan(d, w_cap, &p);
+  Arena ar(nullptr);
+  ar.take<double>(p.q_elems);
+  ar.take<double>(p.p_elems);
+  ar.take<double>(p.p_elems);
+  ar.take<double>((size_t)kWgBlocks * p.max_out);
+  return ar.size();
+}
+
+static size_t wgrad_lds(int ra_cap, int rb_cap) {
+  return (size_t)(2 * ra_cap + 2 * rb_cap) * 2 * kWgChunk * sizeof(double);
+}
+
+template <typename T>
+static int conv_backward_w_t(const TensorDev& w, const T* f, const T* gy, T* gf,
+                             const TensorDev& gw, void* ws, hipStream_t s) {
+  const int d = w.d - 1;
+  const long long N = 1LL << d, half = N >> 1;
+  WgPlan p;
+  wg_plan(d, w.cap, &p);
+  Arena ar(ws);
+  double* qs = ar.take<double>(p.q_elems);
+  double* pb[2] = {ar.take<double>(p.p_elems), ar.take<double>(p.p_elems)};
+  double* part = ar.take<double>((size_t)kWgBlocks * p.max_out);
+  ToepMeta tm;
+  for (int k = 0; k <= w.d; ++k) tm.woff[k] = w.off[k];
+  const T* wc = static_cast<const T*>(w.cores);
+  T* G = static_cast<T*>(gw.cores);
+  for (int k = 1; k <= d; ++k) {
+    const size_t lds = wgrad_lds(k == 1 ? 1 : w.cap[k - 1], w.cap[k]);
+    if (lds > 64 * 1024) return QTT_ENOTSUP;
+  }
+  static std::once_flag attr_once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(attr_once, [] {
+    const int mx = (int)wgrad_lds(kMaxRank, kMaxRank);
+    hipError_t e1 = hipFuncSetAttribute((const void*)k_wgrad_part<T, 0>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    hipError_t e2 = hipFuncSetAttribute((const void*)k_wgrad_part<T, 1>,
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    attr_err = e1 != hipSuccess ? e1 : e2;
+  });
+  QTT_HIP_CHECK(attr_err);
+  ProbeScope _ps(QTT_K_ADJOINT, s);
+  k_copy_ranks<<<1, 64, 0, s>>>(w.ranks, gw.ranks, d + 2);
+  QTT_LAUNCH_CHECK();
+  // Q_d .. Q_1, top-down, all kept
+  k_toep_qfirst<T><<<(unsigned)((N + 255) / 256), 256, 0, s>>>(f, qs + p.qoff[d], wc, w.ranks, tm,
+                                                               d, N);
+  QTT_LAUNCH_CHECK();
+  for (int k = d; k >= 2; --k) {
+    const int gyd = (2 * w.cap[k - 1] + 4 * kToepNB - 1) / (4 * kToepNB);
+    dim3 grid((unsigned)((half + 63) / 64), (unsigned)gyd);
+    k_toep_qstep<T><<<grid, 256, 0, s>>>(qs + p.qoff[k], qs + p.qoff[k - 1], wc, w.ranks, tm, k,
+                                        N);
+    QTT_LAUNCH_CHECK();
+  }
+  // P sweep bottom-up with the gradient of core k from P_{k-1} and Q_k
+  const long long nch = (half + kWgChunk - 1) / kWgChunk;
+  const int nblk = (int)(nch < kWgBlocks ? nch : kWgBlocks);
+  const double* pcur = nullptr;
+  for (int k = 1; k <= d; ++k) {
+    const size_t lds = wgrad_lds(k == 1 ? 1 : w.cap[k - 1], w.cap[k]);
+    if (k == 1)
+      k_wgrad_part<T, 1><<<nblk, 256, lds, s>>>(gy, qs + p.qoff[k], w.ranks, k, N, part,
+                                                p.max_out);
+    else
+      k_wgrad_part<T, 0><<<nblk, 256, lds, s>>>(pcur, qs + p.qoff[k], w.ranks, k, N, part,
+                                                p.max_out);
+    QTT_LAUNCH_CHECK();
+    const int nout = 2 * w.cap[k - 1] * w.cap[k];
+    k_wgcore_sum<T><<<(nout + 255) / 256, 256, 0, s>>>(part, nblk, p.max_out, w.ranks, k, G,
+                                                       gw.off[k - 1]);
+    QTT_LAUNCH_CHECK();
+    // P_k (k = d included: the top core's gradient needs P_d)
+    double* nxt = pb[(k - 1) & 1];
+    const int gyd = (2 * w.cap[k] + 4 * kToepNB - 1) / (4 * kToepNB);
+    dim3 grid((unsigned)((half + 63) / 64), (unsigned)gyd);
+    if (k == 1)
+      k_toep_step<T, T, 1, 1><<<grid, 256, 0, s>>>(gy, nxt, wc, w.ranks, tm, k, N);
+    else
+      k_toep_step<T, double, 1, 0><<<grid, 256, 0, s>>>(pcur, nxt, wc, w.ranks, tm, k, N);
+    QTT_LAUNCH_CHECK();
+    if (k == d) {
+      // the transposed product itself from P_{d-1} (or g when d = 1)
+      const unsigned gl = (unsigned)((half + 255) / 256);
+      if (d == 1)
+        k_toep_last<T, T, 1, 1><<<gl, 256, 0, s>>>(gy, gf, wc, w.ranks, tm, d, N);
+      else
+        k_toep_last<T, double, 1, 0><<<gl, 256, 0, s>>>(pcur, gf, wc, w.ranks, tm, d, N);
+      QTT_LAUNCH_CHECK();
+    }
+    pcur = nxt;
+  }
+  // core d+1 from P_d and f
+  {
+    const int nb2 = 2 * w.cap[d];
+    long long nbx = (N + 255) / 256;
+    if (nbx > kWgBlocks) nbx = kWgBlocks;
+    dim3 grid((unsigned)nbx, (unsigned)nb2);
+    k_wgrad_top_part<T><<<grid, 256, 0, s>>>(pcur, f, N, part, p.max_out);
+    QTT_LAUNCH_CHECK();
+    k_wgcore_sum<T><<<(nb2 + 255) / 256, 256, 0, s>>>(part, (int)nbx, p.max_out, w.ranks, d + 1,
+                                                      G, gw.off[d]);
+    QTT_LAUNCH_CHECK();
+  }
+  return QTT_OK;
+}
+
+int run_conv_backward_w(const TensorDev& w, int dtype, const void* f, const void* gy, void* gf,
+                        const TensorDev& gw, void* ws, hipStream_t s) {
+  if (dtype == QTT_F64)
+    return conv_backward_w_t<double>(w, static_cast<const double*>(f),
+                                     static_cast<const double*>(gy), static_cast<double*>(gf), gw,
+                                     ws, s);
+  return conv_backward_w_t<float>(w, static_cast<const float*>(f), static_cast<const float*>(gy),
+                                  static_cast<float*>(gf), gw, ws, s);
+}
+
 // ========================================================== full adjoint
 // For G = <g, full(F)>:  dG/dF_k[a, i, b] = sum_rest H_{k-1}[a][i + 2 rest] Rf_k[b][rest]
 // with the right interfaces Rf_k (r_k x 2^(d-k)),
@@ -344,11 +689,6 @@ __global__ void k_gcore_sum(const double* part, int nblk, int max_out, const int
   double s = 0.0;
   for (int b = 0; b < nblk; ++b) s += part[(size_t)b * max_out + o];
   gcores[off + o] = (T)s;
-}
-
-__global__ void k_copy_ranks(const int32_t* src, int32_t* dst, int n) {
-  const int i = threadIdx.x;
-  if (i < n) dst[i] = src[i];
 }
 
 size_t full_adjoint_ws_bytes(int d, const int* cap, int dtype) {

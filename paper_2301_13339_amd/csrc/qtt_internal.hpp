@@ -211,6 +211,9 @@ size_t toeplitz_ws_elems(int d, const int32_t* w_cap);
 int run_toeplitz(const TensorDev& w, int dtype, const void* x, void* y, int trans, void* ws,
                  hipStream_t s);
 size_t full_adjoint_ws_bytes(int d, const int* cap, int dtype);
+size_t wgrad_ws_bytes(int d, const int32_t* w_cap);
+int run_conv_backward_w(const TensorDev& w, int dtype, const void* f, const void* gy, void* gf,
+                        const TensorDev& gw, void* ws, hipStream_t s);
 int run_full_adjoint(const TensorDev& f, int dtype, const void* g, const TensorDev& gr, void* ws,
                      hipStream_t s);
 constexpr int kDotPartials = 512;

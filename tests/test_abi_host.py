@@ -210,15 +210,29 @@ def test_adjoint_entry_points_validate():
     g = L.qtt_tensor()
     ctypes.pointer(g)[0] = f
     assert so.qtt_conv_full_backward(ctypes.byref(f), ctypes.byref(w), ctypes.byref(w), fake,
-                                     ctypes.byref(g), None, fake, 1 << 30, None) == -1
+                                     ctypes.byref(g), None, None, fake, 1 << 30, None) == -1
     g.cap[2] = 3
     assert so.qtt_conv_full_backward(ctypes.byref(f), ctypes.byref(w), None, fake,
-                                     ctypes.byref(g), None, fake, 1 << 30, None) == -1
+                                     ctypes.byref(g), None, None, fake, 1 << 30, None) == -1
     g.cap[2] = 4
     assert so.qtt_conv_full_backward(ctypes.byref(f), ctypes.byref(w), None, fake,
-                                     ctypes.byref(g), None, fake, 16, None) == -2
+                                     ctypes.byref(g), None, None, fake, 16, None) == -2
+    # the kernel-core gradient tensor must mirror w
+    gw = L.qtt_tensor()
+    ctypes.pointer(gw)[0] = w
+    gw.cap[1] = w.cap[1] + 1
+    assert so.qtt_conv_full_backward(ctypes.byref(f), ctypes.byref(w), None, fake,
+                                     ctypes.byref(g), ctypes.byref(gw), None, fake, 1 << 30,
+                                     None) == -1
     fcap = (ctypes.c_int32 * 5)(1, 2, 4, 2, 1)
-    assert so.qtt_query_conv_full_backward(4, fcap, wcap, None, L.QTT_F64,
+    assert so.qtt_query_conv_full_backward(4, fcap, wcap, None, 0, L.QTT_F64,
                                            ctypes.byref(ws)) == 0
     assert ws.value > 0
+    ws_w = ctypes.c_size_t()
+    assert so.qtt_query_conv_full_backward(4, fcap, wcap, None, 1, L.QTT_F64,
+                                           ctypes.byref(ws_w)) == 0
+    # the stored forward states: 2 w_cap[k] 2^d doubles for k = 1..d
+    assert ws_w.value - ws.value >= sum(2 * wcap[k] * 16 * 8 for k in range(1, 5))
+    assert so.qtt_query_conv_full_backward(4, fcap, wcap, None, 2, L.QTT_F64,
+                                           ctypes.byref(ws_w)) == -1
     assert so.qtt_query_full_adjoint(4, fcap, L.QTT_F64, ctypes.byref(ws)) == 0

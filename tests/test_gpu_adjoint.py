@@ -105,11 +105,17 @@ def test_conv_full_backward_matches_oracle(q, d, dt):
     r = y.double() - torch.tensor(target, device=DEV)
     assert float((r * r).sum()) == pytest.approx(L, rel=1e-10 if dt == torch.float64 else 1e-5)
     gy = (2.0 * r).to(dt)
-    gr, gb = q.conv_full_backward(f, w, wdb, gy)
+    gr, gw_t, gb = q.conv_full_backward(f, w, wdb, gy, grad_w=True)
     tol = 1e-10 if dt == torch.float64 else 2e-5
     got = gr.core_list()
     for k in range(d):
         assert rel(got[k], gc[k]) <= tol, k
+    # kernel cores: the adjoint of Full of W applied to dL/dw
+    gW = grads.full_adjoint(wc, gw)
+    assert gw_t.ranks_host() == w.ranks_host()
+    gotw = gw_t.core_list()
+    for k in range(d + 1):
+        assert rel(gotw[k], gW[k]) <= tol, ("W", k)
     # dL/dB = <gy, T(dw) f>: compare on the scale of its terms
     scale = float(np.linalg.norm(2.0 * (conv.toeplitz_apply_fft(tt.tt_full(cores), wv) - target))
                   * np.linalg.norm(conv.toeplitz_apply_fft(tt.tt_full(cores), bv)))
@@ -123,12 +129,24 @@ def test_autograd_function_matches_oracle(q):
     cores, target, B = _problem(d)
     L, gc, gB, gw, gf = grads.grads(cores, B, target)
     f = q.from_cores(cores, torch.float64, DEV)
+    w = q.kernel_sinc(d, B, 1e-9, torch.float64, DEV).compact()
     cparam = f.cores.clone().requires_grad_(True)
+    wparam = w.cores.clone().requires_grad_(True)
     Bt = torch.tensor([B], dtype=torch.float64, requires_grad=True)
-    y = q.conv_full(f, Bt, cparam, eps_w=1e-9, eps_dB=1e-9)
+    y = q.conv_full(f, Bt, cparam, eps_dB=1e-9, w=w, wcores=wparam)
     loss = ((y - torch.tensor(target, device=DEV)) ** 2).sum()
     loss.backward()
     assert float(loss.detach()) == pytest.approx(L, rel=1e-7)
+    # kernel cores against the oracle on the GPU's own generator QTT
+    Wh = w.core_list()
+    _, _, _, gw, _ = grads.grads(cores, B, target, w=tt.tt_full(Wh))
+    gW = grads.full_adjoint(Wh, gw)
+    wflat = wparam.grad.detach().cpu().numpy()
+    off = 0
+    for k in range(d + 1):
+        n = Wh[k].size
+        assert rel(wflat[off:off + n].reshape(Wh[k].shape), gW[k]) <= 1e-10, ("W", k)
+        off += n
     # the gradient array has f's capacity layout; compare core by core
     flat = cparam.grad.detach().cpu().numpy()
     off = 0
@@ -161,13 +179,21 @@ def test_backward_at_d20_fp64(q):
     wdb = q.from_cores(bc, dt, DEV)
     y = q.toeplitz_apply(w, q.full(f))
     gy = 2.0 * (y - torch.tensor(target, device=DEV))
-    gr, gb = q.conv_full_backward(f, w, wdb, gy)
+    gr, gw_t, gb = q.conv_full_backward(f, w, wdb, gy, grad_w=True)
     tol = 1e-10
     got = gr.core_list()
     fgf = float(np.dot(gf, tt.tt_full(cores)))
     for k in range(d):
         assert rel(got[k], gc[k]) <= tol, k
         assert float(np.sum(got[k] * cores[k])) == pytest.approx(fgf, rel=10 * tol)
+    # kernel cores, and <dL/dW_k, W_k> = <dL/dw, w> for every k (Full of W is
+    # linear in each core)
+    gW = grads.full_adjoint(wc, gw)
+    gotw = gw_t.core_list()
+    wgw = float(np.dot(gw, wv))
+    for k in range(d + 1):
+        assert rel(gotw[k], gW[k]) <= tol, ("W", k)
+        assert float(np.sum(gotw[k] * wc[k])) == pytest.approx(wgw, rel=10 * tol)
     scale = float(np.linalg.norm(2.0 * (conv.toeplitz_apply_fft(tt.tt_full(cores), wv) - target))
                   * np.linalg.norm(conv.toeplitz_apply_fft(tt.tt_full(cores), bv)))
     assert abs(float(gb.cpu()) - gB) <= tol * scale
@@ -201,11 +227,69 @@ def test_backward_at_d20_fp32(q):
     f = q.from_cores(cores, dt, DEV)
     w = q.from_cores(wc, dt, DEV)
     wdb = q.from_cores(bc, dt, DEV)
-    gr, gb = q.conv_full_backward(f, w, wdb, torch.tensor(gy, dtype=dt, device=DEV))
+    gr, gw_t, gb = q.conv_full_backward(f, w, wdb, torch.tensor(gy, dtype=dt, device=DEV),
+                                        grad_w=True)
     got = gr.core_list()
     for k in range(d):
         assert rel(got[k], gc[k]) <= 1e-5, k
+    # dL/dw_u = sum_j gy_j f_{j+N-u} (the oracle's correlation), then Full's adjoint
+    m = 4 * fv.size
+    cc = np.fft.irfft(np.fft.rfft(gy, m) * np.conj(np.fft.rfft(fv, m)), m)
+    gwv = np.zeros(2 * fv.size)
+    u = np.arange(1, 2 * fv.size)
+    gwv[1:] = cc[(u - fv.size) % m]
+    gW = grads.full_adjoint(wc, gwv)
+    gotw = gw_t.core_list()
+    for k in range(d + 1):
+        assert rel(gotw[k], gW[k]) <= 1e-5, ("W", k)
     assert abs(float(gb.cpu()) - gB) <= 1e-5 * float(np.linalg.norm(gy) * np.linalg.norm(zb))
+
+
+def test_differentiation_workload_d22_fp32(q):
+    """The differentiation workload at full size: d = 22, FP32 storage, signal
+    cores from the decomposition of the noisy Gaussian-bump signal (eps 1e-4,
+    ranks <= 32), kernel QTT at B = 220 (compacted to its ranks), target the
+    convolution of the clean signal at B = 200.  Loss, every signal-core and
+    kernel-core gradient and dL/dB through the autograd Function, against the
+    FP64 oracle gradients of the same loss on the same (FP32-valued) cores,
+    within max(2 eps, 1e-5)."""
+    d, B0, Bt_, eps, R = 22, 220.0, 200.0, 1e-4, 32
+    print("case: differentiation d=22 f32", flush=True)
+    dt = torch.float32
+    noisy, clean = G.diff_workload(d)
+    target = conv.toeplitz_apply_fft(clean, conv.toeplitz_generator(d, Bt_))
+    f = q.decompose(torch.tensor(noisy, dtype=dt, device=DEV), eps, R)
+    w = q.kernel_sinc(d, B0, eps / 10, dt, DEV).compact()
+    cparam = f.cores.clone().requires_grad_(True)
+    wparam = w.cores.clone().requires_grad_(True)
+    Bt = torch.tensor([B0], dtype=torch.float64, requires_grad=True)
+    y = q.conv_full(f, Bt, cparam, eps_dB=1e-7, w=w, wcores=wparam)
+    loss = ((y.double() - torch.tensor(target, device=DEV)) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    Fh, Wh = f.core_list(), w.core_list()
+    Dh = q.kernel_sinc_dB(d, B0, 1e-7, dt, DEV).core_list()
+    L, gc, gB, gw, _ = grads.grads(Fh, B0, target, w=tt.tt_full(Wh), dw=tt.tt_full(Dh))
+    gW = grads.full_adjoint(Wh, gw)
+    tol = max(2 * eps, 1e-5)
+    eL = abs(float(loss.detach()) - L) / L
+    cflat = cparam.grad.detach().cpu().double().numpy()
+    wflat = wparam.grad.detach().cpu().double().numpy()
+    ef, off = [], 0
+    for k in range(d):
+        n = Fh[k].size
+        ef.append(rel(cflat[off:off + n].reshape(Fh[k].shape), gc[k]))
+        off += f.cap[k] * 2 * f.cap[k + 1]
+    ew, off = [], 0
+    for k in range(d + 1):
+        n = Wh[k].size
+        ew.append(rel(wflat[off:off + n].reshape(Wh[k].shape), gW[k]))
+        off += n
+    eB = abs(float(Bt.grad) - gB) / abs(gB)
+    print(f"d=22 f32: loss {eL:.2e}, signal cores max {max(ef):.2e}, kernel cores max "
+          f"{max(ew):.2e}, dL/dB {eB:.2e} (W ranks {w.ranks_host()})", flush=True)
+    assert eL <= tol
+    assert max(ef) <= tol and max(ew) <= tol and eB <= tol
 
 
 def test_backward_rejects_bad_arguments(q):
