@@ -22,6 +22,13 @@ def q():
     return qq
 
 
+# a rank decision of the sketch is declared a tie when the oracle's tail sum
+# lies within this relative distance of the threshold: with the operands
+# rounded alike on both sides, the GPU's FP32 accumulation of the sketch
+# perturbs sigma(B)^2 by about 1e-6 relative
+TIE = 1e-4
+
+
 def rel(a, b):
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -47,18 +54,29 @@ def test_sketch_equals_exact_when_ell_covers(q, method, dt):
 @pytest.mark.parametrize("method,ell", [("sketch_f32", 12), ("sketch_f32", 24),
                                         ("sketch_bf16", 12), ("sketch_bf16", 24)])
 def test_sketch_matches_oracle_sketch(q, method, ell, dt):
-    """ell below some unfoldings' row count: the same Omega on both sides."""
+    """ell below some unfoldings' row count: the same Omega on both sides.  The
+    rank decisions are compared with the oracle sketch whose operands are
+    rounded as the GPU's are (bfloat16 for the BF16 method), so both sides
+    take them on the same values; the output is compared with the FP64-operand
+    oracle sketch within the method's tolerance."""
     d, B, eps, seed = 14, 400.0, 1e-4, 11
     noisy, _ = G.scatterers_1d(d, seed=3)
     ref = P.pipeline_1d(noisy, B, eps, 32, sketch_ell=ell, sketch_seed=seed)
+    same = ref if method == "sketch_f32" else P.pipeline_1d(
+        noisy, B, eps, 32, sketch_ell=ell, sketch_seed=seed, sketch_operands="bf16")
     x = torch.tensor(noisy, dtype=dt, device=DEV)
     out, st = q.pipeline(x, B, eps, 32, round_method=method, sketch_ell=ell, sketch_seed=seed)
     got = out.cpu().numpy()
     err = rel(got, ref["out"])
     tol = max(2 * eps, 1e-5) if method == "sketch_f32" else max(2 * eps, 3e-3)
     gr = st["z"].ranks_host()
-    print(f"{method} ell={ell} {dt}: rel {err:.3e} ranks {gr} vs {ref['Z_ranks']}", flush=True)
-    assert all(abs(a - b) <= 1 for a, b in zip(gr, ref["Z_ranks"]))
+    margin = same["Z_info"]["margin"]
+    print(f"{method} ell={ell} {dt}: rel {err:.3e} ranks {gr} vs {same['Z_ranks']} "
+          f"(decision margin {margin:.2e})", flush=True)
+    if margin >= TIE:
+        assert gr == same["Z_ranks"]
+    else:  # a declared tie: the sums' rounding may settle it either way
+        assert all(abs(a - b) <= 1 for a, b in zip(gr, same["Z_ranks"]))
     if max(ref["Z_ranks"]) < ell:
         assert err <= tol
     else:
@@ -102,19 +120,69 @@ def test_sketch_image_bf16(q):
     assert rel(out.cpu().numpy(), ref["out"]) <= max(2 * eps, 3e-3)
 
 
-def test_image_4096_precision_form(q):
-    """The 4096 x 4096 image at full size (FP32 data, BF16-operand sketch,
-    ell = 64): against the FP64 exact pipeline on the same input (the oracle's
-    exact-SVD sweep at this size is beyond a test's time), within
-    max(2 eps, 3e-3); ranks within the capacities; no status bits."""
-    noisy, _ = G.sar_image_2d(12, 12, seed=3)
-    print("image 4096", flush=True)
-    eps, R = 1e-3, 32
-    x32 = torch.tensor(noisy, dtype=torch.float32, device=DEV)
+@pytest.fixture(scope="module")
+def image4096():
+    noisy, clean = G.sar_image_2d(12, 12, seed=3)
+    return noisy, clean
+
+
+def test_image_4096_exact_forms_against_the_oracle(q, image4096):
+    """The 4096 x 4096 image at full size (24 binary modes, separable sinc
+    Bx = By = 1000, eps = 1e-3, R = 32) through the exact pipeline: FP64 within
+    1e-10 of the oracle's FP64 pipeline with the same ranks; FP32 data within
+    max(2 eps, 1e-5); the BF16-operand sketch rounding (ell = 64) within
+    max(2 eps, 3e-3) of the same oracle."""
+    noisy, _ = image4096
+    eps, R, B = 1e-3, 32, 1000.0
+    print("case: image 4096 exact forms", flush=True)
+    ref = P.pipeline_2d(noisy, B, B, eps, R)
     x64 = torch.tensor(noisy, dtype=torch.float64, device=DEV)
-    out, st = q.pipeline(x32, (1000.0, 1000.0), eps, R, shape2d=noisy.shape,
-                         round_method="sketch_bf16", sketch_ell=64, sketch_seed=1)
-    ref, st64 = q.pipeline(x64, (1000.0, 1000.0), eps, R, shape2d=noisy.shape)
-    assert rel(out.cpu().numpy(), ref.cpu().numpy()) <= max(2 * eps, 3e-3)
-    assert st["z"].status_host() == 0 and st["f"].status_host() == 0
-    assert max(st["f"].ranks_host()) <= R
+    out, st = q.pipeline(x64, (B, B), eps, R, shape2d=noisy.shape)
+    e64 = rel(out.cpu().numpy(), ref["out"])
+    print(f"FP64: rel {e64:.3e} Z ranks {st['z'].ranks_host()} oracle {ref['Z_ranks']} margins "
+          f"{ref['F_info']['margin']:.2e} {ref['Z_info']['margin']:.2e}", flush=True)
+    assert st["f"].ranks_host() == ref["F_ranks"]
+    assert st["z"].ranks_host() == ref["Z_ranks"]
+    assert e64 <= 1e-10
+    del out, x64
+    x32 = torch.tensor(noisy, dtype=torch.float32, device=DEV)
+    o32, st32 = q.pipeline(x32, (B, B), eps, R, shape2d=noisy.shape)
+    e32 = rel(o32.cpu().numpy(), ref["out"])
+    ob, stb = q.pipeline(x32, (B, B), eps, R, shape2d=noisy.shape, round_method="sketch_bf16",
+                         sketch_ell=64, sketch_seed=1)
+    eb = rel(ob.cpu().numpy(), ref["out"])
+    print(f"FP32 exact: rel {e32:.3e}; BF16 sketch: rel {eb:.3e} ranks {stb['z'].ranks_host()}",
+          flush=True)
+    assert e32 <= max(2 * eps, 1e-5)
+    assert eb <= max(2 * eps, 3e-3)
+    for s_ in (st32, stb):
+        assert s_["z"].status_host() == 0 and s_["f"].status_host() == 0
+
+
+
+
+def test_image_4096_sketch_against_the_oracle_sketch(q, image4096):
+    """The BF16 and FP32 sketch roundings of the full-size image against the
+    oracle's sketch sweep with the same Omega (Philox, seed 1, ell = 64; the
+    oracle takes the exact step where ell covers the rows): ranks exact unless
+    a decision is a declared tie, outputs within the method's tolerance."""
+    noisy, _ = image4096
+    eps, R, B, ell = 1e-3, 32, 1000.0, 64
+    print("case: image 4096 sketch vs oracle sketch", flush=True)
+    x32 = torch.tensor(noisy, dtype=torch.float32, device=DEV)
+    noisy32 = noisy.astype(np.float32).astype(np.float64)
+    for method, ops in (("sketch_f32", "f64"), ("sketch_bf16", "bf16")):
+        ref = P.pipeline_2d(noisy32, B, B, eps, R, sketch_ell=ell, sketch_seed=1,
+                            sketch_operands=ops)
+        margin = ref["Z_info"]["margin"]
+        out, st = q.pipeline(x32, (B, B), eps, R, shape2d=noisy.shape, round_method=method,
+                             sketch_ell=ell, sketch_seed=1)
+        err = rel(out.cpu().numpy(), ref["out"])
+        gr = st["z"].ranks_host()
+        print(f"{method}: rel {err:.3e} ranks {gr} oracle {ref['Z_ranks']} margin {margin:.2e} "
+              f"sketched steps {ref['Z_info']['sketched']}", flush=True)
+        if margin >= TIE:
+            assert gr == ref["Z_ranks"]
+        else:
+            assert all(abs(a - b) <= 1 for a, b in zip(gr, ref["Z_ranks"]))
+        assert err <= (max(2 * eps, 1e-5) if method == "sketch_f32" else max(2 * eps, 3e-3))
