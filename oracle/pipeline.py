@@ -39,6 +39,8 @@ def relative_error(a, ref) -> float:
 
 
 def _toeplitz(f, w, fft):
+    if fft == "blocked":
+        return conv.toeplitz_apply_blocked(f, w)
     return conv.toeplitz_apply_fft(f, w) if fft else conv.toeplitz_apply(f, w)
 
 
@@ -48,7 +50,8 @@ def pipeline_1d(x, B: float, eps: float, max_rank: int = 0, eps_w: float | None 
     """Run the composed pipeline on a 1-D signal of length ``2**d``.
 
     ``fft`` selects the DFT route for the exact convolution (default: on for
-    ``d > 14``); both routes compute the same sum.  ``sketch_ell > 0`` takes
+    ``d > 14``); ``fft="blocked"`` takes the direct sum as block-Toeplitz
+    matrix products; all routes compute the same sum.  ``sketch_ell > 0`` takes
     the rounding's truncated SVDs from Algorithms 4 and 5 (``ell`` columns,
     ``sketch_seed``, sketch operands ``sketch_operands``: ``"f64"`` or
     ``"bf16"``); ``delta > 0`` adds the drop-off cut (exact rounding only).  Returns a dict with the cores, the intermediate full arrays,

@@ -146,3 +146,20 @@ def test_table_7_1_rejects_variance_reading():
     e_std = pipeline.relative_error(conv.conv_same_fft(xn, g, dx), conv.conv_same_fft(f, g, dx))
     e_var = pipeline.relative_error(conv.conv_same_fft(f + noise, g, dx), conv.conv_same_fft(f, g, dx))
     assert e_var > 4 * e_std
+
+
+@pytest.mark.parametrize("d,block", [(4, 1), (6, 8), (9, 64), (10, 1024)])
+def test_blocked_toeplitz_equals_direct_sum(d, block):
+    """The block-Toeplitz organisation of (2.2) gives the direct sum."""
+    rng = np.random.default_rng(d)
+    n = 1 << d
+    f = rng.standard_normal(n)
+    w = rng.standard_normal(2 * n)
+    want = conv.toeplitz_apply(f, w)
+    got = conv.toeplitz_apply_blocked(f, w, block=block)
+    assert np.allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    # the block diagonals partition the sum
+    nb = n // min(block, n)
+    half = conv.toeplitz_apply_blocked(f, w, block=block, diagonals=range(-(nb - 1), 1))
+    rest = conv.toeplitz_apply_blocked(f, w, block=block, diagonals=range(1, nb))
+    assert np.allclose(half + rest, want, rtol=0, atol=1e-12 * np.abs(want).max())
