@@ -176,14 +176,19 @@ int qtt_decompose_dropoff(const void* x, int d, int dtype, double eps, double de
  * C-contiguous (r_{k-1}, M, r_k) with the actual ranks, at element offset
  * sum_{j<k} cap[j-1] M cap[j].  The rank of step k is Algorithm 1's rule at
  * eps (tau = eps ||x|| / sqrt(K-1)) on the step's singular values, then the
- * cap.  Errors: QTT_EINVAL for invalid arguments or capacities other than the
+ * cap.  status (device int32, may be NULL) receives, OR-ed in,
+ * QTT_STATUS_RANKCAP when an eps-rank exceeded a cap that the library's
+ * capacity (128 / M, at most QTT_MAX_RANK) set below the caller's max_rank
+ * (or with max_rank = 0), and QTT_STATUS_NONFINITE for non-finite input.
+ * Errors: QTT_EINVAL for invalid arguments or capacities other than the
  * query's, QTT_ENOSPC for a short workspace.
  */
 int qtt_query_decompose_modes(int K, int M, int max_rank, int method, int oversample,
                               int32_t* cap, size_t* ws_bytes, size_t* core_elems);
 int qtt_decompose_modes(const double* x, int K, int M, double eps, int max_rank, int method,
                         int oversample, uint64_t seed, const int32_t* cap, int32_t* ranks,
-                        double* cores, void* ws, size_t ws_bytes, void* stream);
+                        double* cores, int32_t* status, void* ws, size_t ws_bytes,
+                        void* stream);
 
 /*
  * QTT of the Toeplitz generator of the normalised sinc kernel.

@@ -225,7 +225,8 @@ def decompose(x: torch.Tensor, eps: float, max_rank: int = 0, return_sv: bool = 
 
 class TTModes:
     """A TT with K modes of size M (FP64): flat ``cores`` at the query's
-    capacity offsets, ``ranks`` (K+1 int32) on the device."""
+    capacity offsets, ``ranks`` (K+1 int32) and the ``status`` word on the
+    device."""
 
     def __init__(self, K: int, M: int, cap, device):
         self.K, self.M, self.cap = K, M, list(cap)
@@ -233,9 +234,13 @@ class TTModes:
         n = sum(self.cap[k] * M * self.cap[k + 1] for k in range(K))
         self.cores = torch.zeros(n, dtype=torch.float64, device=self.device)
         self.ranks = torch.zeros(K + 1, dtype=torch.int32, device=self.device)
+        self.status = torch.zeros(1, dtype=torch.int32, device=self.device)
 
     def ranks_host(self):
         return [int(v) for v in self.ranks.cpu()]
+
+    def status_host(self) -> int:
+        return int(self.status.cpu()[0])
 
     def core_list(self):
         """Cores as CPU float64 arrays of shape ``(r_{k-1}, M, r_k)``."""
@@ -273,6 +278,7 @@ def decompose_modes(x: torch.Tensor, M: int, eps: float, max_rank: int = 0, meth
                                      int(max_rank), meth, int(oversample), ctypes.c_uint64(seed),
                                      cap, ctypes.c_void_p(out.ranks.data_ptr()),
                                      ctypes.c_void_p(out.cores.data_ptr()),
+                                     ctypes.c_void_p(out.status.data_ptr()),
                                      ctypes.c_void_p(w.data_ptr()), ws.value, _stream(x.device)),
            "qtt_decompose_modes")
     out._keep = [w, x]

@@ -92,7 +92,7 @@ def _declare(L):
     L.qtt_decompose_modes.restype = ctypes.c_int
     L.qtt_decompose_modes.argtypes = [_VP, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                       ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64,
-                                      _I32P, _VP, _VP, _VP, ctypes.c_size_t, _VP]
+                                      _I32P, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP]
     L.qtt_kernel_sinc.restype = ctypes.c_int
     L.qtt_kernel_sinc.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                   _TP, _VP, ctypes.c_size_t, _VP]

@@ -233,7 +233,8 @@ int qtt_query_decompose_modes(int K, int M, int max_rank, int method, int oversa
 
 int qtt_decompose_modes(const double* x, int K, int M, double eps, int max_rank, int method,
                         int oversample, uint64_t seed, const int32_t* cap, int32_t* ranks,
-                        double* cores, void* ws, size_t ws_bytes, void* stream) {
+                        double* cores, int32_t* status, void* ws, size_t ws_bytes,
+                        void* stream) {
   if (!x || !cap || !ranks || !cores || !ws || !(eps >= 0.0) || !isfinite(eps) ||
       !modes_args_ok(K, M, max_rank, method, oversample))
     return QTT_EINVAL;
@@ -244,8 +245,12 @@ int qtt_decompose_modes(const double* x, int K, int M, double eps, int max_rank,
     if (cap[k] < need[k]) return QTT_ENOSPC;
   for (int k = 0; k <= K; ++k)
     if (cap[k] != need[k]) return QTT_EINVAL;  // the core offsets follow the query's capacities
-  return run_decompose_modes(x, K, M, eps, method, oversample, seed, cap, ranks, cores, ws,
-                             static_cast<hipStream_t>(stream));
+  // the library's capacity (QTT_MAX_RANK, lowered to 128 / M) decides when it
+  // is below the caller's cap; only then is a binding cap reported
+  const int lib_cap = (128 / M) < QTT_MAX_RANK ? 128 / M : QTT_MAX_RANK;
+  const int lib_capped = (max_rank == 0 || max_rank > lib_cap) ? 1 : 0;
+  return run_decompose_modes(x, K, M, eps, method, oversample, seed, cap, ranks, cores, status,
+                             lib_capped, ws, static_cast<hipStream_t>(stream));
 }
 
 int qtt_kernel_sinc(int d, double B, double eps_w, int dtype, qtt_tensor* w_out, void* ws,

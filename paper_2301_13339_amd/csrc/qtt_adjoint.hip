@@ -474,11 +474,8 @@ static int conv_backward_w_t(const TensorDev& w, const T* f, const T* gy, T* gf,
   static hipError_t attr_err = hipSuccess;
   std::call_once(attr_once, [] {
     const int mx = (int)wgrad_lds(kMaxRank, kMaxRank);
-    hipError_t e1 = hipFuncSetAttribute((const void*)k_wgrad_part<T, 0>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    hipError_t e2 = hipFuncSetAttribute((const void*)k_wgrad_part<T, 1>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-    attr_err = e1 != hipSuccess ? e1 : e2;
+    set_lds_limit((const void*)k_wgrad_part<T, 0>, mx, &attr_err);
+    set_lds_limit((const void*)k_wgrad_part<T, 1>, mx, &attr_err);
   });
   QTT_HIP_CHECK(attr_err);
   ProbeScope _ps(QTT_K_ADJOINT, s);

@@ -20,6 +20,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <vector>
@@ -598,13 +599,12 @@ static int batch_stages(qtt_batch* p, const T* x, T* out, char* ws, hipStream_t 
     QTT_LAUNCH_CHECK();
     const size_t lds_max =
         sizeof(double) * (2 * kToepMaxBond * (1 << kToepMaxCB) + kToepMaxBond * kToepMaxBond);
-    static bool attr = false;
-    if (!attr) {
-      QTT_HIP_CHECK(hipFuncSetAttribute((const void*)k_batch_toep<T>,
-                                        hipFuncAttributeMaxDynamicSharedMemorySize,
-                                        (int)lds_max));
-      attr = true;
-    }
+    static std::once_flag attr_once;
+    static hipError_t attr_err = hipSuccess;
+    std::call_once(attr_once, [lds_max] {
+      set_lds_limit((const void*)k_batch_toep<T>, (int)lds_max, &attr_err);
+    });
+    QTT_HIP_CHECK(attr_err);
     for (size_t qi = 0; qi < p->toep_wg0.size(); ++qi) {
       if (p->toep_total[qi] > 0xFFFFFFFFLL / 64) return QTT_ENOTSUP;  // grid limit
       const long long* twg = reinterpret_cast<const long long*>(ws + p->o_twg) + (size_t)n * qi;

@@ -26,6 +26,8 @@
 // Ranks stay in device memory; no kernel needs a host synchronisation.
 #include <math.h>
 
+#include <mutex>
+
 #include "qtt_eig.hpp"
 #include "qtt_internal.hpp"
 #include "qtt_sinc.hpp"
@@ -867,7 +869,9 @@ __global__ void k_flag_status(const int32_t* iflags, int32_t* status) {
 // 1..6, projections + Grams of the remainders, eig steps, the tail.  Each
 // workgroup owns a slice of global scratch (scal, U, A/V for orders > 64 and
 // two remainder buffers of nmax elements).
-__device__ __forceinline__ void wg_sync_global() {
+// workgroup barrier that also orders this workgroup's global-memory writes
+// (its scratch slice) before the reads that follow it; not a grid barrier
+__device__ __forceinline__ void wg_barrier_with_global_fence() {
   __threadfence();
   __syncthreads();
 }
@@ -891,7 +895,7 @@ __device__ __noinline__ void batch_project(const T* Ain, double B, int nk, long 
         if (i < M && j < M) Ly.A[i * Ly.lda + j] = acc[a][c];
       }
   }
-  wg_sync_global();
+  wg_barrier_with_global_fence();
 }
 
 template <typename T, int GEN>
@@ -981,7 +985,7 @@ __device__ __noinline__ void batch_line(const BatchTask& tk, const T* x, T* core
     __syncthreads();
   }
   level_steps<T>(smem, L, D, tk.eps, meta, cores, scal, umat, so);
-  wg_sync_global();
+  wg_barrier_with_global_fence();
   int tail_k = L + 1;
   while (tail_k < D && !((1LL << (D - tail_k)) * 2LL * meta.caps[tail_k - 1] <= kTailElems))
     ++tail_k;
@@ -1001,7 +1005,7 @@ __device__ __noinline__ void batch_line(const BatchTask& tk, const T* x, T* core
     const EigLayout Ly = eig_layout(smem, M, gA, gV);
     const int r = eig_step_solve_at<T>(Ly, M, k, scal[1], meta.caps[k], cores, meta.offs[k - 1],
                                        umat, so);
-    wg_sync_global();
+    wg_barrier_with_global_fence();
     const int M2 = 2 * r;
     const EigLayout Ly2 = eig_layout(smem, M2, gA, gV);
     batch_project_any<T, 0>(2 * meta.caps[k], xb[cur], tk.B, tk.nk, 1LL << (D - k), M, r, umat,
@@ -1011,7 +1015,7 @@ __device__ __noinline__ void batch_line(const BatchTask& tk, const T* x, T* core
   }
   tail_steps<T, 0>(smem, xb[cur], tk.B, tk.nk, k, D, tk.eps, meta, cores, scal, 0, so, flag);
   if (GEN == 1) {
-    wg_sync_global();
+    wg_barrier_with_global_fence();
     const int rp = so.ranks[D - 1];
     const double sc = scal[2] != 0.0 ? 1.0 / scal[2] : 1.0;
     T* last = cores + meta.offs[D - 1];
@@ -1037,7 +1041,7 @@ __global__ void __launch_bounds__(kEigThreads) k_batch_decompose(
     if (t >= ntasks) break;  // every wave leaves on the same value
     const BatchTask tk = tasks[t];
     batch_line<T, GEN>(tk, x, cores, ranks, status, lds(smem), s_meta, my, xb0, xb1);
-    wg_sync_global();
+    wg_barrier_with_global_fence();
   }
 }
 
@@ -1116,45 +1120,28 @@ int plan_decompose(int D, int rcap, int dtype, void* ws, DecompPlan* p) {
 }
 
 template <typename T, int GEN>
-static void set_attrs() {
-  hipFuncSetAttribute((const void*)k_level_eig<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_level_eig());
-  hipFuncSetAttribute((const void*)k_eig_step<T>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_eig_step());
-  hipFuncSetAttribute((const void*)k_tail<T, 0>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_tail());
-  hipFuncSetAttribute((const void*)k_tail<T, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_tail());
-  hipFuncSetAttribute((const void*)k_tail<T, GEN>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                      (int)lds_tail());
-  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 1>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 2>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 4>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_gram<T, GEN, 8>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 1>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 2>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 4>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_gram<T, 0, 8>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_mfma<T, GEN, 16>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_mfma<T, GEN, 32>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_mfma<T, GEN, 64>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_mfma<T, 0, 16>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_mfma<T, 0, 32>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  hipFuncSetAttribute((const void*)k_project_mfma<T, 0, 64>,
-                      hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+static hipError_t set_attrs() {
+  hipError_t e = hipSuccess;
+  set_lds_limit((const void*)k_level_eig<T>, (int)lds_level_eig(), &e);
+  set_lds_limit((const void*)k_eig_step<T>, (int)lds_eig_step(), &e);
+  set_lds_limit((const void*)k_tail<T, 0>, (int)lds_tail(), &e);
+  set_lds_limit((const void*)k_tail<T, 1>, (int)lds_tail(), &e);
+  set_lds_limit((const void*)k_tail<T, GEN>, (int)lds_tail(), &e);
+  set_lds_limit((const void*)k_project_gram<T, GEN, 1>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_gram<T, GEN, 2>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_gram<T, GEN, 4>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_gram<T, GEN, 8>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_gram<T, 0, 1>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_gram<T, 0, 2>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_gram<T, 0, 4>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_gram<T, 0, 8>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_mfma<T, GEN, 16>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_mfma<T, GEN, 32>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_mfma<T, GEN, 64>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_mfma<T, 0, 16>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_mfma<T, 0, 32>, 160 * 1024, &e);
+  set_lds_limit((const void*)k_project_mfma<T, 0, 64>, 160 * 1024, &e);
+  return e;
 }
 
 template <typename T, int GEN>
@@ -1211,11 +1198,11 @@ static int launch_project(const T* Ain, const Source& src, long long rowsA, int 
 template <typename T, int GEN>
 static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
                            const TensorDev& out, double* sv, hipStream_t stream, double delta) {
-  static bool attrs = false;
-  if (!attrs) {
-    set_attrs<T, GEN>();
-    attrs = true;
-  }
+  // kernel attributes once per instantiation, safe under concurrent first calls
+  static std::once_flag attr_once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(attr_once, [] { attr_err = set_attrs<T, GEN>(); });
+  QTT_HIP_CHECK(attr_err);
   const int D = P.D;
   const T* x = static_cast<const T*>(src.x);
   T* cores = static_cast<T*>(out.cores);
@@ -1376,13 +1363,12 @@ template <typename T, int GEN>
 static int batch_decompose_t(const T* x, const BatchTask* tasks, int ntasks, int32_t* counter,
                              T* cores, int32_t* ranks, int32_t* status, char* wscr,
                              long long wstride, long long nmax, int nwg, hipStream_t s) {
-  static bool attrs = false;
-  if (!attrs) {
-    QTT_HIP_CHECK(hipFuncSetAttribute((const void*)k_batch_decompose<T, GEN>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)batch_decompose_lds()));
-    attrs = true;
-  }
+  static std::once_flag attr_once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(attr_once, [] {
+    set_lds_limit((const void*)k_batch_decompose<T, GEN>, (int)batch_decompose_lds(), &attr_err);
+  });
+  QTT_HIP_CHECK(attr_err);
   ProbeScope _ps(QTT_K_BATCH, s);
   k_batch_decompose<T, GEN><<<nwg, kEigThreads, batch_decompose_lds(), s>>>(
       x, tasks, ntasks, counter, cores, ranks, status, wscr, wstride, nmax);

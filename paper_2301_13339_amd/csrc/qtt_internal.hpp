@@ -111,6 +111,11 @@ void set_hip_error(hipError_t e);
       return QTT_EHIP;                          \
     }                                           \
   } while (0)
+// Raise the dynamic-LDS limit of a kernel; keeps the first failure in *err.
+inline void set_lds_limit(const void* fn, int bytes, hipError_t* err) {
+  const hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e != hipSuccess && *err == hipSuccess) *err = e;
+}
 #define QTT_LAUNCH_CHECK()                      \
   do {                                          \
     hipError_t _e = hipGetLastError();          \
@@ -192,7 +197,7 @@ int modes_caps(int K, int M, int max_rank, int32_t* cap);
 size_t modes_ws_bytes(int K, int M, int method, int oversample);
 int run_decompose_modes(const double* x, int K, int M, double eps, int method, int oversample,
                         uint64_t seed, const int32_t* cap, int32_t* ranks, double* cores,
-                        void* ws, hipStream_t s);
+                        int32_t* status, int lib_capped, void* ws, hipStream_t s);
 
 // --------------------------------------------------------------- other ops
 int plan_full(int d, const int32_t* cap, int dtype, void* ws, size_t* ws_bytes, void** bufs);

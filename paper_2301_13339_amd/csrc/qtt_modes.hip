@@ -18,6 +18,8 @@
 // Every streaming pass multiplies on the FP64 matrix cores.
 #include <math.h>
 
+#include <mutex>
+
 #include "qtt_eig.hpp"
 #include "qtt_internal.hpp"
 #include "qtt_philox.hpp"
@@ -439,14 +441,16 @@ __device__ __forceinline__ MEig meig_layout(double* smem, int E, double* gV) {
   return L;
 }
 
+// status (may be null) receives QTT_STATUS_NONFINITE for a non-finite matrix
+// and, when lib_capped, QTT_STATUS_RANKCAP for an eps-rank above cap
 template <class MP, class MPV>
 __device__ int meig_solve(const MEig& L, MP A, MPV V, int E, double tau2, int cap, int32_t* rk,
-                          int k) {
+                          int k, int32_t* status = nullptr, int lib_capped = 0) {
   StepOut so;
   so.ranks = rk;
-  so.status = nullptr;
+  so.status = status;
   so.sv = nullptr;
-  so.lib_capped = 0;
+  so.lib_capped = lib_capped;
   so.dbg = nullptr;
   so.delta2 = 0.0;
   return solve_and_truncate<kEigThreads, true>(A, V, E, L.lda, lds(L.sx), lds(L.iscr), lds(L.lam),
@@ -466,7 +470,8 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
                                                       const int32_t* iq, double* scal,
                                                       int cap_k, double* cores, long long off_k,
                                                       double* umat, double* gV,
-                                                      int set_tau, double eps, int K, int ncol) {
+                                                      int set_tau, double eps, int K, int ncol,
+                                                      int32_t* status, int lib_capped) {
   extern __shared__ double smem[];
   const int tid = threadIdx.x;
   const int rp = ranks[k - 1];
@@ -558,9 +563,9 @@ __global__ void __launch_bounds__(kEigThreads) k_meig(const double* G, int M, in
   __syncthreads();
   int r;
   if (E <= kEigLds)
-    r = meig_solve(L, lds(L.A), lds(L.V), E, scal[1], cap_k, ranks, k);
+    r = meig_solve(L, lds(L.A), lds(L.V), E, scal[1], cap_k, ranks, k, status, lib_capped);
   else
-    r = meig_solve(L, lds(L.A), L.V, E, scal[1], cap_k, ranks, k);
+    r = meig_solve(L, lds(L.A), L.V, E, scal[1], cap_k, ranks, k, status, lib_capped);
   // U (m x r) and core k
   const bool basis = use_q == 1 || tall;
   for (int e = tid; e < m * r; e += kEigThreads) {
@@ -780,11 +785,9 @@ static int as_elems(int tc, int mcap) {
 constexpr int kMaxStreamLds = 150 * 1024;
 
 template <int MB>
-static void set_stream_attrs() {
-  (void)hipFuncSetAttribute((const void*)k_mgram<MB>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            kMaxStreamLds);
-  (void)hipFuncSetAttribute((const void*)k_msketch<MB>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, kMaxStreamLds);
+static void set_stream_attrs(hipError_t* e) {
+  set_lds_limit((const void*)k_mgram<MB>, kMaxStreamLds, e);
+  set_lds_limit((const void*)k_msketch<MB>, kMaxStreamLds, e);
 }
 
 template <int MB>
@@ -859,27 +862,25 @@ static int stream_pass(int which, const double* R, int M, int mcap, int32_t* ran
 
 int run_decompose_modes(const double* x, int K, int M, double eps, int method, int oversample,
                         uint64_t seed, const int32_t* cap, int32_t* ranks, double* cores,
-                        void* ws, hipStream_t s) {
-  static bool attrs = false;
-  if (!attrs) {
-    (void)hipFuncSetAttribute((const void*)k_meig, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds_meig());
-    (void)hipFuncSetAttribute((const void*)k_mqr, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        (int)lds_mqr());
-    (void)hipFuncSetAttribute((const void*)k_mproj, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kMaxStreamLds);
-    (void)hipFuncSetAttribute((const void*)k_mbgram, hipFuncAttributeMaxDynamicSharedMemorySize,
-                              kMaxStreamLds);
-    set_stream_attrs<1>();
-    set_stream_attrs<2>();
-    set_stream_attrs<3>();
-    set_stream_attrs<4>();
-    set_stream_attrs<5>();
-    set_stream_attrs<6>();
-    set_stream_attrs<7>();
-    set_stream_attrs<8>();
-    attrs = true;
-  }
+                        int32_t* status, int lib_capped, void* ws, hipStream_t s) {
+  static std::once_flag attr_once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(attr_once, [] {
+    hipError_t* e = &attr_err;
+    set_lds_limit((const void*)k_meig, (int)lds_meig(), e);
+    set_lds_limit((const void*)k_mqr, (int)lds_mqr(), e);
+    set_lds_limit((const void*)k_mproj, kMaxStreamLds, e);
+    set_lds_limit((const void*)k_mbgram, kMaxStreamLds, e);
+    set_stream_attrs<1>(e);
+    set_stream_attrs<2>(e);
+    set_stream_attrs<3>(e);
+    set_stream_attrs<4>(e);
+    set_stream_attrs<5>(e);
+    set_stream_attrs<6>(e);
+    set_stream_attrs<7>(e);
+    set_stream_attrs<8>(e);
+  });
+  QTT_HIP_CHECK(attr_err);
   const ModesPlan P = modes_plan(ws, K, M);
   long long N = 1;
   for (int k = 0; k < K; ++k) N *= M;
@@ -912,7 +913,7 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
     if (short_unf) {
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(nullptr, M, ranks, k, 2, cur, P.iq, P.scal,
                                                 cap[k], cores, off, P.umat, P.gV, 0, eps, K,
-                                                (int)n);
+                                                (int)n, status, lib_capped);
       QTT_LAUNCH_CHECK();
     } else if (!rs) {
       rc = stream_pass(0, cur, M, mcap, ranks, k, n, &np, &ps, 0, seed, P, s);
@@ -921,7 +922,8 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gram, M, ranks, k, 0, nullptr, P.iq, P.scal,
                                                 cap[k], cores, off, P.umat, P.gV,
-                                                (k == 1 && first_exact) ? 1 : 0, eps, K, 0);
+                                                (k == 1 && first_exact) ? 1 : 0, eps, K, 0,
+                                                status, lib_capped);
       QTT_LAUNCH_CHECK();
     } else {
       rc = stream_pass(1, cur, M, mcap, ranks, k, n, &np, &ps, ell, seed, P, s);
@@ -936,7 +938,7 @@ int run_decompose_modes(const double* x, int K, int M, double eps, int method, i
       if (rc) return rc;
       k_meig<<<1, kEigThreads, lds_meig(), s>>>(P.gramb, M, ranks, k, 1, P.q, P.iq, P.scal,
                                                 cap[k], cores, off, P.umat, P.gV, 0, eps,
-                                                K, 0);
+                                                K, 0, status, lib_capped);
       QTT_LAUNCH_CHECK();
     }
     {

@@ -16,6 +16,8 @@
 // Box-Muller transform of its first two words.
 #include <math.h>
 
+#include <mutex>
+
 #include "qtt_eig.hpp"
 #include "qtt_internal.hpp"
 #include "qtt_philox.hpp"
@@ -407,13 +409,12 @@ static int sketch_t(const T* y, int D, double eps, const int* cap, int ell, uint
                     const TensorDev& out, void* ws, hipStream_t s) {
   SketchPlan p;
   sketch_plan(D, sizeof(T) == 8 ? QTT_F64 : QTT_F32, ell, ws, &p);
-  static bool attr = false;
-  if (!attr) {
-    QTT_HIP_CHECK(hipFuncSetAttribute((const void*)k_sketch_step<T>,
-                                      hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)sketch_step_lds()));
-    attr = true;
-  }
+  static std::once_flag attr_once;
+  static hipError_t attr_err = hipSuccess;
+  std::call_once(attr_once, [] {
+    set_lds_limit((const void*)k_sketch_step<T>, (int)sketch_step_lds(), &attr_err);
+  });
+  QTT_HIP_CHECK(attr_err);
   StepOut so;
   so.ranks = out.ranks;
   so.status = out.status;

@@ -119,15 +119,15 @@ def test_modes_query_and_validation():
     fake = ctypes.c_void_p(0x1000)
     so.qtt_query_decompose_modes(3, 4, 0, 0, 0, cap, ctypes.byref(ws), None)
     # null input, NaN tolerance, short workspace, capacities other than the query's
-    assert so.qtt_decompose_modes(None, 3, 4, 1e-3, 0, 0, 0, 0, cap, fake, fake, fake,
+    assert so.qtt_decompose_modes(None, 3, 4, 1e-3, 0, 0, 0, 0, cap, fake, fake, None, fake,
                                   ws.value, None) == -1
-    assert so.qtt_decompose_modes(fake, 3, 4, float("nan"), 0, 0, 0, 0, cap, fake, fake, fake,
+    assert so.qtt_decompose_modes(fake, 3, 4, float("nan"), 0, 0, 0, 0, cap, fake, fake, None, fake,
                                   ws.value, None) == -1
-    assert so.qtt_decompose_modes(fake, 3, 4, 1e-3, 0, 0, 0, 0, cap, fake, fake, fake,
+    assert so.qtt_decompose_modes(fake, 3, 4, 1e-3, 0, 0, 0, 0, cap, fake, fake, None, fake,
                                   ws.value - 1, None) == -2
     cap2 = (ctypes.c_int32 * 4)(*cap[:4])
     cap2[1] = cap[1] + 1
-    assert so.qtt_decompose_modes(fake, 3, 4, 1e-3, 0, 0, 0, 0, cap2, fake, fake, fake,
+    assert so.qtt_decompose_modes(fake, 3, 4, 1e-3, 0, 0, 0, 0, cap2, fake, fake, None, fake,
                                   ws.value, None) == -1
 
 

@@ -6,7 +6,7 @@ steps) or 1e-9 (randomised steps), left-orthonormal cores."""
 import numpy as np
 import pytest
 
-from oracle import ttm
+from oracle import tt, ttm
 
 pytestmark = pytest.mark.gpu
 
@@ -57,6 +57,13 @@ def test_modes_match_oracle(name, K, M, data, eps, R, method, p):
     t = q.decompose_modes(torch.tensor(x, device="cuda"), M, eps, R, method=method,
                           oversample=p, seed=17)
     assert t.ranks_host() == info["ranks"]
+    # the library's capacity (128 // M) reports when it, not the caller's cap,
+    # truncated an eps-rank
+    lib_cap = min(q.QTT_MAX_RANK, 128 // M)
+    lib_decides = R == 0 or R > lib_cap
+    capped = any(tt.truncation_rank(sv, info["tau"], 0) > min(M ** k, M ** (K - k), reff)
+                 for k, sv in enumerate(info["sv"], start=1))
+    assert bool(t.status_host() & 2) == (lib_decides and capped), (t.status_host(), capped)
     cores = t.core_list()
     full = ttm.tt_full_modes(cores)
     want = ttm.tt_full_modes(ref)
@@ -105,3 +112,16 @@ def test_modes_unaligned_input_same_result(method, p):
     assert a.ranks_host() == b.ranks_host()
     for ca, cb in zip(a.core_list(), b.core_list()):
         assert np.array_equal(ca, cb)
+
+
+def test_modes_rank_capacity_flag_at_the_largest_mode():
+    """M = 64 at eps = 0: the unfoldings keep at most 128 // 64 = 2 rows' worth of
+    rank, far below the exact ranks, so the capacity flag is set; with the
+    caller's own cap at 2 the cap is the caller's and no flag is set."""
+    x = np.random.default_rng(64).random(64 ** 3)
+    t = q.decompose_modes(torch.tensor(x, device="cuda"), 64, 0.0)
+    assert t.ranks_host() == [1, 2, 2, 1]
+    assert t.status_host() == 2
+    t2 = q.decompose_modes(torch.tensor(x, device="cuda"), 64, 0.0, 2)
+    assert t2.ranks_host() == [1, 2, 2, 1]
+    assert t2.status_host() == 0
