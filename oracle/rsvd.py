@@ -85,20 +85,29 @@ def round_bf16(x) -> np.ndarray:
     return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
+def round_operands(operands: str):
+    """The rounding applied to the operands of the sketch products."""
+    if operands == "f64":
+        return lambda v: np.asarray(v, dtype=np.float64)
+    if operands == "f32":
+        return lambda v: np.asarray(v, dtype=np.float64).astype(np.float32).astype(np.float64)
+    if operands == "bf16":
+        return round_bf16
+    raise ValueError(operands)
+
+
 def sketch_product(A, ell: int, step: int, seed: int, block: int = 1 << 15,
                    operands: str = "f64") -> np.ndarray:
     """``Y = A Omega`` for the ``n x ell`` test matrix of ``step``, summed over
     blocks of ``block`` rows of ``Omega`` (the same entries as
     :func:`gaussian_matrix`; only one block is drawn at a time).
 
-    ``operands="bf16"`` rounds the entries of ``A`` and ``Omega`` to bfloat16
-    (:func:`round_bf16`) before the product, which is then exact in float64:
-    the values a sketch with bfloat16 operands multiplies."""
-    A = np.asarray(A, dtype=np.float64)
-    if operands == "bf16":
-        A = round_bf16(A)
-    elif operands != "f64":
-        raise ValueError(operands)
+    ``operands="bf16"`` (``"f32"``) rounds the entries of ``A`` and ``Omega``
+    to bfloat16 (:func:`round_bf16`) or to single precision before the
+    product, which is then exact in float64: the values a sketch with such
+    operands multiplies."""
+    rnd = round_operands(operands)
+    A = rnd(np.asarray(A, dtype=np.float64))
     m, n = A.shape
     Y = np.zeros((m, ell))
     for r0 in range(0, n, block):
@@ -111,9 +120,7 @@ def sketch_product(A, ell: int, step: int, seed: int, block: int = 1 << 15,
         u1 = (x[0].astype(np.float64) + 0.5) * 2.0 ** -32
         u2 = (x[1].astype(np.float64) + 0.5) * 2.0 ** -32
         om = (np.sqrt(-2.0 * np.log(u1)) * np.cos(2.0 * np.pi * u2)).reshape(r1 - r0, ell)
-        if operands == "bf16":
-            om = round_bf16(om)
-        Y += A[:, r0:r1] @ om
+        Y += A[:, r0:r1] @ rnd(om)
     return Y
 
 
@@ -142,8 +149,15 @@ def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0
     drew ``Omega``) and ``margin``: the smallest ``|tail^2 - tau^2| / tau^2``
     over the decisions the threshold made (as in :func:`oracle.tt.tt_svd`),
     which flags rank decisions that a perturbation of ``B`` can flip.
-    ``operands`` is passed to :func:`sketch_product` (the sketch ``Y`` only;
-    ``Q``, ``B = Q^T A`` and its SVD stay in float64).
+    ``operands`` sets the values the two products of a sketched step see:
+    with ``"f64"`` both are exact in float64 and the remainder is
+    ``Sigma V^T`` from the SVD of ``B``; with ``"f32"`` or ``"bf16"`` the
+    entries of ``A`` and ``Omega`` are rounded to that format before the
+    range-finder product ``Y = A Omega``, and those of ``Q`` and ``A`` to
+    single precision before ``B = Q^T A`` (each product then exact in
+    float64); ``Q``, the SVD of ``B`` and ``U = Q U~`` stay in float64, and the
+    remainder is the projection ``U^T A`` of the unrounded unfolding (equal to
+    ``Sigma V^T`` in exact arithmetic).
     """
     v = np.asarray(a, dtype=np.float64).ravel()
     K = tt.log2_exact(v.size)
@@ -159,12 +173,19 @@ def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0
     rem = v.reshape((1, -1), order="F")
     for k in range(1, K):
         A = rem.reshape((2 * r_prev, -1), order="F")
+        project = False
         if ell >= A.shape[0]:
             U, s, Vt = np.linalg.svd(A, full_matrices=False)
         else:
             Q, _ = np.linalg.qr(sketch_product(A, ell, k, seed, operands=operands),
                                 mode="reduced")
-            U, s, Vt = rsvd(A, Q)
+            if operands == "f64":
+                U, s, Vt = rsvd(A, Q)
+            else:
+                rnd = round_operands("f32")
+                Ut, s, Vt = np.linalg.svd(rnd(Q).T @ rnd(A), full_matrices=False)
+                U = Q @ Ut
+                project = True
             info["sketched"].append(k)
         r = tt.truncation_rank(s, tau, max_rank)
         info["sv"].append(s.copy())
@@ -176,7 +197,7 @@ def tt_svd_sketch(a, eps: float, max_rank: int = 0, ell: int = 32, seed: int = 0
                     info["margin"] = min(info["margin"], abs(t - tau * tau) / (tau * tau))
         U, Vt = tt._gauge(U[:, :r].copy(), Vt[:r, :].copy())
         cores.append(U.reshape((r_prev, 2, r), order="F"))
-        rem = s[:r, None] * Vt
+        rem = (U.T @ A) if project else s[:r, None] * Vt
         info["ranks"].append(r)
         r_prev = r
     cores.append(rem.reshape((r_prev, 2, 1), order="F"))

@@ -178,3 +178,28 @@ def test_sketch_product_bf16_operands_is_the_product_of_rounded_values():
     # the rounding moves the sketch by about 2^-8 relative, not more
     full = A @ om
     assert np.linalg.norm(got - full) <= 2.0 ** -6 * np.linalg.norm(full)
+
+
+def test_sketched_sweep_with_rounded_operands_is_near_optimal():
+    """A sum of five rank-1 QTT terms (ranks <= 5) sketched with ell = 8 below the
+    row counts: with operands rounded to single precision or bfloat16 the kept
+    subspaces tilt by about that format's unit roundoff, so the tensor is
+    recovered to about 1e-6 or 1e-2; exact operands recover it to rounding."""
+    d = 12
+    rng = np.random.default_rng(9)
+    x = np.zeros(1 << d)
+    for _ in range(5):
+        t = np.ones(1)
+        for _k in range(d):
+            t = np.concatenate([t * rng.uniform(0.5, 1.5), t * rng.uniform(-1.5, 1.5)])
+        x += t
+    err = {}
+    for ops in ("f64", "f32", "bf16"):
+        cores, info = rsvd.tt_svd_sketch(x, 0.0, 5, ell=8, seed=4, return_info=True,
+                                         operands=ops)
+        assert info["sketched"] and max(info["ranks"]) == 5
+        err[ops] = np.linalg.norm(tt.tt_full(cores) - x) / np.linalg.norm(x)
+    assert err["f64"] <= 1e-12
+    assert err["f32"] <= 1e-5
+    assert err["bf16"] <= 3e-2
+    assert err["f64"] < err["f32"] < err["bf16"]
