@@ -253,22 +253,28 @@ int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int me
 int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_t seed,
               qtt_tensor* z, void* ws, size_t ws_bytes, void* stream);
 
-/* Capacities and workspace of qtt_round_sketch (1 <= ell <= QTT_SKETCH_MAX_ELL). */
+/* Capacities and workspace of qtt_round_sketch (2 <= ell <= QTT_SKETCH_MAX_ELL: the first
+ * unfolding has two rows, so its step is exact and gives the norm). */
 int qtt_query_round_sketch(int d, const int32_t* y_cap, int max_rank, int dtype, int ell,
                            int32_t* z_cap, size_t* ws_bytes, size_t* core_elems);
 
 /*
  * Randomised rounding (Algorithms 4 and 5 of Appendix A inside the TT-SVD
- * sweep of the represented tensor): at every step the unfolding A (m x n)
- * is sketched as Y = A Omega (m x ell, Omega Gaussian from Philox-4x32-10,
- * counter (row, col, step, 0), key = seed, Box-Muller of the first two
- * words), Q = qr(Y) and B = Q^T A give the truncated SVD, whose rank follows
- * the rule of Algorithm 1 at eps (cap max_rank).  The sketch GEMM runs in
- * FP32 (bf16 = 0) or with operands rounded to bfloat16 (bf16 = 1), with FP32
- * accumulation and an FP64 combine of the partial sums; QR, the small
- * eigenproblem and the Gram of A stay in FP64.  With ell >= m a step is the
- * exact SVD.  qtt_round's QTT_ROUND_SKETCH_* methods are this call with
- * ell = QTT_SKETCH_ELL.
+ * sweep of the represented tensor): at every step whose unfolding A (m x n)
+ * has more rows than the sketch width (m > ell), Y = A Omega (m x ell,
+ * Omega Gaussian from Philox-4x32-10, counter (row, col, step, 0), key =
+ * seed, Box-Muller of the first two words), Q = qr(Y) and B = Q^T A give the
+ * truncated SVD through the eigendecomposition of B B^T, whose rank follows
+ * the rule of Algorithm 1 at eps (cap max_rank); the next remainder is
+ * U^T A with U = Q U~.  The range-finder product Y = A Omega runs on the
+ * matrix cores with single-precision operands (bf16 = 0,
+ * v_mfma_f32_16x16x4f32) or operands rounded to bfloat16 (bf16 = 1,
+ * v_mfma_f32_16x16x32_bf16); B = Q^T A and B B^T run on the FP32 matrix
+ * cores with single-precision operands; all accumulate in FP32 with an FP64
+ * combine of the partial sums; QR, the small eigenproblem and the
+ * projection stay in FP64.  No Gram of A is formed on these steps.
+ * A step with ell >= m is the exact SVD (FP64 Gram).  qtt_round's
+ * QTT_ROUND_SKETCH_* methods are this call with ell = QTT_SKETCH_ELL.
  */
 int qtt_round_sketch(const qtt_tensor* y, double eps, int max_rank, int ell, int bf16,
                      uint64_t seed, qtt_tensor* z, void* ws, size_t ws_bytes, void* stream);

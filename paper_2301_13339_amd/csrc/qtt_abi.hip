@@ -398,7 +398,7 @@ int qtt_query_round(int d, const int32_t* y_cap, int max_rank, int dtype, int me
 
 int qtt_query_round_sketch(int d, const int32_t* y_cap, int max_rank, int dtype, int ell,
                            int32_t* z_cap, size_t* ws_bytes, size_t* core_elems) {
-  if (ell < 1 || ell > QTT_SKETCH_MAX_ELL) return QTT_EINVAL;
+  if (ell < 2 || ell > QTT_SKETCH_MAX_ELL) return QTT_EINVAL;
   return query_round_common(d, y_cap, max_rank, dtype, ell, z_cap, ws_bytes, core_elems);
 }
 
@@ -443,7 +443,7 @@ int qtt_round(const qtt_tensor* y, double eps, int max_rank, int method, uint64_
 
 int qtt_round_sketch(const qtt_tensor* y, double eps, int max_rank, int ell, int bf16,
                      uint64_t seed, qtt_tensor* z, void* ws, size_t ws_bytes, void* stream) {
-  if (ell < 1 || ell > QTT_SKETCH_MAX_ELL || (bf16 != 0 && bf16 != 1)) return QTT_EINVAL;
+  if (ell < 2 || ell > QTT_SKETCH_MAX_ELL || (bf16 != 0 && bf16 != 1)) return QTT_EINVAL;
   return round_common(y, eps, max_rank, ell, bf16, seed, z, ws, ws_bytes, stream);
 }
 

@@ -157,101 +157,43 @@ int run_conv(const TensorDev& f, const TensorDev* w, int n_axes, const int32_t* 
 // result is scattered by the layout of the mode.
 enum { GEMM_LEFT = 0, GEMM_RIGHT = 1, GEMM_FINAL = 2 };
 
-template <typename T, int MODE>
-__global__ void __launch_bounds__(256) k_chain_gemm(const T* A, const T* B, T* C,
-                                                    const int32_t* ranks, int k, int Mh, int Nh) {
-  constexpr int TM = 64, TN = 64, TK = 16;
-  __shared__ T As[TK][TM + 1];
-  __shared__ T Bs[TK][TN + 1];
-  int M, N, K, rk = 0;
-  if (MODE == GEMM_LEFT) {
-    K = ranks[k - 1];
-    rk = ranks[k];
-    M = Mh;
-    N = 2 * rk;
-  } else if (MODE == GEMM_RIGHT) {
-    M = 2 * ranks[k - 1];
-    K = ranks[k];
-    N = Nh;
-  } else {
-    M = Mh;
-    K = ranks[k];
-    N = Nh;
-  }
-  const int row0 = blockIdx.y * TM, col0 = blockIdx.x * TN;
-  if (row0 >= M || col0 >= N) return;
-  const int tid = threadIdx.x;
-  // thread (tr, tc) owns rows tr + 16a and columns tc + 16b: LDS reads of A
-  // are consecutive across the wave, reads of B are broadcasts
-  const int tr = tid & 15, tc = tid >> 4;
-  T acc[4][4];
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = (T)0;
-  for (int k0 = 0; k0 < K; k0 += TK) {
-    for (int e = tid; e < TK * TM; e += 256) {
-      const int kk = e % TK, mm = e / TK;
-      const int gr = row0 + mm, gk = k0 + kk;
-      As[kk][mm] = (gr < M && gk < K) ? A[(long long)gr * K + gk] : (T)0;
-    }
-    for (int e = tid; e < TK * TN; e += 256) {
-      const int nn = e % TN, kk = e / TN;
-      const int gk = k0 + kk, gc = col0 + nn;
-      Bs[kk][nn] = (gk < K && gc < N) ? B[(long long)gk * N + gc] : (T)0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < TK; ++kk) {
-      T xa[4], xb[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) xa[a] = As[kk][tr + 16 * a];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) xb[b] = Bs[kk][tc + 16 * b];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = fma(xa[a], xb[b], acc[a][b]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int gr = row0 + tr + 16 * a;
-    if (gr >= M) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int gc = col0 + tc + 16 * b;
-      if (gc >= N) continue;
-      long long dst;
-      if (MODE == GEMM_LEFT) {
-        const int i = gc / rk, bb = gc - i * rk;
-        dst = ((long long)gr + (long long)Mh * i) * rk + bb;
-      } else if (MODE == GEMM_RIGHT) {
-        dst = (long long)(gr >> 1) * (2LL * N) + (gr & 1) + 2LL * gc;
-      } else {
-        dst = (long long)gr + (long long)M * gc;
-      }
-      C[dst] = acc[a][b];
-    }
-  }
-}
-
-// FP64 chain product on the matrix cores.  v_mfma_f64_16x16x4f64 takes one
-// A entry per lane (row l % 16, k = l / 16), one B entry (k = l / 16,
-// column l % 16) and leaves D[4i + l / 16][l % 16] in accumulator i.  A
-// workgroup of four waves owns a tile of C (32 x 32: one 16 x 16 block per
-// wave, which keeps several workgroups per compute unit for the narrow
-// chains of Full); the A and B panels of 16 k-values
-// pass through LDS (stored k-major, so the fragment reads of a wave are 16
-// consecutive doubles per k).
+// Chain products on the matrix cores: v_mfma_f64_16x16x4f64 (FP64) and
+// v_mfma_f32_16x16x4f32 (FP32, FP32 accumulation) take one A entry per lane
+// (row l % 16, k = l / 16) and one B entry (k = l / 16, column l % 16); the
+// FP64 instruction leaves D[4i + l / 16][l % 16] in accumulator i, the FP32
+// one D[4 (l / 16) + i][l % 16].  A workgroup of four waves owns a
+// tile of C (32 x 32: one 16 x 16 block per wave, which keeps several
+// workgroups per compute unit for the narrow chains of Full); the A and B
+// panels of TK k-values pass through LDS (stored k-major, so the fragment
+// reads of a wave are 16 consecutive elements per k).
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int MODE, int SZ, int TK>
-__device__ __forceinline__ void chain_tile(const double* A, const double* B, double* C,
-                                           const int32_t* ranks, int k, int Mh, int Nh,
-                                           int bx, int by, double (*As)[TK][SZ + 4],
-                                           double (*Bs)[TK][SZ + 4]) {
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  using type = f64x4;
+  static __device__ __forceinline__ f64x4 step(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // row of the 16 x 16 block held by accumulator e of lane l
+  static __device__ __forceinline__ int row(int e, int l) { return 4 * e + (l >> 4); }
+};
+template <>
+struct MfmaAcc<float> {
+  using type = f32x4;
+  static __device__ __forceinline__ f32x4 step(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int e, int l) { return 4 * (l >> 4) + e; }
+};
+
+template <typename T, int MODE, int SZ, int TK>
+__device__ __forceinline__ void chain_tile(const T* A, const T* B, T* C, const int32_t* ranks,
+                                           int k, int Mh, int Nh, int bx, int by,
+                                           T (*As)[TK][SZ + 4], T (*Bs)[TK][SZ + 4]) {
+  using acc_t = typename MfmaAcc<T>::type;
   // SZ x SZ tile (bx, by) per workgroup; each wave an (SZ/2) x (SZ/2)
   // quarter made of NB x NB blocks of 16 x 16
   constexpr int NB = SZ / 32, PA = SZ * TK / 256;
@@ -279,19 +221,19 @@ __device__ __forceinline__ void chain_tile(const double* A, const double* B, dou
   // thread), B panel TK k x SZ columns (PA consecutive columns per thread)
   const int am = tid / (TK / PA), ak = (tid % (TK / PA)) * PA;
   const int bk = tid / (SZ / PA), bn = (tid % (SZ / PA)) * PA;
-  double ra[PA], rb[PA];
+  T ra[PA], rb[PA];
   auto load = [&](int k0) {
     const int gr = row0 + am;
 #pragma unroll
     for (int t = 0; t < PA; ++t) {
       const int gk = k0 + ak + t;
-      ra[t] = (gr < M && gk < K) ? A[(long long)gr * K + gk] : 0.0;
+      ra[t] = (gr < M && gk < K) ? A[(long long)gr * K + gk] : (T)0;
     }
     const int gk = k0 + bk;
 #pragma unroll
     for (int t = 0; t < PA; ++t) {
       const int gc = col0 + bn + t;
-      rb[t] = (gk < K && gc < N) ? B[(long long)gk * N + gc] : 0.0;
+      rb[t] = (gk < K && gc < N) ? B[(long long)gk * N + gc] : (T)0;
     }
   };
   auto store = [&](int buf) {
@@ -300,11 +242,11 @@ __device__ __forceinline__ void chain_tile(const double* A, const double* B, dou
 #pragma unroll
     for (int t = 0; t < PA; ++t) Bs[buf][bk][bn + t] = rb[t];
   };
-  f64x4 acc[NB][NB];
+  acc_t acc[NB][NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i)
 #pragma unroll
-    for (int j = 0; j < NB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = acc_t{(T)0, (T)0, (T)0, (T)0};
   const int nk = (K + TK - 1) / TK;
   load(0);
   store(0);
@@ -315,7 +257,7 @@ __device__ __forceinline__ void chain_tile(const double* A, const double* B, dou
 #pragma unroll
     for (int kk = 0; kk < TK; kk += 4) {
       const int kr = kk + (l >> 4);
-      double fa[NB], fb[NB];
+      T fa[NB], fb[NB];
 #pragma unroll
       for (int i = 0; i < NB; ++i) fa[i] = As[cur][kr][wr + 16 * i + (l & 15)];
 #pragma unroll
@@ -323,8 +265,7 @@ __device__ __forceinline__ void chain_tile(const double* A, const double* B, dou
 #pragma unroll
       for (int i = 0; i < NB; ++i)
 #pragma unroll
-        for (int j = 0; j < NB; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+        for (int j = 0; j < NB; ++j) acc[i][j] = MfmaAcc<T>::step(fa[i], fb[j], acc[i][j]);
     }
     if (kt + 1 < nk) store(cur ^ 1);
     __syncthreads();
@@ -335,7 +276,7 @@ __device__ __forceinline__ void chain_tile(const double* A, const double* B, dou
     for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const int gr = row0 + wr + 16 * i + 4 * e + (l >> 4);
+        const int gr = row0 + wr + 16 * i + MfmaAcc<T>::row(e, l);
         const int gc = col0 + wc + 16 * j + (l & 15);
         if (gr >= M || gc >= N) continue;
         long long dst;
@@ -351,31 +292,31 @@ __device__ __forceinline__ void chain_tile(const double* A, const double* B, dou
       }
 }
 
-template <int MODE, int SZ, int TK>
-__global__ void __launch_bounds__(256) k_chain_mfma(const double* A, const double* B, double* C,
+template <typename T, int MODE, int SZ, int TK>
+__global__ void __launch_bounds__(256) k_chain_mfma(const T* A, const T* B, T* C,
                                                     const int32_t* ranks, int k, int Mh, int Nh) {
-  __shared__ double As[2][TK][SZ + 4];
-  __shared__ double Bs[2][TK][SZ + 4];
-  chain_tile<MODE, SZ, TK>(A, B, C, ranks, k, Mh, Nh, blockIdx.x, blockIdx.y, As, Bs);
+  __shared__ T As[2][TK][SZ + 4];
+  __shared__ T Bs[2][TK][SZ + 4];
+  chain_tile<T, MODE, SZ, TK>(A, B, C, ranks, k, Mh, Nh, blockIdx.x, blockIdx.y, As, Bs);
 }
 
 // One step of the left chain and one of the right chain in a single launch
 // (they are independent until the final product): blocks 0 .. glx*gly - 1
 // take the left step's tiles, the rest the right step's.
-template <int SZ, int TK>
-__global__ void __launch_bounds__(256) k_chain_pair(const double* lamA, const double* coreL,
-                                                    double* dstL, int kl, int Mh, int glx,
-                                                    int gly, const double* coreR,
-                                                    const double* rhoB, double* dstR, int kr,
-                                                    int Nh, int grx, const int32_t* ranks) {
-  __shared__ double As[2][TK][SZ + 4];
-  __shared__ double Bs[2][TK][SZ + 4];
+template <typename T, int SZ, int TK>
+__global__ void __launch_bounds__(256) k_chain_pair(const T* lamA, const T* coreL, T* dstL, int kl,
+                                                    int Mh, int glx, int gly, const T* coreR,
+                                                    const T* rhoB, T* dstR, int kr, int Nh,
+                                                    int grx, const int32_t* ranks) {
+  __shared__ T As[2][TK][SZ + 4];
+  __shared__ T Bs[2][TK][SZ + 4];
   const int b = blockIdx.x, nl = glx * gly;
   if (b < nl)
-    chain_tile<GEMM_LEFT, SZ, TK>(lamA, coreL, dstL, ranks, kl, Mh, 0, b % glx, b / glx, As, Bs);
+    chain_tile<T, GEMM_LEFT, SZ, TK>(lamA, coreL, dstL, ranks, kl, Mh, 0, b % glx, b / glx, As,
+                                     Bs);
   else
-    chain_tile<GEMM_RIGHT, SZ, TK>(coreR, rhoB, dstR, ranks, kr, 0, Nh, (b - nl) % grx,
-                                   (b - nl) / grx, As, Bs);
+    chain_tile<T, GEMM_RIGHT, SZ, TK>(coreR, rhoB, dstR, ranks, kr, 0, Nh, (b - nl) % grx,
+                                      (b - nl) / grx, As, Bs);
 }
 
 // d == 1: out = core
@@ -434,14 +375,14 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
   size_t le, re;
   full_sizes(d, cap, &m, &le, &re);
   // left chain: Lam_1 = core 1 memory (2 x r_1); right chain: Rho_d = core d
-  // memory (r_{d-1} x 2).  In FP64 the two chains advance together, one
-  // launch per pair of steps.
+  // memory (r_{d-1} x 2).  The two chains advance together, one launch per
+  // pair of steps.
   const T* lam = cores + t.off[0];
   int li = 0;
   const T* rho = cores + t.off[d - 1];
   int ri = 2;
   int kl = 2, kr = d - 1;
-  if constexpr (sizeof(T) == 8) {
+  {
     for (; kl <= m && kr >= m + 1; ++kl, --kr) {
       T* dl = static_cast<T*>(bufs[li]);
       T* dr = static_cast<T*>(bufs[ri]);
@@ -450,7 +391,7 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
       const int grx = (Nh + 31) / 32, gry = (2 * cap[kr - 1] + 31) / 32;
       {
         ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
-        k_chain_pair<32, 32><<<glx * gly + grx * gry, 256, 0, stream>>>(
+        k_chain_pair<T, 32, 32><<<glx * gly + grx * gry, 256, 0, stream>>>(
             lam, cores + t.off[kl - 1], dl, kl, Mh, glx, gly, cores + t.off[kr - 1], rho, dr, kr,
             Nh, grx, t.ranks);
       }
@@ -465,16 +406,12 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     T* dst = static_cast<T*>(bufs[li]);
     const int Mh = 1 << (k - 1);
     const int Ncap = 2 * cap[k];
-    const int ts = sizeof(T) == 8 ? 32 : 64;  // tile of the FP64 matrix-core kernel / vector kernel
+    const int ts = 32;  // tile of the matrix-core kernel
     dim3 grid((Ncap + ts - 1) / ts, (Mh + ts - 1) / ts);
     {
       ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
-      if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_LEFT, 32, 32><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst, t.ranks,
-                                                          k, Mh, 0);
-      else
-        k_chain_gemm<T, GEMM_LEFT><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst,
-                                                           t.ranks, k, Mh, 0);
+      k_chain_mfma<T, GEMM_LEFT, 32, 32><<<grid, 256, 0, stream>>>(lam, cores + t.off[k - 1], dst,
+                                                                   t.ranks, k, Mh, 0);
     }
     QTT_LAUNCH_CHECK();
     lam = dst;
@@ -484,16 +421,12 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
     T* dst = static_cast<T*>(bufs[ri]);
     const int Nh = 1 << (d - k);
     const int Mcap = 2 * cap[k - 1];
-    const int ts = sizeof(T) == 8 ? 32 : 64;
+    const int ts = 32;
     dim3 grid((Nh + ts - 1) / ts, (Mcap + ts - 1) / ts);
     {
       ProbeScope _ps(QTT_K_FULL_CHAIN, stream);
-      if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_RIGHT, 32, 32><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst, t.ranks,
-                                                           k, 0, Nh);
-      else
-        k_chain_gemm<T, GEMM_RIGHT><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho, dst,
-                                                            t.ranks, k, 0, Nh);
+      k_chain_mfma<T, GEMM_RIGHT, 32, 32><<<grid, 256, 0, stream>>>(cores + t.off[k - 1], rho,
+                                                                    dst, t.ranks, k, 0, Nh);
     }
     QTT_LAUNCH_CHECK();
     rho = dst;
@@ -501,14 +434,12 @@ static int run_full_t(const TensorDev& t, T* out, void* ws, hipStream_t stream) 
   }
   {
     const int Mh = 1 << m, Nh = 1 << (d - m);
-    const int ts = sizeof(T) == 8 ? 32 : 64;
+    const int ts = 32;
     dim3 grid((Nh + ts - 1) / ts, (Mh + ts - 1) / ts);
     {
       ProbeScope _ps(QTT_K_FULL_FINAL, stream);
-      if constexpr (sizeof(T) == 8)
-        k_chain_mfma<GEMM_FINAL, 32, 32><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
-      else
-        k_chain_gemm<T, GEMM_FINAL><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh, Nh);
+      k_chain_mfma<T, GEMM_FINAL, 32, 32><<<grid, 256, 0, stream>>>(lam, rho, out, t.ranks, m, Mh,
+                                                                    Nh);
     }
     QTT_LAUNCH_CHECK();
   }
