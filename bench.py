@@ -29,6 +29,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector / matrix
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector
+BF16_PEAK_TFLOPS = 2500.0      # MI355X dense bfloat16 matrix
 N_CU = 256
 
 WORKLOADS = {
@@ -439,10 +440,27 @@ def bench_modes(args, wl):
     print(json.dumps(res), flush=True)
 
 
+def sketch_gemm_work(D, zranks, ell):
+    """Algorithmic work of the sketch GEMMs of one rounding sweep: for every
+    step k whose unfolding (m_k = 2 r_{k-1} rows, n_k = 2^(D-k) columns) is
+    wider than the sketch (m_k > ell), Y = A Omega (2 m n ell flops, bfloat16
+    operands) and B = Q^T A with B B^T (2 ell m n + 2 ell^2 n flops, FP32);
+    each pass reads the unfolding once (4 m n bytes in FP32)."""
+    fl_y = fl_b = byts = 0
+    for k in range(1, D):
+        m, n = 2 * zranks[k - 1], 1 << (D - k)
+        if m > ell:
+            fl_y += 2 * m * n * ell
+            fl_b += 2 * ell * m * n + 2 * ell * ell * n
+            byts += 2 * 4 * m * n
+    return fl_y, fl_b, byts
+
+
 def bench_image(args, wl):
-    """The precision form on a 4096 x 4096 image: FP32 data, BF16-operand
-    sketch rounding with FP32 accumulation, FP64 QR and eigensolvers; the error
-    against the FP64 exact pipeline on the GPU is reported with it."""
+    """The precision form on a 4096 x 4096 image: FP32 data, bfloat16-operand
+    sketch rounding (matrix cores, FP32 accumulation), FP64 QR and
+    eigensolvers; the error against the FP64 exact pipeline on the GPU is
+    reported with it, and the exact FP32 pipeline is timed beside it."""
     import numpy as np
     import torch
 
@@ -458,32 +476,63 @@ def bench_image(args, wl):
         return q.pipeline(x, (B, B), eps, R, shape2d=noisy.shape, round_method="sketch_bf16",
                           sketch_ell=ell, sketch_seed=1)
 
+    def exact32():
+        return q.pipeline(x, (B, B), eps, R, shape2d=noisy.shape)
+
     for _ in range(max(args.warmup, 1)):
         out, st = step()
+        exact32()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        out, st = step()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms = (t1 - t0) * 1e3 / args.steps
+
+    def timed(fn, steps):
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = None
+        for e0, e1 in evs:
+            e0.record()
+            res = fn()
+            e1.record()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        return (t1 - t0) / steps, sorted(e0.elapsed_time(e1) for e0, e1 in evs), res
+
+    wall, spread, (out, st) = timed(step, args.steps)
+    wall32, spread32, _ = timed(exact32, max(3, min(args.steps, 10)))
+    # GPU time per step of every kernel class (one probed step each)
+    classes = ["level_gram", "reduce", "level_eig", "project", "eig_step", "tail", "conv",
+               "full_chain", "full_final", "sketch", "sketch_gemm", "other"]
+    per = {}
+    for c in classes:
+        with q.probe(c) as p:
+            step()
+            torch.cuda.synchronize()
+        per[c] = (p.ms, p.launches)
+    dom = max(classes, key=lambda c: per[c][0])
+    zr = st["z"].ranks_host()
+    D = 2 * dd
+    fl_y, fl_b, gb = sketch_gemm_work(D, zr, ell)
+    g_ms = per["sketch_gemm"][0]
+    sk = {"launches_per_step": per["sketch_gemm"][1], "ms_per_step": g_ms,
+          "flops_per_step": {"Y_bf16": fl_y, "BBt_f32": fl_b}, "bytes_per_step": gb}
+    if g_ms > 0:
+        sk["achieved_TFLOPs"] = (fl_y + fl_b) / (g_ms * 1e-3) / 1e12
+        sk["frac_of_bf16_peak"] = sk["achieved_TFLOPs"] / BF16_PEAK_TFLOPS
+        sk["achieved_GBs"] = gb / (g_ms * 1e-3) / 1e9
+        sk["frac_of_hbm"] = sk["achieved_GBs"] / HBM_PEAK_GBS
     x64 = torch.tensor(noisy, dtype=torch.float64, device="cuda")
     ref, st64 = q.pipeline(x64, (B, B), eps, R, shape2d=noisy.shape)
     torch.cuda.synchronize()
-    t2 = time.perf_counter()
-    for _ in range(3):
-        q.pipeline(x, (B, B), eps, R, shape2d=noisy.shape)
-    torch.cuda.synchronize()
-    exact32_ms = (time.perf_counter() - t2) * 1e3 / 3
     o, r = out.double().cpu().numpy(), ref.cpu().numpy()
     res = {
         "metric": "samples/s for QTT decompose+conv+round+reconstruct at eps=1e-3",
-        "value": n * args.steps / (t1 - t0),
+        "value": n / wall,
         "unit": "samples/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms,
+        "ms_per_step": wall * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -491,13 +540,53 @@ def bench_image(args, wl):
         "data": "synthetic",
         "config": {"workload": f"image4096: {1 << dd} x {1 << dd} SAR-like image (200 point "
                                f"scatterers, 10 dB noise), separable sinc Bx=By={B:g}, eps={eps:g}, "
-                               f"rank cap {R}, BF16-operand sketch rounding (ell={ell})",
+                               f"rank cap {R}, bfloat16-operand sketch rounding (ell={ell})",
                    "samples": n},
+        "step_ms_p10_p50_p90": [spread[int(0.1 * (len(spread) - 1))], spread[len(spread) // 2],
+                                spread[int(0.9 * (len(spread) - 1))]],
+        "roofline": image_roofline(dom, per[dom], D, zr, st["f"].ranks_host(), ell),
+        "sketch_gemm": sk,
+        "e2e_hbm": {"algorithmic_bytes": 2 * n * 4,
+                    "achieved_GBs": 2 * n * 4 / wall / 1e9,
+                    "frac": 2 * n * 4 / wall / 1e9 / HBM_PEAK_GBS},
         "rel_err_vs_fp64_exact": float(np.linalg.norm(o - r) / np.linalg.norm(r)),
-        "ranks": {"Z_sketch": st["z"].ranks_host(), "Z_exact": st64["z"].ranks_host()},
-        "exact_fp32_ms": exact32_ms,
+        "ranks": {"Z_sketch": zr, "Z_exact": st64["z"].ranks_host()},
+        "exact_fp32": {"value": n / wall32, "ms_per_step": wall32 * 1e3,
+                       "step_ms_p10_p50_p90": [spread32[int(0.1 * (len(spread32) - 1))],
+                                               spread32[len(spread32) // 2],
+                                               spread32[int(0.9 * (len(spread32) - 1))]]},
+        "kernels_ms_per_step": {c: round(v[0], 4) for c, v in per.items()},
+        "kernel_launches_per_step": {c: v[1] for c, v in per.items()},
     }
     print(json.dumps(res), flush=True)
+
+
+def image_roofline(cls, ms_launches, D, zr, fr, ell):
+    """Work per launch of the dominant class of the image step over its
+    average launch time.  One-workgroup classes count 9 E^3 flops per
+    eigensolve of order E (QR of the sketch: 4 m ell^2); streaming classes
+    the bytes they must read."""
+    ms, launches = ms_launches
+    avg = ms / max(launches, 1) * 1e-3
+    common = {"kernel": cls, "traffic": None, "avg_launch_us": avg * 1e6,
+              "launches_per_step": launches}
+    if cls in ("sketch", "eig_step", "tail", "level_eig"):
+        if cls == "sketch":
+            works = []
+            for k in range(1, D):
+                m = 2 * zr[k - 1]
+                if m > ell:
+                    works.append(4.0 * m * ell * ell)
+                works.append(9.0 * min(m, ell) ** 3)
+        else:
+            works = [9.0 * (2 * r) ** 3 for r in fr[5:D - 1]] or [9.0 * 64 ** 3]
+        w = sum(works) / len(works)
+        ach = w / avg / 1e12
+        return {"bound": "alu", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": ach / FP64_PEAK_TFLOPS, **common,
+                "work_per_launch": f"{w:.4g} flops (9 E^3 per eigensolve, 4 m ell^2 per QR)"}
+    return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
+            **common}
 
 
 def cpu_model() -> str:

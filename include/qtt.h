@@ -476,7 +476,8 @@ int qtt_batch_status_offset(const qtt_batch* plan, int64_t* status_off_bytes,
 #define QTT_K_OTHER 10       /* bookkeeping kernels                            */
 #define QTT_K_ADJOINT 11     /* Toeplitz products on full vectors, adjoint of Full */
 #define QTT_K_BATCH 12       /* batched (many-line) kernels                     */
-#define QTT_K_SKETCH 13      /* randomised rounding (sketch passes and steps)   */
+#define QTT_K_SKETCH 13      /* randomised rounding: QR of the sketch, eigensteps */
+#define QTT_K_SKETCH_GEMM 14 /* sketch GEMMs Y = A Omega, B = Q^T A, B B^T (MFMA) */
 
 int qtt_probe_start(int cls, int max_launches);
 int qtt_probe_stop(double* total_ms, int* launches);

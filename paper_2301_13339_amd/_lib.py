@@ -41,7 +41,7 @@ EXPORTS = [
 K_CLASSES = {
     "level_gram": 1, "reduce": 2, "level_eig": 3, "project": 4, "eig_step": 5, "tail": 6,
     "conv": 7, "full_chain": 8, "full_final": 9, "other": 10, "adjoint": 11,
-    "batch": 12, "sketch": 13,
+    "batch": 12, "sketch": 13, "sketch_gemm": 14,
 }
 
 

@@ -114,7 +114,7 @@ const char* qtt_strerror(int code) {
 const char* qtt_last_hip_error(void) { return g_hip_err; }
 
 int qtt_probe_start(int cls, int max_launches) {
-  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_SKETCH || max_launches < 1 || max_launches > (1 << 20))
+  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_SKETCH_GEMM || max_launches < 1 || max_launches > (1 << 20))
     return QTT_EINVAL;
   probe_free();
   g_probe.ev = new hipEvent_t[2 * (size_t)max_launches];

@@ -549,6 +549,10 @@ size_t sketch_step_lds() {
 
 static size_t sketch_qr_lds() { return sizeof(double) * ((size_t)kMaxM * (kSkMaxEll + 1) + kSkMaxEll); }
 
+// exact-step Gram partials: kGramParts of kGramPstride doubles (m <= ell <= 64)
+constexpr int kGramParts = 512;
+constexpr int kGramPstride = kSkMaxEll * kSkMaxEll;
+
 struct SketchPlan {
   double* scal;
   double* partials;
@@ -565,7 +569,8 @@ static void sketch_plan(int D, int dtype, int ell, void* ws, SketchPlan* p) {
   const size_t es = elem_size(dtype);
   p->scal = ar.take<double>(16);
   p->pstride = kMaxM * kMaxM + kMaxM * ell;
-  p->partials = ar.take<double>((size_t)kMaxPartials * p->pstride);
+  const size_t pe = (size_t)kMaxPartials * p->pstride, ge = (size_t)kGramParts * kGramPstride;
+  p->partials = ar.take<double>(pe > ge ? pe : ge);
   p->gy = ar.take<double>((size_t)p->pstride);
   p->gq = ar.take<double>((size_t)kMaxM * kSkMaxEll);
   p->umat = ar.take<double>((size_t)kMaxM * kMaxRank);
@@ -605,72 +610,103 @@ static int sketch_t(const T* y, int D, double eps, const int* cap, int ell, uint
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   const T* X = y;
   int cur = 0;
-  ProbeScope _ps(QTT_K_SKETCH, s);
   for (int k = 1; k <= D - 1; ++k) {
     const long long n = 1LL << (D - k);
     const int mcap = (k == 1) ? 2 : 2 * cap[k - 1];  // bound on m = 2 r_{k-1}
     const int kin = k - 1;  // ranks index of r_{k-1}; 0 -> m = 2
     const long long nstage = (n + kSkSR - 1) / kSkSR;
     const int blocks = (int)(nstage < kMaxPartials ? nstage : kMaxPartials);
-    // 1. exact step (m <= ell): partials of the Gram (no-op on a sketched step)
+    // 1. exact step (m <= ell): partials of the Gram (no-op on a sketched step),
+    // m^2 <= kGramPstride entries each, up to kGramParts of them so that the
+    // pass spreads over every compute unit
     const int mg = mcap < ell ? mcap : ell;
-    int nparts = blocks;
+    int nparts;
     if (mcap <= 16 && mcap <= ell) {
       // narrow: the Gram in 2048-value stages
       const long long ns2 = (n * mcap + 2047) / 2048;
-      nparts = (int)(ns2 < kMaxPartials ? ns2 : kMaxPartials);
-      k_gram_small<T><<<nparts, 256, 0, s>>>(X, n, out.ranks, kin, p.partials, p.pstride);
+      nparts = (int)(ns2 < kGramParts ? ns2 : kGramParts);
+      ProbeScope _ps(QTT_K_PROJECT, s);
+      k_gram_small<T><<<nparts, 256, 0, s>>>(X, n, out.ranks, kin, p.partials, kGramPstride);
     } else {
+      nparts = (int)(nstage < kGramParts ? nstage : kGramParts);
       const size_t lds = sizeof(double) * kSkSR * mg;
+      ProbeScope _ps(QTT_K_PROJECT, s);
       if (mg <= 16)
-        k_gram_sketch<T, 1><<<blocks, 256, lds, s>>>(X, n, out.ranks, kin, ell, p.partials,
-                                                     p.pstride);
+        k_gram_sketch<T, 1><<<nparts, 256, lds, s>>>(X, n, out.ranks, kin, ell, p.partials,
+                                                     kGramPstride);
       else if (mg <= 32)
-        k_gram_sketch<T, 2><<<blocks, 256, lds, s>>>(X, n, out.ranks, kin, ell, p.partials,
-                                                     p.pstride);
+        k_gram_sketch<T, 2><<<nparts, 256, lds, s>>>(X, n, out.ranks, kin, ell, p.partials,
+                                                     kGramPstride);
       else
-        k_gram_sketch<T, 4><<<blocks, 256, lds, s>>>(X, n, out.ranks, kin, ell, p.partials,
-                                                     p.pstride);
+        k_gram_sketch<T, 4><<<nparts, 256, lds, s>>>(X, n, out.ranks, kin, ell, p.partials,
+                                                     kGramPstride);
     }
     QTT_LAUNCH_CHECK();
-    k_sum_partials<<<(mg * mg + 255) / 256, 256, 0, s>>>(p.partials, p.pstride, nparts,
-                                                         out.ranks, kin, ell, 0, p.gy);
+    {
+      ProbeScope _ps(QTT_K_REDUCE, s);
+      k_sum_partials<<<(mg * mg + 255) / 256, 256, 0, s>>>(p.partials, kGramPstride, nparts,
+                                                           out.ranks, kin, ell, 0, p.gy);
+    }
     QTT_LAUNCH_CHECK();
     // 2. sketched step (m > ell, decided on the device): Y, Q, B B^T
     if (mcap > ell) {
       const int mp = (mcap + 15) & ~15, ep = (ell + 15) & ~15, mk = (mcap + 31) & ~31;
       const size_t lds_y = sizeof(OT) * (size_t)(mp + ep) * kSkLd;
-      k_sketch_y<T, BF><<<blocks, 256, lds_y, s>>>(X, n, out.ranks, kin, ell, k0, k1, k,
-                                                   p.partials, p.pstride);
+      {
+        ProbeScope _ps(QTT_K_SKETCH_GEMM, s);
+        k_sketch_y<T, BF><<<blocks, 256, lds_y, s>>>(X, n, out.ranks, kin, ell, k0, k1, k,
+                                                     p.partials, p.pstride);
+      }
       QTT_LAUNCH_CHECK();
-      k_sum_partials<<<(mcap * ell + 255) / 256, 256, 0, s>>>(p.partials, p.pstride, blocks,
-                                                              out.ranks, kin, ell, 1, p.gy);
+      {
+        ProbeScope _ps(QTT_K_REDUCE, s);
+        k_sum_partials<<<(mcap * ell + 255) / 256, 256, 0, s>>>(p.partials, p.pstride, blocks,
+                                                                out.ranks, kin, ell, 1, p.gy);
+      }
       QTT_LAUNCH_CHECK();
-      k_sketch_qr<<<1, kEigThreads, sketch_qr_lds(), s>>>(p.gy, k, ell, out.ranks, p.gq);
+      {
+        ProbeScope _ps(QTT_K_SKETCH, s);
+        k_sketch_qr<<<1, kEigThreads, sketch_qr_lds(), s>>>(p.gy, k, ell, out.ranks, p.gq);
+      }
       QTT_LAUNCH_CHECK();
       const size_t lds_b = sizeof(float) * ((size_t)(ep + kSkSR) * (mk + 8) +
                                             (size_t)ep * (kSkSR + 4));
-      k_sketch_gb<T><<<blocks, 256, lds_b, s>>>(X, n, out.ranks, kin, ell, p.gq, p.partials,
-                                                p.pstride);
+      {
+        ProbeScope _ps(QTT_K_SKETCH_GEMM, s);
+        k_sketch_gb<T><<<blocks, 256, lds_b, s>>>(X, n, out.ranks, kin, ell, p.gq, p.partials,
+                                                  p.pstride);
+      }
       QTT_LAUNCH_CHECK();
-      k_sum_partials<<<(ell * ell + 255) / 256, 256, 0, s>>>(p.partials, p.pstride, blocks,
-                                                             out.ranks, kin, ell, 2, p.gy);
+      {
+        ProbeScope _ps(QTT_K_REDUCE, s);
+        k_sum_partials<<<(ell * ell + 255) / 256, 256, 0, s>>>(p.partials, p.pstride, blocks,
+                                                               out.ranks, kin, ell, 2, p.gy);
+      }
       QTT_LAUNCH_CHECK();
     }
     // 3. the small eigenproblem, rank and core k
-    k_sketch_step<T><<<1, kEigThreads, sketch_step_lds(), s>>>(
-        p.gy, p.gq, k, D, eps, k == 1, ell, p.scal, cap[k], cores, out.off[k - 1], p.umat, so);
+    {
+      ProbeScope _ps(QTT_K_SKETCH, s);
+      k_sketch_step<T><<<1, kEigThreads, sketch_step_lds(), s>>>(
+          p.gy, p.gq, k, D, eps, k == 1, ell, p.scal, cap[k], cores, out.off[k - 1], p.umat, so);
+    }
     QTT_LAUNCH_CHECK();
     // 4. next remainder
     T* Xn = static_cast<T*>(p.xbuf[cur]);
     long long pb = (n * cap[k] + 255) / 256;
     if (pb > 4096) pb = 4096;
-    k_sketch_project<T><<<(unsigned)pb, 256, 0, s>>>(X, n, out.ranks, kin, k, p.umat, Xn);
+    {
+      ProbeScope _ps(QTT_K_PROJECT, s);
+      k_sketch_project<T><<<(unsigned)pb, 256, 0, s>>>(X, n, out.ranks, kin, k, p.umat, Xn);
+    }
     QTT_LAUNCH_CHECK();
     X = Xn;
     cur ^= 1;
   }
-  k_sketch_last<T><<<1, 64, 0, s>>>(X, out.ranks, D, cores, out.off[D - 1], out.ranks);
+  {
+    ProbeScope _ps(QTT_K_OTHER, s);
+    k_sketch_last<T><<<1, 64, 0, s>>>(X, out.ranks, D, cores, out.off[D - 1], out.ranks);
+  }
   QTT_LAUNCH_CHECK();
   return QTT_OK;
 }
