@@ -18,6 +18,8 @@ Modules
 ``rsvd``      range finder and randomized SVD (Algorithms 4 and 5).
 ``ttm``       TT-SVD and max-rank TT-RSVD for mode sizes other than 2.
 ``grads``     gradients of the convolution + reconstruction loss.
+``qfft``      QTT-FFT / QTT-iFFT (radix-2 stages with rounding), Hadamard
+              product and the QTT-FFT convolution route (Algorithm 2, Step 3).
 
 Readings of passages that are ambiguous or garbled are listed in each
 function's docstring.

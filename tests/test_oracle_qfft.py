@@ -1,0 +1,231 @@
+"""Pins of the oracle's QTT-FFT convolution route (Algorithm 2, Step 3) against
+what the mathematics and the paper fix: numpy's FFT (exact transform), the
+inverse DFT, a pure tone (rank 1 at every stage), the error identity of each
+rounding, the direct convolution (2.2), and Table 7.1's QTT_0 errors, which
+the paper obtained with this route."""
+
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import conv, qfft as Q, tt
+from oracle import pipeline as P
+from synthetic import generators as G
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "table_7_1_qtt_errors.json")))["values"]
+
+
+def random_tt(D, r, seed, complex_=True):
+    rng = np.random.default_rng(seed)
+    rk = [1] + [min(r, 2 ** k, 2 ** (D - k)) for k in range(1, D)] + [1]
+    cores = []
+    for k in range(D):
+        c = rng.standard_normal((rk[k], 2, rk[k + 1]))
+        if complex_:
+            c = c + 1j * rng.standard_normal(c.shape)
+        cores.append(c)
+    return cores
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("D", list(range(1, 11)))
+def test_qfft_exact_equals_numpy_fft(D):
+    """No truncation: the transform is numpy's DFT (exponent -2 pi i a b / N),
+    in bit-reversed order; QiFFT of it is the input again."""
+    x = random_tt(D, 6, D)
+    v = Q.full(x)
+    y = Q.qfft(x)
+    assert rel(Q.full(y), np.fft.fft(v)[Q.bit_reverse(D)]) <= 1e-13
+    z = Q.qifft(y)
+    assert rel(Q.full(z), v) <= 1e-13
+
+
+@pytest.mark.parametrize("D", [3, 8])
+def test_qifft_equals_numpy_ifft(D):
+    X = random_tt(D, 5, 100 + D)
+    got = Q.full(Q.qifft(X))
+    spec = np.empty(1 << D, dtype=complex)
+    spec[Q.bit_reverse(D)] = Q.full(X)        # natural-order spectrum
+    assert rel(got, np.fft.ifft(spec)) <= 1e-13
+
+
+def test_stage_is_one_factor_of_the_dft():
+    """After stage 1 of an 8-digit transform the tensor is the sum over the top
+    digit with the first factor: Y(a', b_1) = sum_{a_8} x(a) exp(-2 pi i b_1 a / 2^8)."""
+    D = 8
+    x = random_tt(D, 4, 7)
+    v = Q.full(x)
+    y = Q.full(Q.fft_stage(Q.as_complex(x), 1, -1))
+    a = np.arange(1 << D)
+    for b1 in (0, 1):
+        lo = a[: 1 << (D - 1)]
+        want = v[lo] * np.exp(-2j * np.pi * b1 * lo / (1 << D)) + \
+            v[lo + (1 << (D - 1))] * np.exp(-2j * np.pi * b1 * (lo + (1 << (D - 1))) / (1 << D))
+        got = y[lo + b1 * (1 << (D - 1))]
+        assert rel(got, want) <= 1e-13
+
+
+def test_tone_stays_rank_one():
+    """A pure tone exp(2 pi i f a / N) is rank 1, and so is every partial DFT of it:
+    with the cap R^ = 1 the transform is exact, N at position rev(f)."""
+    D, f = 12, 1234
+    cores = [np.array([1.0, np.exp(2j * np.pi * f * 2 ** p / 2 ** D)]).reshape(1, 2, 1)
+             for p in range(D)]
+    y, info = Q.qfft(cores, -1, 0.0, 1, 0.0, return_info=True)
+    assert all(r == [1] * (D + 1) for r in info["ranks"])
+    spec = np.empty(1 << D, dtype=complex)
+    spec[Q.bit_reverse(D)] = Q.full(y)
+    want = np.zeros(1 << D)
+    want[f] = 2 ** D
+    assert np.max(np.abs(spec - want)) <= 1e-12 * 2 ** D
+
+
+def test_rounding_error_identity_per_stage():
+    """Each rounding discards exactly the Frobenius norm it reports (the
+    sweep keeps the left part left-orthonormal and the right part
+    right-orthonormal), and the errors of the stages add up to at most
+    sum_s 2^((D-s)/2) e_s (later stages scale by sqrt 2 each)."""
+    D, R = 10, 4
+    x = random_tt(D, 8, 3)
+    v = Q.full(x)
+    cores = Q.as_complex(x)
+    info = Q._new_info()
+    bound = 0.0
+    for s in range(1, D + 1):
+        m = D + 1 - s
+        exact = Q.fft_stage(cores, s, -1)
+        if m > 1:
+            cores, e = Q.round_doubled(exact, m, 0.0, R, 0.0, info)
+        else:
+            cores, e = exact, 0.0
+        assert abs(np.linalg.norm(Q.full(cores) - Q.full(exact)) - e) <= 1e-10 * np.linalg.norm(
+            Q.full(exact))
+        bound += 2 ** ((D - s) / 2) * e
+        assert max(Q.ranks(cores)) <= max(R, 2)
+    err = np.linalg.norm(Q.full(cores) - np.fft.fft(v)[Q.bit_reverse(D)])
+    assert 0 < err <= bound * (1 + 1e-9)
+    y2 = Q.qfft(x, -1, 0.0, R)
+    assert rel(Q.full(y2), Q.full(cores)) <= 1e-12
+
+
+def test_rounding_keeps_canonical_form():
+    """After a stage's rounding, cores 2..D are right-orthonormal (the
+    invariant the next stage relies on)."""
+    D = 9
+    x = random_tt(D, 6, 11)
+    cores = Q.as_complex(x)
+    info = Q._new_info()
+    for s in range(1, D):
+        m = D + 1 - s
+        cores, _ = Q.round_doubled(Q.fft_stage(cores, s, -1), m, 0.0, 5, 0.0, info)
+        for G_ in cores[1:]:
+            M = G_.reshape(G_.shape[0], -1)
+            assert np.max(np.abs(M @ M.conj().T - np.eye(M.shape[0]))) <= 1e-12
+
+
+def test_tolerance_rule_bounds_each_rounding():
+    """With eps^ only, each stage's rounding error is at most
+    eps^ ||Y_s|| (the tail rule on at most D-1 bonds at tau = eps^ ||Y|| / sqrt(D-1))."""
+    D, eps = 10, 1e-3
+    x = random_tt(D, 6, 5)
+    y, info = Q.qfft(x, -1, eps, 0, 0.0, return_info=True)
+    nrm = np.linalg.norm(Q.full(x))
+    for s, e in enumerate(info["discarded"], start=1):
+        assert e <= eps * nrm * 2 ** (s / 2) * (1 + 1e-12)
+
+
+def test_hadamard_is_entrywise_product():
+    a = random_tt(7, 4, 1)
+    b = random_tt(7, 3, 2)
+    h = Q.hadamard(a, b)
+    assert rel(Q.full(h), Q.full(a) * Q.full(b)) <= 1e-13
+    assert Q.ranks(h) == [x * y for x, y in zip(Q.ranks(a), Q.ranks(b))]
+
+
+def test_hadamard_round_exact_when_sketch_covers():
+    """ell = R^ + p at least the product's ranks: the sketch spans every right
+    part and the result is the exact product."""
+    a = random_tt(8, 3, 4)
+    b = random_tt(8, 2, 5)
+    h, info = Q.hadamard_round(a, b, 0.0, 6, 0.0, oversample=4, seed=9, return_info=True)
+    assert rel(Q.full(h), Q.full(a) * Q.full(b)) <= 1e-12
+    assert max(Q.ranks(h)) <= 6
+
+
+def test_hadamard_round_near_optimal():
+    """ell below the product's ranks: the randomised rounding's error is
+    within a small factor of the deterministic rounding at the same cap."""
+    a = random_tt(10, 6, 6)
+    b = random_tt(10, 5, 7)
+    exact = Q.full(a) * Q.full(b)
+    for R in (4, 8):
+        det = Q.hadamard_round(a, b, 0.0, 0, 0.0)
+        det_capped, _ = Q.truncate_right_to_left(
+            _left_orth(det), 0.0, R, 0.0, Q._new_info())
+        rnd = Q.hadamard_round(a, b, 0.0, R, 0.0, oversample=8, seed=R)
+        e_det = rel(Q.full(det_capped), exact)
+        e_rnd = rel(Q.full(rnd), exact)
+        assert max(Q.ranks(rnd)) <= R
+        assert e_rnd <= 3.0 * e_det + 1e-12, (R, e_rnd, e_det)
+
+
+def _left_orth(cores):
+    out = list(cores)
+    for p in range(len(out) - 1):
+        r0, _, r1 = out[p].shape
+        q, r = np.linalg.qr(out[p].reshape(2 * r0, r1))
+        out[p] = q.reshape(r0, 2, q.shape[1])
+        out[p + 1] = np.einsum("kb,bjc->kjc", r, out[p + 1])
+    return out
+
+
+@pytest.mark.parametrize("d,B", [(4, 3.0), (6, 10.0), (8, 40.0), (9, 100.0)])
+def test_conv_route_exact_equals_direct_convolution(d, B):
+    """No truncation: the real part of QiFFT(QFFT(F) . QFFT(G)) on the padded
+    data and the rotated generator is the direct sum T(w) f of (2.2); the
+    imaginary part vanishes."""
+    rng = np.random.default_rng(d)
+    f = rng.standard_normal(1 << d)
+    w = conv.toeplitz_generator(d, B)
+    y = Q.full(Q.conv_fft(tt.tt_svd(f, 0.0), tt.tt_svd(w, 0.0)))
+    ref = conv.toeplitz_apply(f, w)
+    assert rel(y.real, ref) <= 1e-12
+    assert np.linalg.norm(y.imag) <= 1e-12 * np.linalg.norm(ref)
+    dense = conv.toeplitz_dense(w) @ f
+    assert rel(y.real, dense) <= 1e-12
+
+
+def test_realify_is_the_real_part():
+    c = random_tt(6, 4, 8)
+    r = Q.realify(c)
+    assert all(np.isrealobj(g) for g in r)
+    assert rel(tt.tt_full(r), Q.full(c).real) <= 1e-13
+    assert Q.ranks(r)[1:-1] == [2 * x for x in Q.ranks(c)[1:-1]]
+
+
+@pytest.mark.parametrize("name,gen", [("example1", G.paper_example1),
+                                      ("example2", G.paper_example2)])
+def test_paper_table_7_1_qtt0_through_the_qfft_route(name, gen):
+    """Examples 1 and 2 at K = 20 through the paper's own route (max-rank
+    TT-SVD with R_max = 10, QFFT/QiFFT truncated at R^_max = 15): the error
+    (7.1) against the noise-free convolution reproduces Table 7.1's QTT_0
+    column (0.0028 and 0.0011) within 10 %."""
+    K = 20
+    noisy, clean, _, _ = gen(K, 0)
+    x = np.zeros(1 << K)
+    c = np.zeros(1 << K)
+    x[: noisy.size] = noisy
+    c[: clean.size] = clean
+    B = (1 << K) / float(GOLD[name]["resolution_in_dx"])
+    F = tt.tt_svd(x, 1e-4, 10)
+    W = tt.tt_svd(conv.toeplitz_generator(K, B), 1e-5, 0)
+    y = Q.full(Q.conv_fft(F, W, 0.0, 15, 0.0, oversample=8, seed=1))
+    e = P.relative_error(y.real, P.clean_reference_1d(c, B))
+    assert abs(e - GOLD[name]["qtt0"]) <= 0.1 * GOLD[name]["qtt0"], e
