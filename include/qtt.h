@@ -58,10 +58,12 @@ extern "C" {
 /* device status bits (OR-ed into *status) */
 #define QTT_STATUS_NONFINITE 1  /* the input held NaN or Inf                    */
 #define QTT_STATUS_RANKCAP 2    /* an eps-rank exceeded the rank capacity       */
+#define QTT_STATUS_FFT_RANK 4   /* a QTT-FFT input rank above QTT_FFT_MAX_RANK  */
 
 /* element types */
 #define QTT_F32 0
 #define QTT_F64 1
+#define QTT_C128 2  /* complex, FP64 (re, im) pairs; QTT-FFT tensors only */
 
 /* rounding methods for qtt_round */
 #define QTT_ROUND_EXACT 0       /* TT-SVD of the represented tensor, FP64 sums  */
@@ -455,6 +457,82 @@ int qtt_batch_status_offset(const qtt_batch* plan, int64_t* status_off_bytes,
                             int32_t* chunk_bits);
 
 /* ------------------------------------------------------------ measurement */
+/* ------------------------------------------------------------- QTT-FFT */
+#define QTT_FFT_MAX_RANK 16  /* largest rank into and out of a QTT-FFT          */
+#define QTT_FFT_MAX_ELL 32   /* largest sketch width R^_max + p of qtt_conv_fft  */
+
+/*
+ * Sizes for qtt_fft.  Outputs (either may be NULL): cap[0..d] =
+ * min(2^k, 2^(d-k), max_rank or QTT_FFT_MAX_RANK), the capacities the output
+ * tensor needs, and the workspace size.
+ */
+int qtt_query_fft(int d, int max_rank, int32_t* cap, size_t* ws_bytes);
+
+/*
+ * QTT-FFT (Section 4; the truncated transform of Section 5): the DFT
+ * X(b) = sum_a x(a) exp(-2 pi i a b / 2^d) of a complex QTT tensor, computed
+ * in QTT format as the d radix-2 decimation-in-frequency stages (stage s sums
+ * over digit a_m, m = d + 1 - s, and doubles bonds 1..m-1), each followed by
+ * the rounding of the doubled bonds: Householder QR from the left, then
+ * one-sided Jacobi SVDs from core m down to core 2, truncated to
+ * min(r_eps, r_drop, cap) as in Algorithm 1 with modifications (1) and (3),
+ * tau = eps ||Y_s|| / sqrt(d-1).  The output is in BIT-REVERSED mode order:
+ * mode p of y holds digit b_(d+1-p).
+ * inverse != 0: QTT-iFFT, x(a) = 2^-d sum_b X(b) exp(+2 pi i a b / 2^d), with
+ * the input in the bit-reversed order a forward transform returns and the
+ * output in natural order.
+ *   x         complex tensor (dtype QTT_C128); its actual ranks must not exceed
+ *             QTT_FFT_MAX_RANK, otherwise the output is the zero tensor and
+ *             QTT_STATUS_FFT_RANK is set in y->status
+ *   eps       tolerance of each rounding (0 = off); delta: drop-off threshold
+ *             in [0, 1) (0 = off); max_rank: cap R^_max in 0..QTT_FFT_MAX_RANK
+ *             (0 = QTT_FFT_MAX_RANK, with QTT_STATUS_RANKCAP set when the
+ *             tolerance or drop-off rank exceeded it)
+ *   y         complex tensor, d modes, capacities from qtt_query_fft
+ * All arithmetic is FP64.  Errors: QTT_EINVAL (arguments, d > 31),
+ * QTT_ENOSPC (y or workspace).
+ */
+int qtt_fft(const qtt_tensor* x, int inverse, double eps, int max_rank, double delta,
+            qtt_tensor* y, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Sizes for qtt_conv_fft: y_cap[0..d] = 2 min(2^k, 2^(d+1-k), max_rank_hat)
+ * inside (1 at the ends) and the workspace size.  Requires
+ * 1 <= max_rank_hat <= QTT_FFT_MAX_RANK and max_rank_hat + oversample <=
+ * QTT_FFT_MAX_ELL.
+ */
+int qtt_query_conv_fft(int d, int max_rank_hat, int oversample, int32_t* y_cap, size_t* ws_bytes);
+
+/*
+ * The QTT-FFT convolution route, Step 3 of Algorithm 2:
+ * I = QiFFT(QFFT(F) . QFFT(G)), truncated by R^_max (and optionally a
+ * tolerance and the drop-off threshold) in every transform.
+ *   f         real data tensor, d modes (f32 or f64); it is zero-padded by
+ *             one mode (2^(d+1) samples, the data in the lower half)
+ *   w         real Toeplitz generator of the kernel, d + 1 modes (as written
+ *             by qtt_kernel_sinc: lag u - 2^d at index u); it is rotated by
+ *             2^d (lag 0 at index 0, the
+ *             negative lags at the top), so that the lower half of the
+ *             circular convolution is the discrete convolution (2.2), the
+ *             product T(w) f of qtt_conv
+ *   eps_hat, max_rank_hat, delta_hat   the rule of every rounding, as in
+ *             qtt_fft (max_rank_hat >= 1)
+ *   oversample, seed   the product of the two spectra (ranks r_F r_G) is
+ *             rounded by a randomised TT rounding: Gaussian sketch TT of
+ *             ranks ell = max_rank_hat + oversample (Philox-4x32-10, counter
+ *             (2t + i, u, p, 0) for entry (t, i, u) of core p, key = seed),
+ *             orthogonalisation left to right, then the truncation sweep
+ *   y         real tensor, d modes, dtype of f, capacities from
+ *             qtt_query_conv_fft: the real part of the lower half of the
+ *             inverse transform as a real TT (complex ranks doubled)
+ * The actual ranks of f and w must not exceed QTT_FFT_MAX_RANK; otherwise y
+ * is the zero tensor and QTT_STATUS_FFT_RANK is set in y->status.  The
+ * transforms run in FP64 complex arithmetic whatever the dtype of f.
+ */
+int qtt_conv_fft(const qtt_tensor* f, const qtt_tensor* w, double eps_hat, int max_rank_hat,
+                 double delta_hat, int oversample, uint64_t seed, qtt_tensor* y, void* ws,
+                 size_t ws_bytes, void* stream);
+
 /*
  * Kernel classes for the launch probe.  Between qtt_probe_start and
  * qtt_probe_stop the library records a HIP event pair on the launch stream
@@ -478,6 +556,8 @@ int qtt_batch_status_offset(const qtt_batch* plan, int64_t* status_off_bytes,
 #define QTT_K_BATCH 12       /* batched (many-line) kernels                     */
 #define QTT_K_SKETCH 13      /* randomised rounding: QR of the sketch, eigensteps */
 #define QTT_K_SKETCH_GEMM 14 /* sketch GEMMs Y = A Omega, B = Q^T A, B B^T (MFMA) */
+#define QTT_K_QFFT 15        /* QTT-FFT stages and their rounding (one workgroup each) */
+#define QTT_K_QFFT_HADAMARD 16 /* randomised rounding of the spectra's product    */
 
 int qtt_probe_start(int cls, int max_launches);
 int qtt_probe_stop(double* total_ms, int* launches);

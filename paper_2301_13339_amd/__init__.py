@@ -22,17 +22,19 @@ import os
 
 import torch
 
-from ._lib import (QTT_F32, QTT_F64, QTT_MAX_RANK, QTT_MAXD, QTT_ROUND_EXACT,
+from ._lib import (QTT_C128, QTT_F32, QTT_F64, QTT_FFT_MAX_ELL, QTT_FFT_MAX_RANK,
+                   QTT_MAX_RANK, QTT_MAXD, QTT_ROUND_EXACT,
                    QTT_ROUND_SKETCH_BF16, QTT_ROUND_SKETCH_F32, QTT_STATUS_NONFINITE,
                    QTT_STATUS_RANKCAP, QttError, lib, lib_path, qtt_tensor)
 
 __all__ = [
     "QTT", "probe", "from_cores", "decompose", "kernel_sinc", "conv", "round", "full", "pipeline",
     "toeplitz_apply", "kernel_sinc_dB", "full_adjoint", "conv_full_backward", "ConvFull",
-    "conv_full", "Batch", "lib_path", "QttError", "QTT_MAX_RANK",
+    "conv_full", "Batch", "lib_path", "QttError", "QTT_MAX_RANK", "qfft", "conv_fft",
+    "QTT_FFT_MAX_RANK",
 ]
 
-_DT = {torch.float32: QTT_F32, torch.float64: QTT_F64}
+_DT = {torch.float32: QTT_F32, torch.float64: QTT_F64, torch.complex128: QTT_C128}
 
 
 class probe:
@@ -61,7 +63,7 @@ class probe:
         self.ms = ms.value
         self.launches = n.value
         return False
-_TORCH = {QTT_F32: torch.float32, QTT_F64: torch.float64}
+_TORCH = {QTT_F32: torch.float32, QTT_F64: torch.float64, QTT_C128: torch.complex128}
 
 
 def _check(rc: int, what: str):
@@ -156,9 +158,11 @@ class QTT:
         return t
 
     def core_list(self):
-        """Cores as CPU float64 numpy arrays of shape ``(r_{k-1}, 2, r_k)``."""
+        """Cores as CPU float64 (complex128 for complex tensors) numpy arrays of
+        shape ``(r_{k-1}, 2, r_k)``."""
         r = self.ranks_host()
-        flat = self.cores.detach().cpu().double().numpy()
+        flat = self.cores.detach().cpu()
+        flat = (flat if flat.is_complex() else flat.double()).numpy()
         out = []
         for k, o in enumerate(self.core_offsets()):
             n = r[k] * 2 * r[k + 1]
@@ -175,7 +179,8 @@ def from_cores(cores, dtype=torch.float64, device="cuda") -> QTT:
     d = len(cores)
     ranks = [int(cores[0].shape[0])] + [int(c.shape[2]) for c in cores]
     t = _make(d, _DT[dtype], ranks, device)
-    flat = torch.cat([torch.as_tensor(c, dtype=torch.float64).reshape(-1) for c in cores])
+    wide = torch.complex128 if dtype == torch.complex128 else torch.float64
+    flat = torch.cat([torch.as_tensor(c, dtype=wide).reshape(-1) for c in cores])
     t.cores[: flat.numel()].copy_(flat.to(dtype))
     t.ranks.copy_(torch.tensor(ranks, dtype=torch.int32))
     return t
@@ -400,6 +405,72 @@ def full_noalloc(t: QTT, out: torch.Tensor) -> torch.Tensor:
     _check(lib().qtt_full_noalloc(ctypes.byref(tc), ctypes.c_void_p(out.data_ptr()),
                                   _stream(t.device)), "qtt_full_noalloc")
     return out
+
+
+def qfft(x: QTT, inverse: bool = False, eps: float = 0.0, max_rank: int = 0,
+         delta: float = 0.0) -> QTT:
+    """QTT-FFT of a complex QTT (bit-reversed output), or with ``inverse`` the
+    QTT-iFFT of a bit-reversed spectrum; every stage rounded by the rule
+    ``(eps, max_rank, delta)`` (see ``qtt_fft`` in include/qtt.h)."""
+    if x.dtype != QTT_C128:
+        raise ValueError("qfft takes a complex QTT (torch.complex128 cores)")
+    cap = (ctypes.c_int32 * (x.d + 1))()
+    ws = ctypes.c_size_t()
+    _check(lib().qtt_query_fft(x.d, int(max_rank), cap, ctypes.byref(ws)), "qtt_query_fft")
+    y = _make(x.d, QTT_C128, list(cap), x.device)
+    wsb = _workspace(ws.value, x.device)
+    xc, yc = x._c(), y._c()
+    _check(lib().qtt_fft(ctypes.byref(xc), int(bool(inverse)), float(eps), int(max_rank),
+                         float(delta), ctypes.byref(yc), ctypes.c_void_p(wsb.data_ptr()),
+                         ws.value, _stream(x.device)), "qtt_fft")
+    y._keep.append(wsb)
+    return y
+
+
+def conv_fft(f: QTT, w: QTT, max_rank_hat: int = 15, eps_hat: float = 0.0, delta_hat: float = 0.0,
+             oversample: int = 8, seed: int = 0) -> QTT:
+    """Step 3 of Algorithm 2 by QTT-FFT: ``QiFFT(QFFT(F) . QFFT(G))`` of the
+    zero-padded data ``f`` (``d`` modes) and the rotated Toeplitz generator
+    ``w`` (``d + 1`` modes, as from :func:`kernel_sinc`); returns the real part
+    of the lower half as a real QTT (dtype of ``f``)."""
+    cap = (ctypes.c_int32 * (f.d + 1))()
+    ws = ctypes.c_size_t()
+    _check(lib().qtt_query_conv_fft(f.d, int(max_rank_hat), int(oversample), cap,
+                                    ctypes.byref(ws)), "qtt_query_conv_fft")
+    y = _make(f.d, f.dtype, list(cap), f.device)
+    wsb = _workspace(ws.value, f.device)
+    fc, wc, yc = f._c(), w._c(), y._c()
+    _check(lib().qtt_conv_fft(ctypes.byref(fc), ctypes.byref(wc), float(eps_hat),
+                              int(max_rank_hat), float(delta_hat), int(oversample),
+                              ctypes.c_uint64(int(seed)), ctypes.byref(yc),
+                              ctypes.c_void_p(wsb.data_ptr()), ws.value, _stream(f.device)),
+           "qtt_conv_fft")
+    y._keep.append(wsb)
+    return y
+
+
+def pipeline_fft(x: torch.Tensor, B: float, eps: float, max_rank: int = 10,
+                 max_rank_hat: int = 15, eps_w: float | None = None, eps_hat: float = 0.0,
+                 delta: float = 0.0, oversample: int = 8, seed: int = 0):
+    """Algorithm 2 with the QTT-FFT route of Step 3: decompose (tolerance, cap
+    ``max_rank``, optional drop-off), build the kernel QTT, convolve by
+    ``QiFFT(QFFT(F) . QFFT(G))`` truncated at ``max_rank_hat`` (and ``delta``
+    as the paper uses the same threshold in both places), reconstruct.
+    Returns ``(out, stages)``."""
+    if eps_w is None:
+        eps_w = eps / 10.0
+    d = int(x.numel()).bit_length() - 1
+    main = torch.cuda.current_stream(x.device)
+    side = _side_stream(x.device)
+    side.wait_stream(main)
+    f = decompose(x, eps, max_rank, delta=delta)
+    with torch.cuda.stream(side):
+        w = kernel_sinc(d, float(B), eps_w, x.dtype, x.device)
+    main.wait_stream(side)
+    w.record_stream(main)
+    y = conv_fft(f, w, max_rank_hat, eps_hat, delta, oversample, seed)
+    out = full(y)
+    return out, dict(f=f, w=w, y=y)
 
 
 def pipeline(x: torch.Tensor, B, eps: float, max_rank: int = 0, eps_w: float | None = None,

@@ -7,15 +7,19 @@ import os
 
 QTT_F32 = 0
 QTT_F64 = 1
+QTT_C128 = 2
 QTT_ROUND_EXACT = 0
 QTT_ROUND_SKETCH_F32 = 1
 QTT_ROUND_SKETCH_BF16 = 2
 QTT_STATUS_NONFINITE = 1
 QTT_STATUS_RANKCAP = 2
+QTT_STATUS_FFT_RANK = 4
 QTT_MAXD = 48
 QTT_MAX_RANK = 64
 QTT_BATCH_MAXD = 18
 QTT_NOALLOC_SCRATCH_MIB = 32
+QTT_FFT_MAX_RANK = 16
+QTT_FFT_MAX_ELL = 32
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 lib_path = os.path.join(HERE, "libqtt.so")
@@ -34,6 +38,7 @@ EXPORTS = [
     "qtt_query_conv_full_backward", "qtt_conv_full_backward",
     "qtt_batch_create", "qtt_batch_destroy", "qtt_batch_run", "qtt_batch_info",
     "qtt_batch_status_offset",
+    "qtt_query_fft", "qtt_fft", "qtt_query_conv_fft", "qtt_conv_fft",
     "qtt_probe_start", "qtt_probe_stop",
 ]
 
@@ -41,7 +46,7 @@ EXPORTS = [
 K_CLASSES = {
     "level_gram": 1, "reduce": 2, "level_eig": 3, "project": 4, "eig_step": 5, "tail": 6,
     "conv": 7, "full_chain": 8, "full_final": 9, "other": 10, "adjoint": 11,
-    "batch": 12, "sketch": 13, "sketch_gemm": 14,
+    "batch": 12, "sketch": 13, "sketch_gemm": 14, "qfft": 15, "qfft_hadamard": 16,
 }
 
 
@@ -152,6 +157,16 @@ def _declare(L):
     L.qtt_batch_info.argtypes = [_VP, ctypes.c_int, ctypes.c_int, _I64P, _I64P, _I32P, _I64P]
     L.qtt_batch_status_offset.restype = ctypes.c_int
     L.qtt_batch_status_offset.argtypes = [_VP, _I64P, _I32P]
+    L.qtt_query_fft.restype = ctypes.c_int
+    L.qtt_query_fft.argtypes = [ctypes.c_int, ctypes.c_int, _I32P, _SZP]
+    L.qtt_fft.restype = ctypes.c_int
+    L.qtt_fft.argtypes = [_TP, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, _TP,
+                          _VP, ctypes.c_size_t, _VP]
+    L.qtt_query_conv_fft.restype = ctypes.c_int
+    L.qtt_query_conv_fft.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _SZP]
+    L.qtt_conv_fft.restype = ctypes.c_int
+    L.qtt_conv_fft.argtypes = [_TP, _TP, ctypes.c_double, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_int, ctypes.c_uint64, _TP, _VP, ctypes.c_size_t, _VP]
     L.qtt_probe_start.restype = ctypes.c_int
     L.qtt_probe_start.argtypes = [ctypes.c_int, ctypes.c_int]
     L.qtt_probe_stop.restype = ctypes.c_int

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libqtt.so")
 ARCH = os.environ.get("QTT_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["qtt_decompose.hip", "qtt_ops.hip", "qtt_adjoint.hip", "qtt_batch.hip", "qtt_sketch.hip",
-           "qtt_modes.hip", "qtt_noalloc.hip", "qtt_abi.hip"]
+           "qtt_modes.hip", "qtt_noalloc.hip", "qtt_fft.hip", "qtt_abi.hip"]
 
 
 def _hipcc() -> str:

@@ -105,6 +105,7 @@ const char* qtt_strerror(int code) {
     case QTT_EHIP: return "HIP runtime error";
     case QTT_STATUS_NONFINITE: return "input held a non-finite value";
     case QTT_STATUS_RANKCAP: return "an eps-rank exceeded the rank capacity";
+    case QTT_STATUS_FFT_RANK: return "a QTT-FFT input rank exceeded QTT_FFT_MAX_RANK";
     case QTT_STATUS_NONFINITE | QTT_STATUS_RANKCAP:
       return "non-finite input; an eps-rank exceeded the rank capacity";
     default: return "unknown code";
@@ -114,7 +115,7 @@ const char* qtt_strerror(int code) {
 const char* qtt_last_hip_error(void) { return g_hip_err; }
 
 int qtt_probe_start(int cls, int max_launches) {
-  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_SKETCH_GEMM || max_launches < 1 || max_launches > (1 << 20))
+  if (cls < QTT_K_LEVEL_GRAM || cls > QTT_K_QFFT_HADAMARD || max_launches < 1 || max_launches > (1 << 20))
     return QTT_EINVAL;
   probe_free();
   g_probe.ev = new hipEvent_t[2 * (size_t)max_launches];

@@ -1,0 +1,204 @@
+"""GPU parity of the QTT-FFT route (Algorithm 2, Step 3): qtt_fft and
+qtt_conv_fft against the oracle's transform, inverse and convolution route on
+the same inputs (the same Philox sketch of the spectra's product): FP64
+complex arithmetic on both sides, ranks equal, represented tensors within a
+bound derived from how far each truncation's kept subspace can move."""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import conv, qfft as Q, tt
+from oracle import pipeline as P
+from synthetic import generators as G
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2301_13339_amd as q  # noqa: E402
+
+U64 = 2.0 ** -53
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                   "table_7_1_qtt_errors.json")))["values"]
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def cut_tolerance(cuts, floor=1e-11):
+    """Parity bound for a run of truncations: a cut keeping sigma_1..sigma_r
+    moves its kept subspace by about u sigma_1 / (sigma_r - sigma_{r+1}) under
+    a rounding-level perturbation, which changes the result by about that
+    angle times sigma_r, relative at most sigma_r / sigma_1; 100x the sum over
+    the cuts, and ``floor`` at least."""
+    tot = 0.0
+    for s1, sr, sr1 in cuts:
+        if s1 <= 0:
+            continue
+        gap = sr - sr1
+        move = sr / s1 if gap <= 0 else min(sr / s1, U64 * sr / gap)
+        tot += move
+    return max(floor, 100.0 * tot)
+
+
+def random_ctt(D, r, seed):
+    rng = np.random.default_rng(seed)
+    rk = [1] + [min(r, 2 ** k, 2 ** (D - k)) for k in range(1, D)] + [1]
+    return [rng.standard_normal((rk[k], 2, rk[k + 1])) +
+            1j * rng.standard_normal((rk[k], 2, rk[k + 1])) for k in range(D)]
+
+
+@pytest.mark.parametrize("D", [1, 2, 5, 8])
+def test_qfft_exact_equals_oracle_and_numpy(D):
+    """Ranks within the engine's capacity: no truncation, the DFT itself."""
+    print("case: qfft exact D", D, flush=True)
+    x = random_ctt(D, 4, D)
+    t = q.from_cores(x, torch.complex128)
+    y = q.qfft(t)
+    got = Q.full(y.core_list())
+    want = np.fft.fft(Q.full(x))[Q.bit_reverse(D)]
+    assert rel(got, want) <= 1e-12
+    assert y.ranks_host() == Q.ranks(Q.qfft(x))
+    z = q.qfft(y, inverse=True)
+    assert rel(Q.full(z.core_list()), Q.full(x)) <= 1e-12
+
+
+@pytest.mark.parametrize("D,R,eps,delta", [(12, 6, 0.0, 0.0), (14, 16, 1e-6, 0.0),
+                                           (13, 10, 0.0, 0.05), (20, 8, 0.0, 0.0)])
+def test_qfft_truncated_matches_oracle(D, R, eps, delta):
+    print("case: qfft truncated", D, R, eps, delta, flush=True)
+    x = random_ctt(D, 8, 100 + D)
+    ref, info = Q.qfft(x, -1, eps, R, delta, return_info=True)
+    t = q.from_cores(x, torch.complex128)
+    y = q.qfft(t, False, eps, R, delta)
+    torch.cuda.synchronize()
+    if info["margin"] >= 1e-6 and info["delta_margin"] >= 1e-6:
+        assert y.ranks_host() == Q.ranks(ref)
+    tol = cut_tolerance(info["cuts"])
+    if D <= 14:
+        err = rel(Q.full(y.core_list()), Q.full(ref))
+    else:
+        # sampled entries of the 2^D-entry tensors
+        idx = np.random.default_rng(D).integers(0, 1 << D, 512)
+        gc, rc = y.core_list(), ref
+        err = rel([_entry(gc, i) for i in idx], [_entry(rc, i) for i in idx])
+    print(f"D {D} R {R}: rel {err:.2e} (tolerance {tol:.1e}) ranks {y.ranks_host()}", flush=True)
+    assert err <= tol
+
+
+def _entry(cores, i):
+    row = np.ones((1, 1), dtype=complex)
+    for k, G_ in enumerate(cores):
+        row = row @ G_[:, (i >> k) & 1, :]
+    return row[0, 0]
+
+
+def test_qifft_of_truncated_spectrum_matches_oracle():
+    D, R = 12, 6
+    X = random_ctt(D, 8, 7)
+    ref, info = Q.qifft(X, 0.0, R, 0.0, return_info=True)
+    y = q.qfft(q.from_cores(X, torch.complex128), True, 0.0, R)
+    assert y.ranks_host() == Q.ranks(ref)
+    assert rel(Q.full(y.core_list()), Q.full(ref)) <= cut_tolerance(info["cuts"])
+
+
+@pytest.mark.parametrize("d,B", [(4, 3.0), (6, 10.0), (7, 30.0)])
+def test_conv_fft_exact_equals_direct_convolution(d, B):
+    """d + 1 <= 8 modes: every rank (at most 16) fits under the cap, the
+    sketch width covers the product's ranks, and the route is the exact
+    discrete convolution (2.2)."""
+    print("case: conv_fft exact", d, flush=True)
+    rng = np.random.default_rng(d)
+    f = rng.standard_normal(1 << d)
+    w = conv.toeplitz_generator(d, B)
+    F = q.from_cores(tt.tt_svd(f, 0.0))
+    W = q.from_cores(tt.tt_svd(w, 0.0))
+    y = q.conv_fft(F, W, max_rank_hat=16, oversample=8, seed=1)
+    out = q.full(y).cpu().numpy()
+    assert rel(out, conv.toeplitz_apply(f, w)) <= 1e-11
+    assert int(y.status.cpu()[0]) == 0
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_conv_fft_matches_oracle_route(dt):
+    """d = 12, R^ = 6, p = 4: the same Philox sketch on both sides."""
+    print("case: conv_fft vs oracle", dt, flush=True)
+    d, B = 12, 200.0
+    noisy, _ = G.gaussian_bumps_1d(d, seed=1)
+    Fc = tt.tt_svd(noisy, 1e-3, 10)
+    Wc = tt.tt_svd(conv.toeplitz_generator(d, B), 1e-4, 0)
+    ref, info = Q.conv_fft(Fc, Wc, 0.0, 6, 0.0, oversample=4, seed=3, return_info=True)
+    y = q.conv_fft(q.from_cores(Fc, dt), q.from_cores(Wc, dt), 6, 0.0, 0.0, 4, 3)
+    out = q.full(y).double().cpu().numpy()
+    want = Q.full(ref).real
+    tol = cut_tolerance(info["cuts"]) if dt == torch.float64 else 1e-5
+    err = rel(out, want)
+    print(f"conv_fft {dt}: rel {err:.2e} (tolerance {tol:.1e}) ranks {y.ranks_host()}", flush=True)
+    assert y.ranks_host()[1:-1] == [2 * r for r in Q.ranks(ref)[1:-1]]
+    assert err <= tol
+
+
+@pytest.mark.parametrize("name,gen", [("example1", G.paper_example1),
+                                      ("example2", G.paper_example2)])
+def test_paper_example_through_the_qfft_route(name, gen):
+    """Examples 1 and 2 at K = 20 with the paper's parameters (R_max = 10,
+    R^_max = 15): the GPU route against the oracle route, and the error (7.1)
+    to the noise-free convolution within 10 % of Table 7.1's QTT_0."""
+    print("case: paper example via qfft", name, flush=True)
+    K = 20
+    noisy, clean, _, _ = gen(K, 0)
+    x = np.zeros(1 << K)
+    c = np.zeros(1 << K)
+    x[: noisy.size] = noisy
+    c[: clean.size] = clean
+    B = (1 << K) / float(GOLD[name]["resolution_in_dx"])
+    out, st = q.pipeline_fft(torch.tensor(x, device="cuda"), B, 1e-4, 10, 15, seed=1)
+    out = out.cpu().numpy()
+    F = tt.tt_svd(x, 1e-4, 10)
+    W = tt.tt_svd(conv.toeplitz_generator(K, B), 1e-5, 0)
+    ref, info = Q.conv_fft(F, W, 0.0, 15, 0.0, oversample=8, seed=1, return_info=True)
+    want = Q.full(ref).real
+    assert st["f"].ranks_host() == tt.tt_ranks(F)
+    err = rel(out, want)
+    tol = cut_tolerance(info["cuts"], floor=1e-9)
+    e2 = P.relative_error(out, P.clean_reference_1d(c, B))
+    print(f"{name}: rel to the oracle route {err:.2e} (tolerance {tol:.1e}), E2 {e2:.5f} "
+          f"(Table 7.1 {GOLD[name]['qtt0']})", flush=True)
+    assert err <= tol
+    assert abs(e2 - GOLD[name]["qtt0"]) <= 0.1 * GOLD[name]["qtt0"]
+
+
+def test_fft_arguments_rejected():
+    x = q.from_cores(random_ctt(6, 4, 1), torch.complex128)
+    with pytest.raises(q.QttError):
+        q.qfft(x, max_rank=17)
+    f = q.from_cores(tt.tt_svd(np.random.default_rng(0).standard_normal(64), 0.0))
+    w = q.from_cores(tt.tt_svd(conv.toeplitz_generator(6, 5.0), 0.0))
+    with pytest.raises(q.QttError):
+        q.conv_fft(f, w, max_rank_hat=0)
+    with pytest.raises(q.QttError):
+        q.conv_fft(f, w, max_rank_hat=16, oversample=17)   # ell > 32
+    with pytest.raises(q.QttError):
+        q.conv_fft(f, f, max_rank_hat=8)                   # generator needs d + 1 modes
+
+
+def test_conv_fft_flags_input_ranks_above_the_engine_limit():
+    """A data tensor whose ranks exceed QTT_FFT_MAX_RANK (a noise vector
+    decomposed with the cap at 32): the route reports QTT_STATUS_FFT_RANK and
+    returns zero instead of reading past its slots."""
+    d = 12
+    f = q.decompose(torch.tensor(np.random.default_rng(1).standard_normal(1 << d),
+                                 device="cuda"), 0.0, 32)
+    assert max(f.ranks_host()) > q.QTT_FFT_MAX_RANK
+    w = q.kernel_sinc(d, 300.0, 1e-5)
+    y = q.conv_fft(f, w, 8)
+    assert y.status_host() & 4
+    assert float(q.full(y).abs().max()) == 0.0
