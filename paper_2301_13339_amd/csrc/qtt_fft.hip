@@ -50,7 +50,7 @@ constexpr int kB = 2 * kR;            // bond inside a stage (doubled)
 constexpr int kSlot = kB * 2 * kB;    // complex entries per core slot
 constexpr int kNT = 256;
 constexpr int kMaxSweeps = 40;        // Jacobi sweeps (convergence takes 6..10)
-constexpr double kJacobiTol = 1e-15;  // |x^H y| <= tol ||x|| ||y|| ends a pair
+constexpr double kJacobiTol = 0x1p-48; // |x^H y| <= tol ||x|| ||y|| ends a pair (32 u)
 constexpr int kMaxD = 31;             // modes of a transform (data d <= 30, plus padding)
 
 // ---------------------------------------------------------------- complex
@@ -240,22 +240,43 @@ __device__ __forceinline__ void house_qr(cplx a[8], int M, int N, cplx* sV, lds_
 // y' = s e x + c y, with t = s / c the smaller root of
 // t^2 + 2 zeta t - 1 = 0, zeta = (|y|^2 - |x|^2) / (2 |g|), which makes
 // x'^H y' = 0.
-__device__ __forceinline__ void jacobi(cplx* sC, cplx* sJ, int M, int N, lds_ptr<int> sFlag) {
+__device__ __forceinline__ void jacobi(cplx* sC, cplx* sJ, int M, int N, lds_ptr<int> sFlag,
+                                       lds_ptr<double> s2, lds_ptr<double> scal) {
   const int t = threadIdx.x, g = t >> 4, h = t & 15;
   for (int i = t; i < kB * kB; i += kNT) {
     const int row = i % kB, col = i / kB;
     sJ[i] = (row == col && col < N) ? mk(1.0, 0.0) : cz();
   }
   if (t < 3) sFlag[t] = 0;
+  // ||C||_F^2 (invariant under the rotations): a pair with a column below
+  // 2^-52 ||C||_F is left alone, since rotating rounding-level columns
+  // against each other never meets the relative test
+  for (int c = g; c < N; c += 16) {
+    double v = 0.0;
+    if (h < M) v += cabs2(sC[c * kB + h]);
+    if (h + 16 < M) v += cabs2(sC[c * kB + h + 16]);
+    v = sum16(v);
+    if (h == 0) s2[c] = v;
+  }
   __syncthreads();
+  if (t == 0) {
+    double f2 = 0.0;
+    for (int c = 0; c < N; ++c) f2 += s2[c];
+    scal[1] = f2 * 0x1p-104;
+  }
+  __syncthreads();
+  const double tiny2 = scal[1];
   const int P = N / 2;
   const double tol2 = kJacobiTol * kJacobiTol;
   for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
     if (t == 0) sFlag[(sweep + 1) % 3] = 0;
     for (int rd = 0; rd < N - 1; ++rd) {
       if (g < P) {
-        const int a = (g == 0) ? 0 : 1 + (g - 1 + rd) % (N - 1);
-        const int b = 1 + (N - 2 - g + rd) % (N - 1);
+        int ia = g - 1 + rd, ib = N - 2 - g + rd;  // both below 2 (N - 1)
+        if (ia >= N - 1) ia -= N - 1;
+        if (ib >= N - 1) ib -= N - 1;
+        const int a = (g == 0) ? 0 : 1 + ia;
+        const int b = 1 + ib;
         cplx x0 = cz(), x1 = cz(), y0 = cz(), y1 = cz();
         if (h < M) {
           x0 = sC[a * kB + h];
@@ -269,12 +290,23 @@ __device__ __forceinline__ void jacobi(cplx* sC, cplx* sJ, int M, int N, lds_ptr
         const double be = sum16(cabs2(y0) + cabs2(y1));
         const cplx gm = csum16(ccfma(x0, y0, ccfma(x1, y1, cz())));
         const double g2 = cabs2(gm);
-        if (g2 > 0.0 && g2 > tol2 * al * be) {
-          const double ga = sqrt(g2);
-          const cplx e = cscale(gm, 1.0 / ga);
-          const double zeta = (be - al) / (2.0 * ga);
-          const double tt = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + tt * tt);
+        if (g2 > 0.0 && g2 > tol2 * al * be && al > tiny2 && be > tiny2) {
+          // Newton-refined hardware estimates instead of divisions and
+          // square roots: the rotation stays exactly unitary to rounding
+          // (cs and sn come from one t), only t's last bits differ
+          const double ig = rsq_acc(g2);
+          const cplx e = cscale(gm, ig);
+          const double zeta = 0.5 * (be - al) * ig;
+          const double az = fabs(zeta);
+          double tt;
+          if (az < 1e100) {
+            const double z2 = fma(zeta, zeta, 1.0);
+            tt = rcp_acc(az + z2 * rsq_acc(z2));
+          } else {
+            tt = 0.5 / az;
+          }
+          if (zeta < 0.0) tt = -tt;
+          const double cs = rsq_acc(fma(tt, tt, 1.0));
           const double sn = cs * tt;
           const cplx se = cscale(e, sn), sec = cconj(se);
           if (h < M) {
@@ -374,7 +406,7 @@ __device__ __forceinline__ void svd_sweep(const Task& T, int m, int M, int rr, S
   int cur = 0;
   for (int p = m; p >= 2; --p) {
     const int N = 2 * rr;
-    jacobi(S.C[cur], S.J, M, N, lds(S.flag));
+    jacobi(S.C[cur], S.J, M, N, lds(S.flag), lds(S.s2), lds(S.scal));
     sort_columns(S.C[cur], M, N, lds(S.s2), lds(S.s2s), lds(S.perm));
     if (t == 0) {
       if (p == m) {
