@@ -42,6 +42,10 @@ WORKLOADS = {
     "image4096": dict(image=12, B=1000.0, max_rank=32, seed=3, eps=1e-3, ell=64),
     # K = 8 modes of size 10, uniform entries: TT-SVD against max-rank TT-RSVD
     "modes_k8_m10": dict(modes_K=8, M=10, max_rank=10, oversample=10, seed=8),
+    # the paper's own route (Algorithm 2 with QTT-FFT in Step 3) on Example 1 at
+    # K = 20: max-rank TT-SVD R_max = 10, QFFT/QiFFT truncated at R^_max = 15
+    "qfft_example1_k20": dict(qfft_K=20, max_rank=10, max_rank_hat=15, eps=1e-4,
+                              oversample=8, seed=1),
 }
 
 
@@ -85,6 +89,8 @@ def main():
         return bench_image(args, wl)
     if "modes_K" in wl:
         return bench_modes(args, wl)
+    if "qfft_K" in wl:
+        return bench_qfft(args, wl)
     d, B, R = wl["d"], wl["B"], wl["max_rank"]
     n = 1 << d
     tdt = torch.float64 if args.dtype == "f64" else torch.float32
@@ -587,6 +593,140 @@ def image_roofline(cls, ms_launches, D, zr, fr, ell):
                 "work_per_launch": f"{w:.4g} flops (9 E^3 per eigensolve, 4 m ell^2 per QR)"}
     return {"bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None,
             **common}
+
+
+def qfft_work(D, R):
+    """Floating-point work of one QTT-FFT (complex FP64, 8 real flops per
+    complex multiply-add): at stage s (m = D + 1 - s) the Householder QR of
+    each doubled core 1..m-1 (2 k x 2 r, about 8 (2k)(2r)^2 complex flops) and
+    one Jacobi SVD of each core m..2 (k x 2r; about 8 sweeps of (2r)^2 / 2
+    pair rotations of 2k + 2r entries, 8 real flops each).  A model of the
+    work the method needs, not a count of executed instructions."""
+    fl = 0.0
+    r = min(R, 16)
+    for s in range(1, D + 1):
+        m = D + 1 - s
+        if m < 2:
+            continue
+        k = 1
+        for p in range(1, m):
+            rr = min(r, 2 ** p, 2 ** (D - p))
+            M, N = 2 * k, 2 * rr
+            fl += 8.0 * M * N * N
+            k = min(M, N)
+        for p in range(m, 1, -1):
+            rr = min(r, 2 ** p, 2 ** (D - p))
+            M, N = min(2 * r, 2 ** (p - 1)), 2 * rr
+            fl += 8 * (N * N / 2) * (M + N) * 8.0
+    return fl
+
+
+def bench_qfft(args, wl):
+    """Algorithm 2 with Step 3 by QTT-FFT (the paper's route) on Example 1 at
+    K = 20: decompose (max-rank TT-SVD), kernel QTT, QFFT of both padded
+    tensors, randomised rounding of their product, QiFFT, Full."""
+    import numpy as np
+    import torch
+
+    import paper_2301_13339_amd as q
+    from synthetic import generators as G
+
+    K, R, Rh, eps = wl["qfft_K"], wl["max_rank"], wl["max_rank_hat"], wl["eps"]
+    noisy, clean, _, _ = G.paper_example1(K, 0)
+    xn = np.zeros(1 << K)
+    xn[: noisy.size] = noisy
+    cn = np.zeros(1 << K)
+    cn[: clean.size] = clean
+    B = (1 << K) / 4.0
+    n = 1 << K
+    x = torch.tensor(xn, device="cuda")
+
+    def step():
+        return q.pipeline_fft(x, B, eps, R, Rh, oversample=wl["oversample"], seed=wl["seed"])
+
+    for _ in range(max(args.warmup, 1)):
+        out, st = step()
+    torch.cuda.synchronize()
+    per = {}
+    for c in ("qfft", "qfft_hadamard", "level_gram", "reduce", "level_eig", "project",
+              "eig_step", "tail", "full_chain", "full_final", "other"):
+        with q.probe(c) as p:
+            step()
+            torch.cuda.synchronize()
+        per[c] = (p.ms, p.launches)
+    steps = max(1, min(args.steps, 10))
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record()
+        out, st = step()
+        e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / steps
+    spread = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    from oracle import pipeline as P
+    e2 = P.relative_error(out.cpu().numpy(), P.clean_reference_1d(cn, B))
+    D = K + 1
+    fl = qfft_work(D, Rh)
+    ms_q, nq = per["qfft"]
+    res = {
+        "metric": "samples/s for QTT decompose+conv+reconstruct, conv by QTT-FFT (Algorithm 2)",
+        "value": n * steps / (t1 - t0),
+        "unit": "samples/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"qfft_example1_k20: the paper's Example 1 (Gaussian-windowed "
+                               f"sines, noise std 0.02, N = 2^{K - 1} - 1 samples padded to "
+                               f"2^{K}), kernel resolution 4 dx, R_max = {R}, R^_max = {Rh}, "
+                               f"complex FP64 transforms", "K": K, "samples": n},
+        "step_ms_p10_p50_p90": [spread[int(0.1 * (len(spread) - 1))], spread[len(spread) // 2],
+                                spread[int(0.9 * (len(spread) - 1))]],
+        "kernels_ms_per_step": {c: round(v[0], 3) for c, v in per.items() if v[1]},
+        # the transforms are sequential chains of small QR/SVD steps run by
+        # one workgroup each (two for the forward pair): the roofline is the
+        # FP64 rate, of which one workgroup can use at most 1/256
+        "roofline": {"bound": "alu", "kernel": "k_qfft",
+                     "achieved": 3 * fl / (ms_q * 1e-3) / 1e12 if ms_q > 0 else None,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (3 * fl / (ms_q * 1e-3) / 1e12) / FP64_PEAK_TFLOPS if ms_q > 0
+                     else None,
+                     "traffic": None,
+                     "work": f"{fl:.3e} flops per transform (model in bench.py qfft_work), "
+                             f"3 transforms per step in {nq} launches"},
+        "e2_vs_clean_convolution": e2,
+        "paper_context": {"table_7_1_e2_qtt0": 0.0028, "table_7_2_seconds_k20_qtt0": 0.653,
+                          "hardware": "not stated in the paper"},
+    }
+    if args.cpu_seconds > 0:
+        from oracle import conv, qfft as QO, tt
+        from threadpoolctl import threadpool_info
+        threads = max((i.get("num_threads", 1) for i in threadpool_info()), default=1)
+        ts = []
+        t_end = time.perf_counter() + args.cpu_seconds
+        while not ts or (time.perf_counter() < t_end and len(ts) < 5):
+            c0 = time.perf_counter()
+            F = tt.tt_svd(xn, eps, R)
+            W = tt.tt_svd(conv.toeplitz_generator(K, B), eps / 10.0)
+            QO.full(QO.conv_fft(F, W, 0.0, Rh, 0.0, wl["oversample"], wl["seed"])).real
+            ts.append(time.perf_counter() - c0)
+        tmed = sorted(ts)[len(ts) // 2]
+        res["cpu_baseline"] = {"value": n / tmed, "unit": "samples/s", "cores": threads,
+                               "kind": "oracle", "cpu_model": cpu_model(),
+                               "sample": f"the oracle's route (TT-SVD, kernel TT-SVD, QFFT x2, "
+                                         f"randomised Hadamard rounding, QiFFT, Full) on the "
+                                         f"same input, median of {len(ts)} runs, "
+                                         f"{tmed:.2f} s each"}
+    print(json.dumps(res), flush=True)
 
 
 def cpu_model() -> str:
