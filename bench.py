@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the timed steps, run one plain device copy of this many MiB "
                          "(a known-size kernel for scaling hardware byte counters)")
+    ap.add_argument("--round-compare", action="store_true",
+                    help="also time TT-rounding of the convolution output in QTT format "
+                         "(QR and SVD sweeps of its cores by torch.linalg / rocSOLVER) "
+                         "against the library's rounding (Full, then the TT-SVD sweep)")
     ap.add_argument("--breakdown", action="store_true",
                     help="also report GPU time per step of every kernel class")
     return ap.parse_args()
@@ -184,9 +188,62 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         res["calib_copy_bytes"] = nb
+    if args.round_compare:
+        res["round_in_qtt_format"] = round_compare(q, st["y"], args.eps)
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(noisy, B, args.eps, R, n, args.cpu_seconds)
     print(json.dumps(res), flush=True)
+
+
+def round_compare(q, y, eps):
+    """TT-rounding of the convolution output y (ranks 2 rho r) done in QTT
+    format -- right-to-left LQ of every core, then left-to-right truncated
+    SVDs with tau = eps ||y|| / sqrt(d-1) -- with the vendor's dense QR and SVD
+    (torch.linalg on rocSOLVER), timed against the library's rounding of the
+    same tensor (Full of y, then the TT-SVD sweep).  A measurement of the
+    alternative, not part of the product path."""
+    import torch
+    cores = [torch.tensor(c, device="cuda") for c in y.core_list()]
+    D = len(cores)
+
+    def qtt_format_round(G):
+        G = [g.clone() for g in G]
+        for k in range(D - 1, 0, -1):
+            r0, _, r1 = G[k].shape
+            Q, Rm = torch.linalg.qr(G[k].reshape(r0, 2 * r1).T)
+            G[k] = Q.T.reshape(Q.shape[1], 2, r1)
+            G[k - 1] = torch.einsum("aib,bc->aic", G[k - 1], Rm.T)
+        tau = eps * torch.linalg.norm(G[0]) / math.sqrt(D - 1)
+        for k in range(D - 1):
+            r0, _, r1 = G[k].shape
+            U, sv, Vh = torch.linalg.svd(G[k].reshape(2 * r0, r1), full_matrices=False)
+            tail = torch.flip(torch.cumsum(torch.flip(sv * sv, [0]), 0), [0])
+            ok = torch.nonzero(tail <= tau * tau)
+            r = max(int(ok[0]) if ok.numel() else sv.numel(), 1)
+            G[k] = U[:, :r].reshape(r0, 2, r)
+            G[k + 1] = torch.einsum("ab,bjc->ajc", sv[:r, None] * Vh[:r], G[k + 1])
+        return G
+
+    def med(fn, reps):
+        ts = []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fn()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - t0) * 1e3)
+        return sorted(ts)[len(ts) // 2], r
+
+    med(lambda: q.round(y, eps, 0), 2)
+    t_lib, z = med(lambda: q.round(y, eps, 0), 5)
+    med(lambda: qtt_format_round(cores), 1)
+    t_qf, Z = med(lambda: qtt_format_round(cores), 3)
+    yr = y.ranks_host()
+    qr_flops = sum(2 * (2 * yr[k + 1]) * yr[k] ** 2 - 2 * yr[k] ** 3 / 3 for k in range(1, D))
+    return {"y_ranks": yr, "library_ms": t_lib, "qtt_format_ms": t_qf,
+            "ranks_equal": z.ranks_host() == [1] + [g.shape[2] for g in Z],
+            "qr_sweep_flops": qr_flops,
+            "qr_sweep_ms_at_fp64_peak": qr_flops / (FP64_PEAK_TFLOPS * 1e12) * 1e3}
 
 
 K_LEVEL = 6          # steps taken from one 64 x 64 data Gram
@@ -211,11 +268,16 @@ def eig_step_sizes(D, R, ranks):
     return [2 * ranks[j - 1] for j in range(K_LEVEL + 1, k)]
 
 
-def source_digest():
+def source_digest(source=None):
+    """Digest of the kernel sources a counter summary was taken on: the .hip
+    file that defines the kernel (all of them when ``source`` is None) and
+    every shared header."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2301_13339_amd", "csrc")
     for fn in sorted(os.listdir(csrc)):
+        if fn.endswith(".hip") and source is not None and fn != source:
+            continue
         with open(os.path.join(csrc, fn), "rb") as f:
             h.update(fn.encode())
             h.update(f.read())
@@ -224,7 +286,7 @@ def source_digest():
 
 def measured_traffic(cls, workload):
     """HBM bytes per launch from the committed counter summary, if it was taken
-    on the current kernel sources (else None)."""
+    on the current sources of the kernel (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(path) as f:
@@ -232,7 +294,7 @@ def measured_traffic(cls, workload):
     except (OSError, ValueError):
         return None
     ent = tab.get(f"{workload}:{cls}")
-    if not ent or ent.get("source_digest") != source_digest():
+    if not ent or ent.get("source_digest") != source_digest(ent.get("source")):
         return None
     return ent.get("bytes_per_launch")
 
