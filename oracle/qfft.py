@@ -112,17 +112,22 @@ def norm(cores) -> float:
 
 
 # -------------------------------------------------------------- the stage
-def fft_stage(cores, s: int, sign: int):
-    """Stage ``s`` (1-based) of the decimation-in-frequency transform, exact."""
+def fft_stage(cores, s: int, sign: int, lo: int = 0, hi: int | None = None):
+    """Stage ``s`` (1-based) of the decimation-in-frequency transform of the
+    digits held by cores ``lo..hi-1`` (0-based; the whole tensor by default),
+    exact.  The summed digit sits at core ``m`` (1-based, ``m = lo + Dax + 1 -
+    s``); cores ``lo+1..m-1`` (1-based) take the doubled bonds, the first of
+    them keeps its left bond."""
     D = len(cores)
-    m = D + 1 - s
-    out = []
-    for p in range(1, m):
+    hi = D if hi is None else hi
+    m = lo + (hi - lo) + 1 - s
+    out = [c.copy() for c in cores[:lo]]
+    for p in range(lo + 1, m):
         G = cores[p - 1]
         r0, _, r1 = G.shape
         G1 = G.copy()
         G1[:, 1, :] *= np.exp(sign * 1j * math.pi * 2.0 ** (p - m))
-        if p == 1:
+        if p == lo + 1:
             H = np.concatenate([G, G1], axis=2)
         else:
             H = np.zeros((2 * r0, 2, 2 * r1), dtype=np.complex128)
@@ -133,7 +138,7 @@ def fft_stage(cores, s: int, sign: int):
     r0, _, r1 = G.shape
     even = G[:, 0, :] + G[:, 1, :]
     odd = G[:, 0, :] - G[:, 1, :]
-    if m == 1:
+    if m == lo + 1:
         H = np.stack([even, odd], axis=1)
     else:
         H = np.zeros((2 * r0, 2, r1), dtype=np.complex128)
@@ -173,8 +178,11 @@ def _new_info():
             "ranks": []}
 
 
-def round_doubled(cores, m: int, eps: float, max_rank: int, delta: float, info):
-    """Rounding of bonds ``1..m-1`` after a stage (the reading above).
+def round_doubled(cores, m: int, eps: float, max_rank: int, delta: float, info, lo: int = 0):
+    """Rounding of the bonds a stage doubled (the reading above): QR sweep over
+    cores ``1..m-1`` (1-based, from the first core of the tensor), then
+    truncated SVDs of cores ``m`` down to ``lo+2``, which truncate bonds
+    ``m-1`` down to ``lo+1``.
 
     Cores right of ``m`` must be right-orthonormal.  Returns the rounded
     cores and the Frobenius norm of the discarded part (the square root of
@@ -190,7 +198,7 @@ def round_doubled(cores, m: int, eps: float, max_rank: int, delta: float, info):
     nrm = float(np.linalg.norm(G[m - 1]))
     tau = eps * nrm / math.sqrt(D - 1) if D > 1 else 0.0
     disc = 0.0
-    for p in range(m - 1, 0, -1):
+    for p in range(m - 1, lo, -1):
         r0, _, r1 = G[p].shape
         U, s, Vh = np.linalg.svd(G[p].reshape(r0, 2 * r1), full_matrices=False)
         r = _rank(s, tau, max_rank, delta, info)
@@ -200,32 +208,60 @@ def round_doubled(cores, m: int, eps: float, max_rank: int, delta: float, info):
     return G, math.sqrt(disc)
 
 
+def right_orthonormalise(cores, p: int):
+    """Core ``p`` (0-based) made right-orthonormal by an LQ factorisation, the
+    L factor absorbed into core ``p-1``."""
+    G = list(cores)
+    r0, _, r1 = G[p].shape
+    Q, R = np.linalg.qr(G[p].reshape(r0, 2 * r1).conj().T)   # C^H = Q R, C = R^H Q^H
+    G[p] = Q.conj().T.reshape(Q.shape[1], 2, r1)
+    G[p - 1] = np.einsum("aib,bc->aic", G[p - 1], R.conj().T)
+    return G
+
+
 def qfft(cores, sign: int = -1, eps: float = 0.0, max_rank: int = 0, delta: float = 0.0,
-         return_info: bool = False):
+         return_info: bool = False, blocks=None):
     """QTT-FFT: the DFT ``X(b) = sum_a x(a) exp(sign 2 pi i a b / 2^D)`` of the
     tensor, each stage followed by the rounding of the doubled bonds; the
     result is in bit-reversed mode order.  ``eps = 0``, ``max_rank = 0`` and
-    ``delta = 0`` give the exact transform (ranks up to the full ones)."""
+    ``delta = 0`` give the exact transform (ranks up to the full ones).
+
+    ``blocks`` (list of 0-based ``(lo, hi)`` core ranges, one per axis, in
+    mode order) gives the multi-dimensional DFT: each block is transformed
+    on its own digits, bit-reversed inside the block.  Blocks run right to
+    left; before a block, the first core of the block to its right is made
+    right-orthonormal (it carried the last butterfly), so that the rounding
+    of every stage sees right-orthonormal cores right of its centre."""
     G = as_complex(cores)
     D = len(G)
+    blocks = [(0, D)] if blocks is None else list(blocks)
     info = _new_info()
-    for s in range(1, D + 1):
-        m = D + 1 - s
-        G = fft_stage(G, s, sign)
-        if m > 1:
-            G, e = round_doubled(G, m, eps, max_rank, delta, info)
-        else:
-            e = 0.0
-        info["discarded"].append(e)
-        info["ranks"].append(ranks(G))
+    for bi in range(len(blocks) - 1, -1, -1):
+        lo, hi = blocks[bi]
+        if bi < len(blocks) - 1:
+            G = right_orthonormalise(G, blocks[bi + 1][0])
+        for s in range(1, hi - lo + 1):
+            m = lo + (hi - lo) + 1 - s
+            G = fft_stage(G, s, sign, lo, hi)
+            if m > lo + 1:
+                G, e = round_doubled(G, m, eps, max_rank, delta, info, lo)
+            else:
+                e = 0.0
+            info["discarded"].append(e)
+            info["ranks"].append(ranks(G))
     return (G, info) if return_info else G
 
 
 def qifft(cores, eps: float = 0.0, max_rank: int = 0, delta: float = 0.0,
-          return_info: bool = False):
-    """QTT-iFFT of a spectrum in bit-reversed mode order; natural-order result
-    ``x(a) = 2^-D sum_b X(b) exp(+2 pi i a b / 2^D)``."""
-    G, info = qfft(reverse(as_complex(cores)), +1, eps, max_rank, delta, True)
+          return_info: bool = False, blocks=None):
+    """QTT-iFFT of a spectrum in bit-reversed mode order (per block); natural
+    order result ``x(a) = 2^-D sum_b X(b) exp(+2 pi i a b / 2^D)``.  Reversing
+    the whole tensor restores the natural digit order inside every block and
+    mirrors the blocks, so the forward stages with the +1 exponent run on the
+    mirrored blocks and the result is reversed back."""
+    D = len(cores)
+    mb = None if blocks is None else [(D - hi, D - lo) for lo, hi in reversed(blocks)]
+    G, info = qfft(reverse(as_complex(cores)), +1, eps, max_rank, delta, True, mb)
     G = reverse(G)
     G[0] = G[0] * 2.0 ** -len(G)
     return (G, info) if return_info else G
@@ -379,3 +415,42 @@ def realify(cores):
             bot = np.concatenate([Im, Re], axis=2)
             out.append(np.concatenate([top, bot], axis=0))
     return out
+
+
+def pad_data_2d(f_cores, dx: int):
+    """A row-major image's TT (column digits first, ``dx`` of them) with one
+    zero-padding mode after the column digits (identity core, slice 1 zero)
+    and one after the row digits."""
+    G = as_complex(f_cores)
+    r = G[dx].shape[0]
+    mid = np.zeros((r, 2, r), dtype=np.complex128)
+    mid[:, 0, :] = np.eye(r)
+    return G[:dx] + [mid] + G[dx:] + [np.array([1.0, 0.0], dtype=np.complex128).reshape(1, 2, 1)]
+
+
+def conv_fft_2d(f_cores, dx: int, wx_cores, wy_cores, eps: float = 0.0, max_rank: int = 0,
+                delta: float = 0.0, oversample: int = 8, seed: int = 0, return_info: bool = False):
+    """Step 3 of Algorithm 2 for a row-major image with the separable kernel:
+    both axes zero-padded by one mode, the kernel the concatenated TTs of the
+    two rotated Toeplitz generators (``dx + 1`` column digits, then ``dy + 1``
+    row digits), the two-dimensional QFFT (one block per axis), the rounded
+    Hadamard product, the QiFFT, and the slice with both padding digits 0."""
+    dy = len(f_cores) - dx
+    if len(wx_cores) != dx + 1 or len(wy_cores) != dy + 1:
+        raise ValueError("the generators need dx + 1 and dy + 1 modes")
+    blocks = [(0, dx + 1), (dx + 1, dx + dy + 2)]
+    F = pad_data_2d(f_cores, dx)
+    Gk = rotate_generator(wx_cores) + rotate_generator(wy_cores)
+    Fh, i1 = qfft(F, -1, eps, max_rank, delta, True, blocks)
+    Gh, i2 = qfft(Gk, -1, eps, max_rank, delta, True, blocks)
+    Hh, i3 = hadamard_round(Fh, Gh, eps, max_rank, delta, oversample, seed, True)
+    C, i4 = qifft(Hh, eps, max_rank, delta, True, blocks)
+    # the padding digits at positions dx and dx + dy + 1 set to 0
+    y = list(C[:dx])
+    y[-1] = np.einsum("aib,bc->aic", y[-1], C[dx][:, 0, :])
+    y = y + lower_half(C[dx + 1:])
+    info = {"qfft_f": i1, "qfft_g": i2, "hadamard": i3, "qifft": i4}
+    for key in ("margin", "delta_margin"):
+        info[key] = min(i[key] for i in (i1, i2, i3, i4))
+    info["cuts"] = [c for i in (i1, i2, i3, i4) for c in i["cuts"]]
+    return (y, info) if return_info else y
