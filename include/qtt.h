@@ -496,25 +496,30 @@ int qtt_fft(const qtt_tensor* x, int inverse, double eps, int max_rank, double d
             qtt_tensor* y, void* ws, size_t ws_bytes, void* stream);
 
 /*
- * Sizes for qtt_conv_fft: y_cap[0..d] = 2 min(2^k, 2^(d+1-k), max_rank_hat)
- * inside (1 at the ends) and the workspace size.  Requires
- * 1 <= max_rank_hat <= QTT_FFT_MAX_RANK and max_rank_hat + oversample <=
- * QTT_FFT_MAX_ELL.
+ * Sizes for qtt_conv_fft (arguments as there): y_cap[0..d] = 2 R^ bounded
+ * by the bond's full rank, 1 at the ends, and the workspace size.  Requires
+ * 1 <= max_rank_hat <= QTT_FFT_MAX_RANK, max_rank_hat + oversample <=
+ * QTT_FFT_MAX_ELL and d + n_axes <= 31.
  */
-int qtt_query_conv_fft(int d, int max_rank_hat, int oversample, int32_t* y_cap, size_t* ws_bytes);
+int qtt_query_conv_fft(int d, int n_axes, const int32_t* axis_modes, int max_rank_hat,
+                       int oversample, int32_t* y_cap, size_t* ws_bytes);
 
 /*
  * The QTT-FFT convolution route, Step 3 of Algorithm 2:
  * I = QiFFT(QFFT(F) . QFFT(G)), truncated by R^_max (and optionally a
  * tolerance and the drop-off threshold) in every transform.
- *   f         real data tensor, d modes (f32 or f64); it is zero-padded by
- *             one mode (2^(d+1) samples, the data in the lower half)
- *   w         real Toeplitz generator of the kernel, d + 1 modes (as written
- *             by qtt_kernel_sinc: lag u - 2^d at index u); it is rotated by
- *             2^d (lag 0 at index 0, the
- *             negative lags at the top), so that the lower half of the
- *             circular convolution is the discrete convolution (2.2), the
- *             product T(w) f of qtt_conv
+ *   f         real data tensor, d modes (f32 or f64); each axis is
+ *             zero-padded by one mode (the data in the lower half)
+ *   w, n_axes, axis_modes   as in qtt_conv: n_axes = 1 (a signal, w[0] with
+ *             d + 1 modes) or 2 (a row-major image, axis_modes = {dx, dy},
+ *             dx + dy = d, w[0] the column axis with dx + 1 modes, w[1] the
+ *             row axis with dy + 1 modes); each w is a Toeplitz generator as
+ *             written by qtt_kernel_sinc (lag u - 2^k at index u), rotated
+ *             here by 2^k (lag 0 at index 0, the negative lags at the top),
+ *             so that the lower half of the circular convolution is the
+ *             discrete convolution (2.2), the product of qtt_conv.  For an
+ *             image both transforms are two-dimensional: each axis's digits
+ *             form a block transformed on its own (bit-reversed inside it)
  *   eps_hat, max_rank_hat, delta_hat   the rule of every rounding, as in
  *             qtt_fft (max_rank_hat >= 1)
  *   oversample, seed   the product of the two spectra (ranks r_F r_G) is
@@ -523,15 +528,15 @@ int qtt_query_conv_fft(int d, int max_rank_hat, int oversample, int32_t* y_cap, 
  *             (2t + i, u, p, 0) for entry (t, i, u) of core p, key = seed),
  *             orthogonalisation left to right, then the truncation sweep
  *   y         real tensor, d modes, dtype of f, capacities from
- *             qtt_query_conv_fft: the real part of the lower half of the
- *             inverse transform as a real TT (complex ranks doubled)
+ *             qtt_query_conv_fft: the real part of the inverse transform with
+ *             every padding digit 0, as a real TT (complex ranks doubled)
  * The actual ranks of f and w must not exceed QTT_FFT_MAX_RANK; otherwise y
  * is the zero tensor and QTT_STATUS_FFT_RANK is set in y->status.  The
  * transforms run in FP64 complex arithmetic whatever the dtype of f.
  */
-int qtt_conv_fft(const qtt_tensor* f, const qtt_tensor* w, double eps_hat, int max_rank_hat,
-                 double delta_hat, int oversample, uint64_t seed, qtt_tensor* y, void* ws,
-                 size_t ws_bytes, void* stream);
+int qtt_conv_fft(const qtt_tensor* f, const qtt_tensor* w, int n_axes, const int32_t* axis_modes,
+                 double eps_hat, int max_rank_hat, double delta_hat, int oversample,
+                 uint64_t seed, qtt_tensor* y, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Kernel classes for the launch probe.  Between qtt_probe_start and

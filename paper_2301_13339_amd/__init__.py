@@ -427,36 +427,44 @@ def qfft(x: QTT, inverse: bool = False, eps: float = 0.0, max_rank: int = 0,
     return y
 
 
-def conv_fft(f: QTT, w: QTT, max_rank_hat: int = 15, eps_hat: float = 0.0, delta_hat: float = 0.0,
-             oversample: int = 8, seed: int = 0) -> QTT:
+def conv_fft(f: QTT, w, max_rank_hat: int = 15, eps_hat: float = 0.0, delta_hat: float = 0.0,
+             oversample: int = 8, seed: int = 0, axis_modes=None) -> QTT:
     """Step 3 of Algorithm 2 by QTT-FFT: ``QiFFT(QFFT(F) . QFFT(G))`` of the
-    zero-padded data ``f`` (``d`` modes) and the rotated Toeplitz generator
-    ``w`` (``d + 1`` modes, as from :func:`kernel_sinc`); returns the real part
-    of the lower half as a real QTT (dtype of ``f``)."""
+    zero-padded data ``f`` and the rotated Toeplitz generator(s) ``w`` (one
+    QTT with ``d + 1`` modes for a signal, or ``[wx, wy]`` with
+    ``axis_modes = [dx, dy]`` for a row-major image, as from
+    :func:`kernel_sinc`); returns the real part with the padding digits at 0
+    as a real QTT (dtype of ``f``)."""
+    ws_list = list(w) if isinstance(w, (list, tuple)) else [w]
+    n_axes = len(ws_list)
+    am = [f.d] if axis_modes is None else [int(v) for v in axis_modes]
+    amc = (ctypes.c_int32 * len(am))(*am)
     cap = (ctypes.c_int32 * (f.d + 1))()
-    ws = ctypes.c_size_t()
-    _check(lib().qtt_query_conv_fft(f.d, int(max_rank_hat), int(oversample), cap,
-                                    ctypes.byref(ws)), "qtt_query_conv_fft")
+    wsz = ctypes.c_size_t()
+    _check(lib().qtt_query_conv_fft(f.d, n_axes, amc, int(max_rank_hat), int(oversample), cap,
+                                    ctypes.byref(wsz)), "qtt_query_conv_fft")
     y = _make(f.d, f.dtype, list(cap), f.device)
-    wsb = _workspace(ws.value, f.device)
-    fc, wc, yc = f._c(), w._c(), y._c()
-    _check(lib().qtt_conv_fft(ctypes.byref(fc), ctypes.byref(wc), float(eps_hat),
+    wsb = _workspace(wsz.value, f.device)
+    fc, yc = f._c(), y._c()
+    warr = (qtt_tensor * n_axes)(*[t._c() for t in ws_list])
+    _check(lib().qtt_conv_fft(ctypes.byref(fc), warr, n_axes, amc, float(eps_hat),
                               int(max_rank_hat), float(delta_hat), int(oversample),
                               ctypes.c_uint64(int(seed)), ctypes.byref(yc),
-                              ctypes.c_void_p(wsb.data_ptr()), ws.value, _stream(f.device)),
+                              ctypes.c_void_p(wsb.data_ptr()), wsz.value, _stream(f.device)),
            "qtt_conv_fft")
     y._keep.append(wsb)
     return y
 
 
-def pipeline_fft(x: torch.Tensor, B: float, eps: float, max_rank: int = 10,
+def pipeline_fft(x: torch.Tensor, B, eps: float, max_rank: int = 10,
                  max_rank_hat: int = 15, eps_w: float | None = None, eps_hat: float = 0.0,
-                 delta: float = 0.0, oversample: int = 8, seed: int = 0):
+                 delta: float = 0.0, oversample: int = 8, seed: int = 0, shape2d=None):
     """Algorithm 2 with the QTT-FFT route of Step 3: decompose (tolerance, cap
-    ``max_rank``, optional drop-off), build the kernel QTT, convolve by
-    ``QiFFT(QFFT(F) . QFFT(G))`` truncated at ``max_rank_hat`` (and ``delta``
-    as the paper uses the same threshold in both places), reconstruct.
-    Returns ``(out, stages)``."""
+    ``max_rank``, optional drop-off), build the kernel QTT(s), convolve by
+    ``QiFFT(QFFT(F) . QFFT(G))`` truncated at ``max_rank_hat`` (and ``delta``,
+    as the paper uses the same threshold in both places), reconstruct.  ``B``
+    is one bandwidth, or ``(Bx, By)`` with ``shape2d = (ny, nx)`` for a
+    row-major image.  Returns ``(out, stages)``."""
     if eps_w is None:
         eps_w = eps / 10.0
     d = int(x.numel()).bit_length() - 1
@@ -465,11 +473,23 @@ def pipeline_fft(x: torch.Tensor, B: float, eps: float, max_rank: int = 10,
     side.wait_stream(main)
     f = decompose(x, eps, max_rank, delta=delta)
     with torch.cuda.stream(side):
-        w = kernel_sinc(d, float(B), eps_w, x.dtype, x.device)
+        if shape2d is None:
+            w = [kernel_sinc(d, float(B), eps_w, x.dtype, x.device)]
+            am = None
+        else:
+            ny, nx = shape2d
+            dy, dx = ny.bit_length() - 1, nx.bit_length() - 1
+            bx, by = B
+            w = [kernel_sinc(dx, float(bx), eps_w, x.dtype, x.device),
+                 kernel_sinc(dy, float(by), eps_w, x.dtype, x.device)]
+            am = [dx, dy]
     main.wait_stream(side)
-    w.record_stream(main)
-    y = conv_fft(f, w, max_rank_hat, eps_hat, delta, oversample, seed)
+    for t in w:
+        t.record_stream(main)
+    y = conv_fft(f, w, max_rank_hat, eps_hat, delta, oversample, seed, am)
     out = full(y)
+    if shape2d is not None:
+        out = out.reshape(shape2d)
     return out, dict(f=f, w=w, y=y)
 
 

@@ -163,10 +163,12 @@ def _declare(L):
     L.qtt_fft.argtypes = [_TP, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_double, _TP,
                           _VP, ctypes.c_size_t, _VP]
     L.qtt_query_conv_fft.restype = ctypes.c_int
-    L.qtt_query_conv_fft.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, _I32P, _SZP]
+    L.qtt_query_conv_fft.argtypes = [ctypes.c_int, ctypes.c_int, _I32P, ctypes.c_int, ctypes.c_int,
+                                     _I32P, _SZP]
     L.qtt_conv_fft.restype = ctypes.c_int
-    L.qtt_conv_fft.argtypes = [_TP, _TP, ctypes.c_double, ctypes.c_int, ctypes.c_double,
-                               ctypes.c_int, ctypes.c_uint64, _TP, _VP, ctypes.c_size_t, _VP]
+    L.qtt_conv_fft.argtypes = [_TP, _TP, ctypes.c_int, _I32P, ctypes.c_double, ctypes.c_int,
+                               ctypes.c_double, ctypes.c_int, ctypes.c_uint64, _TP, _VP,
+                               ctypes.c_size_t, _VP]
     L.qtt_probe_start.restype = ctypes.c_int
     L.qtt_probe_start.argtypes = [ctypes.c_int, ctypes.c_int]
     L.qtt_probe_stop.restype = ctypes.c_int

@@ -373,6 +373,8 @@ struct Task {
   int lib_cap;       // 1: the cap is the library's, flag when the rule wanted more
   double eps;        // tolerance of each rounding (0 = off)
   double delta;      // drop-off threshold (0 = off)
+  int nblk;          // axes: blocks of consecutive cores, each transformed on its own
+  int lo[2], hi[2];  // 0-based first core and end of each block
 };
 struct Tasks {
   Task t[2];
@@ -395,16 +397,16 @@ struct Smem {
 };
 
 // Right-to-left truncation sweep from core m (whose right unfolding, M x
-// 2 rr, is in S.C[0]) down to core 2; cores 1..m-1 are left-orthonormal and
-// cores right of m right-orthonormal.  Truncates bonds m-1..1 with
-// tau^2 = eps^2 ||centre||^2 / (D-1) and writes cores m..1.
-__device__ __forceinline__ void svd_sweep(const Task& T, int m, int M, int rr, Smem& S) {
+// 2 rr, is in S.C[0]) down to core lo + 2; cores 1..m-1 are left-orthonormal
+// and cores right of m right-orthonormal.  Truncates bonds m-1..lo+1 with
+// tau^2 = eps^2 ||centre||^2 / (D-1) and writes cores m..lo+1.
+__device__ __forceinline__ void svd_sweep(const Task& T, int m, int M, int rr, int lo, Smem& S) {
   const int t = threadIdx.x;
   const int D = T.D;
   cplx* const tc = T.cores;
   auto slot = [=](int p) { return tc + (size_t)(p - 1) * kSlot; };
   int cur = 0;
-  for (int p = m; p >= 2; --p) {
+  for (int p = m; p >= lo + 2; --p) {
     const int N = 2 * rr;
     jacobi(S.C[cur], S.J, M, N, lds(S.flag), lds(S.s2), lds(S.scal));
     sort_columns(S.C[cur], M, N, lds(S.s2), lds(S.s2s), lds(S.perm));
@@ -445,25 +447,31 @@ __device__ __forceinline__ void svd_sweep(const Task& T, int m, int M, int rr, S
     rr = r;
     M = Ml;
   }
-  // the last centre is core 1, (1, 2, r_1)
-  cplx* G1 = slot(1);
-  for (int col = t; col < 2 * rr; col += kNT) G1[col] = S.C[cur][col * kB];
+  // the last centre is core lo + 1, (r_lo, 2, rr)
+  cplx* G1 = slot(lo + 1);
+  for (int idx = t; idx < M * 2 * rr; idx += kNT) {
+    const int a = idx % M, col = idx / M;
+    G1[a * 2 * rr + col] = S.C[cur][col * kB + a];
+  }
   barrier_global();
 }
 
-// stage s (m = D + 1 - s >= 2) and the rounding of its doubled bonds
-__device__ __forceinline__ void stage_and_round(const Task& T, int m, Smem& S) {
+// the stage whose summed digit sits at core m (1-based, m >= lo + 2, the
+// block starting at 0-based core lo) and the rounding of its doubled bonds
+__device__ __forceinline__ void stage_and_round(const Task& T, int m, int lo, Smem& S) {
   const int t = threadIdx.x, c = t >> 3, q = t & 7;
   const int D = T.D;
   cplx* const tc = T.cores;
   auto slot = [=](int p) { return tc + (size_t)(p - 1) * kSlot; };  // 1-based core
   if (t <= D) S.r0[t] = S.rk[t];
   __syncthreads();
-  // ---- left-to-right QR sweep over the doubled cores 1..m-1
+  // ---- left-to-right QR sweep over cores 1..m-1; the bonds of cores
+  // lo+1..m-1 double (the first of them keeps its left bond)
   int k = 1;  // rows (left bond) of the current R
   for (int p = 1; p < m; ++p) {
     const int rl = S.r0[p - 1], rr = S.r0[p];
-    const int M = 2 * k, N = 2 * rr;
+    const bool dl = p > lo + 1, dr = p > lo;
+    const int M = 2 * k, N = dr ? 2 * rr : rr;
     cplx wtw;  // twiddle on slice 1 of branch k' = 1
     {
       double sn, cs;
@@ -472,7 +480,8 @@ __device__ __forceinline__ void stage_and_round(const Task& T, int m, Smem& S) {
     }
     const cplx* G = slot(p);
     cplx a[8];
-    const int kp = c / max(rr, 1), beta = c - kp * rr;
+    const int kp = dr ? c / max(rr, 1) : 0, beta = c - kp * rr;
+    const int roff = dl ? kp * rl : 0;
 #pragma unroll
     for (int e = 0; e < 8; ++e) {
       const int row = 8 * q + e;
@@ -483,7 +492,7 @@ __device__ __forceinline__ void stage_and_round(const Task& T, int m, Smem& S) {
           v = G[i * rr + beta];
         } else {
           for (int al = 0; al < rl; ++al)
-            v = cfma(S.R[cp * kB + kp * rl + al], G[(al * 2 + i) * rr + beta], v);
+            v = cfma(S.R[cp * kB + roff + al], G[(al * 2 + i) * rr + beta], v);
         }
         if (kp == 1 && i == 1) v = cmul(v, wtw);
       }
@@ -522,7 +531,55 @@ __device__ __forceinline__ void stage_and_round(const Task& T, int m, Smem& S) {
     }
   }
   __syncthreads();
-  svd_sweep(T, m, k, S.r0[m], S);
+  svd_sweep(T, m, k, S.r0[m], lo, S);
+}
+
+// Core p0 + 1 (1-based) made right-orthonormal: Householder QR of its
+// conjugate-transposed right unfolding C^H = Q R (C = R^H Q^H), the core
+// becomes Q^H and R^H is absorbed into core p0.
+__device__ __forceinline__ void right_orth(const Task& T, int p0, Smem& S) {
+  const int t = threadIdx.x, c = t >> 3, q = t & 7;
+  cplx* const tc = T.cores;
+  cplx* Gc = tc + (size_t)p0 * kSlot;           // the core made right-orthonormal
+  cplx* Gl = tc + (size_t)(p0 - 1) * kSlot;     // its left neighbour
+  const int rl = S.rk[p0], rr = S.rk[p0 + 1], rll = S.rk[p0 - 1];
+  const int M = 2 * rr, N = rl;
+  cplx a[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int row = 8 * q + e;  // row = i * rr + b of C^H, column c = a of C
+    cplx v = cz();
+    if (row < M && c < N) {
+      const int i = row / rr, b = row - i * rr;
+      v = cconj(Gc[(c * 2 + i) * rr + b]);
+    }
+    a[e] = v;
+  }
+  __syncthreads();
+  house_qr(a, M, N, S.V, lds(S.VV), S.R);
+  const int K = min(M, N);
+  __syncthreads();
+  if (c < K) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int row = 8 * q + e;
+      if (row < M) {
+        const int i = row / rr, b = row - i * rr;
+        Gc[(c * 2 + i) * rr + b] = cconj(a[e]);
+      }
+    }
+  }
+  // left neighbour times R^H, through LDS (read all, then write)
+  for (int idx = t; idx < rll * 2 * K; idx += kNT) {
+    const int j = idx % K, ai = idx / K;  // ai = alpha * 2 + i
+    cplx v = cz();
+    for (int x = 0; x < N; ++x) v = ccfma(S.R[j * kB + x], Gl[ai * rl + x], v);
+    S.C[0][idx] = v;
+  }
+  __syncthreads();
+  for (int idx = t; idx < rll * 2 * K; idx += kNT) Gl[idx] = S.C[0][idx];
+  if (t == 0) S.rk[p0] = K;
+  barrier_global();
 }
 
 __global__ __launch_bounds__(kNT) void k_qfft(Tasks tasks) {
@@ -532,31 +589,34 @@ __global__ __launch_bounds__(kNT) void k_qfft(Tasks tasks) {
   const int t = threadIdx.x, D = T.D;
   if (t <= D) S.rk[t] = T.ranks[t];
   __syncthreads();
-  for (int s = 1; s <= D; ++s) {
-    const int m = D + 1 - s;
-    if (m >= 2) {
-      stage_and_round(T, m, S);
-    } else {
-      // last stage: butterfly of core 1 (1, 2, r_1), no bond doubles
-      const int r1 = S.rk[1];
-      cplx* G = T.cores;
-      cplx ev = cz(), od = cz();
-      if (t < r1) {
-        const cplx g0 = G[t], g1 = G[r1 + t];
-        ev = cadd(g0, g1);
-        od = csub(g0, g1);
+  for (int bi = T.nblk - 1; bi >= 0; --bi) {
+    const int lo = bi == 0 ? T.lo[0] : T.lo[1], hi = bi == 0 ? T.hi[0] : T.hi[1];
+    if (bi < T.nblk - 1) right_orth(T, T.lo[1], S);
+    for (int m = hi; m >= lo + 1; --m) {
+      if (m >= lo + 2) {
+        stage_and_round(T, m, lo, S);
+      } else {
+        // the block's last stage: butterfly of core lo + 1, no bond doubles
+        const int rl = S.rk[lo], rr = S.rk[lo + 1];
+        cplx* G = T.cores + (size_t)lo * kSlot;
+        cplx ev = cz(), od = cz();
+        const int al = t / max(rr, 1), be = t - al * rr;
+        if (t < rl * rr) {
+          const cplx g0 = G[(al * 2) * rr + be], g1 = G[(al * 2 + 1) * rr + be];
+          ev = cadd(g0, g1);
+          od = csub(g0, g1);
+        }
+        __syncthreads();
+        if (t < rl * rr) {
+          G[(al * 2) * rr + be] = ev;
+          G[(al * 2 + 1) * rr + be] = od;
+        }
+        barrier_global();
       }
-      __syncthreads();
-      if (t < r1) {
-        G[t] = ev;
-        G[r1 + t] = od;
-      }
-      barrier_global();
     }
   }
   if (t <= D) T.ranks[t] = S.rk[t];
 }
-
 
 // ------------------------------------------------- Hadamard product rounding
 // Randomised rounding of the entrywise product H = A . B of two spectra
@@ -737,15 +797,17 @@ __global__ __launch_bounds__(kNT) void k_had_round(HadArgs H) {
     if (t == 0) S.rk[D] = 1;
   }
   __syncthreads();
-  svd_sweep(T, D, k, 1, S);
+  svd_sweep(T, D, k, 1, 0, S);
   if (t <= D) T.ranks[t] = S.rk[t];
 }
 
 // ----------------------------------------------------- layout conversions
 // Cores of a source tensor into the engine layout (complex, slot stride
-// kSlot), optionally with the mode order reversed, a zero-padding mode
-// appended (slice 1 zero), the top core's slices swapped (rotation by half
-// the length) and the first core scaled.
+// kSlot) from engine core `core0` on: optionally with the mode order
+// reversed, a zero-padding mode inserted before source core `pad_mid`
+// (identity core, slice 1 zero) and one appended at the end (slice 1 zero),
+// the source's top core's slices swapped (rotation by half the length) and
+// the first core scaled.
 struct LoadArgs {
   const void* src;
   int kind;                     // 0 f32, 1 f64, 2 complex FP64 pairs
@@ -754,8 +816,9 @@ struct LoadArgs {
   int d_src;
   cplx* dst;
   int32_t* dst_ranks;
-  int D;
-  int reverse, pad, rotate;
+  int core0;                    // first engine core written
+  int ncores;                   // engine cores written (d_src + the padding cores)
+  int reverse, pad_mid, pad_end, rotate;
   double scale;
   int32_t* status;              // QTT_STATUS_FFT_RANK when a source rank is too large
 };
@@ -766,64 +829,74 @@ __device__ __forceinline__ cplx load_elem(const void* src, int kind, long long i
   return static_cast<const cplx*>(src)[i];
 }
 
+// rank of bond j (0..ncores) of the written cores
+__device__ __forceinline__ int load_rank(const LoadArgs& L, int j) {
+  if (L.pad_end && j == L.ncores) return 1;
+  if (L.pad_mid >= 0 && j == L.pad_mid + 1) return L.src_ranks[L.pad_mid];
+  const int sj = j - ((L.pad_mid >= 0 && j > L.pad_mid) ? 1 : 0);
+  return L.reverse ? L.src_ranks[L.d_src - sj] : L.src_ranks[sj];
+}
+
 __global__ void k_fft_load(LoadArgs L) {
   // a rank above the engine's limit: the tensor is replaced by zero (ranks
   // 1) and the condition reported, so that every later kernel stays inside
   // its slots
   bool bad = false;
   for (int j = 0; j <= L.d_src; ++j) bad |= L.src_ranks[j] > kR || L.src_ranks[j] < 1;
-  const long long total = (long long)L.D * kSlot;
+  const long long g0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  cplx* const dst = L.dst + (size_t)L.core0 * kSlot;
   if (bad) {
-    const long long g0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-    if (g0 < L.D) {
-      L.dst[g0 * kSlot] = mk(0.0, 0.0);
-      L.dst[g0 * kSlot + 1] = mk(0.0, 0.0);
+    if (g0 < L.ncores) {
+      dst[g0 * kSlot] = mk(0.0, 0.0);
+      dst[g0 * kSlot + 1] = mk(0.0, 0.0);
     }
-    if (g0 <= L.D) L.dst_ranks[g0] = 1;
+    if (g0 <= L.ncores) L.dst_ranks[L.core0 + g0] = 1;
     if (g0 == 0 && L.status) atomicOr(L.status, QTT_STATUS_FFT_RANK);
     return;
   }
-  for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
-       g += (long long)gridDim.x * blockDim.x) {
+  const long long total = (long long)L.ncores * kSlot;
+  for (long long g = g0; g < total; g += (long long)gridDim.x * blockDim.x) {
     const int p = (int)(g / kSlot), e = (int)(g - (long long)p * kSlot);
-    if (L.pad && p == L.D - 1) {
-      if (e < 2) L.dst[g] = mk(e == 0 ? 1.0 : 0.0, 0.0);
+    if (L.pad_end && p == L.ncores - 1) {
+      if (e < 2) dst[g] = mk(e == 0 ? 1.0 : 0.0, 0.0);
       continue;
     }
-    const int sp = L.reverse ? L.d_src - 1 - p : p;
+    if (p == L.pad_mid) {
+      const int r = L.src_ranks[L.pad_mid];
+      if (e < r * 2 * r) {
+        const int a = e / (2 * r), i = (e / r) & 1, b = e % r;
+        dst[g] = mk((i == 0 && a == b) ? 1.0 : 0.0, 0.0);
+      }
+      continue;
+    }
+    const int q = p - ((L.pad_mid >= 0 && p > L.pad_mid) ? 1 : 0);  // source core
+    const int sp = L.reverse ? L.d_src - 1 - q : q;
     const int s0 = L.src_ranks[sp], s1 = L.src_ranks[sp + 1];
     const int d0 = L.reverse ? s1 : s0, d1 = L.reverse ? s0 : s1;
     if (e >= d0 * 2 * d1) continue;
     const int a = e / (2 * d1), i = (e / d1) & 1, b = e % d1;
     const int sa = L.reverse ? b : a, sb = L.reverse ? a : b;
-    const int si = (L.rotate && p == L.D - 1) ? 1 - i : i;
+    const int si = (L.rotate && sp == L.d_src - 1) ? 1 - i : i;
     cplx v = load_elem(L.src, L.kind, L.off[sp] + (long long)(sa * 2 + si) * s1 + sb);
     if (p == 0) v = cscale(v, L.scale);
-    L.dst[g] = v;
+    dst[g] = v;
   }
-  const long long g0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  if (g0 <= L.D) {
-    const int j = (int)g0;
-    int r;
-    if (L.pad && j == L.D)
-      r = 1;
-    else
-      r = L.reverse ? L.src_ranks[L.d_src - j] : L.src_ranks[j];
-    L.dst_ranks[j] = r;
-  }
+  if (g0 <= L.ncores) L.dst_ranks[L.core0 + g0] = load_rank(L, (int)g0);
 }
 
 // An engine tensor (D modes) into a caller's tensor: optionally the mode
 // order reversed and the first core scaled (the inverse transform's output),
-// the slice with top digit 0 taken (the lower half of the circular
-// convolution), and the real part as a real TT (interior cores
-// [[Re, -Im], [Im, Re]], bond index s * r + alpha, first core its first block
-// row, last core its first block column).
+// the slices with padding digit 0 taken (mode `mid` and, with `lower`, the
+// last mode: the lower half of the circular convolution on each axis), and
+// the real part as a real TT (interior cores [[Re, -Im], [Im, Re]], bond
+// index s * r + alpha, first core its first block row, last core its first
+// block column).
 struct StoreArgs {
   const cplx* src;
   const int32_t* src_ranks;
   int D;
   int reverse, lower, realify;
+  int mid;                      // logical core of an inner padding digit, or -1
   double scale;
   void* dst;
   int kind;                     // 0 f32, 1 f64, 2 complex
@@ -847,19 +920,32 @@ __device__ __forceinline__ cplx lentry(const StoreArgs& S, int p, int a, int i, 
   }
   return p == 0 ? cscale(v, S.scale) : v;
 }
-// entry of core p of the (possibly lower-half) complex tensor
-__device__ __forceinline__ cplx centry(const StoreArgs& S, int p, int a, int i, int b) {
-  if (S.lower && p == S.D - 2) {
+// logical core of output core p, and the logical rank of output bond j
+__device__ __forceinline__ int lcore(const StoreArgs& S, int p) {
+  return p + ((S.mid >= 0 && p >= S.mid) ? 1 : 0);
+}
+__device__ __forceinline__ int obond(const StoreArgs& S, int j) {
+  return lrank(S, j + ((S.mid >= 0 && j >= S.mid) ? 1 : 0));
+}
+// entry of the logical core lp with the padding digits contracted at 0
+__device__ __forceinline__ cplx centry(const StoreArgs& S, int lp, int a, int i, int b) {
+  if (S.mid >= 0 && lp == S.mid - 1) {
     cplx v = cz();
-    const int rb = lrank(S, S.D - 1);
-    for (int x = 0; x < rb; ++x) v = cfma(lentry(S, p, a, i, x), lentry(S, S.D - 1, x, 0, 0), v);
+    const int rb = lrank(S, S.mid);
+    for (int x = 0; x < rb; ++x) v = cfma(lentry(S, lp, a, i, x), lentry(S, S.mid, x, 0, b), v);
     return v;
   }
-  return lentry(S, p, a, i, b);
+  if (S.lower && lp == S.D - 2) {
+    cplx v = cz();
+    const int rb = lrank(S, S.D - 1);
+    for (int x = 0; x < rb; ++x) v = cfma(lentry(S, lp, a, i, x), lentry(S, S.D - 1, x, 0, 0), v);
+    return v;
+  }
+  return lentry(S, lp, a, i, b);
 }
 
 __global__ void k_fft_store(StoreArgs S) {
-  const int d = S.D - S.lower;
+  const int d = S.D - S.lower - (S.mid >= 0 ? 1 : 0);
   long long total = 0;
   for (int p = 0; p < d; ++p) total += (long long)S.cap[p] * 2 * S.cap[p + 1];
   for (long long g = blockIdx.x * (long long)blockDim.x + threadIdx.x; g < total;
@@ -867,8 +953,8 @@ __global__ void k_fft_store(StoreArgs S) {
     int p = 0;
     while (p + 1 < d && g >= S.off[p + 1]) ++p;
     const int e = (int)(g - S.off[p]);
-    const int c0 = (p == 0) ? 1 : lrank(S, p);
-    const int c1 = (p == d - 1) ? 1 : lrank(S, p + 1);
+    const int c0 = (p == 0) ? 1 : obond(S, p);
+    const int c1 = (p == d - 1) ? 1 : obond(S, p + 1);
     int o0 = c0, o1 = c1;
     if (S.realify) {
       o0 = (p == 0) ? 1 : 2 * c0;
@@ -876,13 +962,14 @@ __global__ void k_fft_store(StoreArgs S) {
     }
     if (e >= o0 * 2 * o1) continue;
     const int A = e / (2 * o1), i = (e / o1) & 1, Bx = e % o1;
+    const int lp = lcore(S, p);
     if (!S.realify) {
-      const cplx v = centry(S, p, A, i, Bx);
+      const cplx v = centry(S, lp, A, i, Bx);
       static_cast<cplx*>(S.dst)[g] = v;
       continue;
     }
     const int s = A / c0, a = A - s * c0, tt = Bx / c1, b = Bx - tt * c1;
-    const cplx z = centry(S, p, a, i, b);
+    const cplx z = centry(S, lp, a, i, b);
     double v;
     if (s == tt)
       v = z.x;
@@ -896,7 +983,7 @@ __global__ void k_fft_store(StoreArgs S) {
   const long long g0 = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (g0 <= d) {
     const int j = (int)g0;
-    int r = (j == 0 || j == d) ? 1 : lrank(S, j);
+    int r = (j == 0 || j == d) ? 1 : obond(S, j);
     if (S.realify && j > 0 && j < d) r *= 2;
     S.dst_ranks[j] = r;
   }
@@ -931,24 +1018,34 @@ static Engine take_engine(Arena& ar, int D) {
   return e;
 }
 
-static int launch_load(const qtt_tensor* src, int kind, const int32_t* src_ranks,
-                       const long long* off, int d_src, Engine dst, int D, int reverse, int pad,
-                       int rotate, double scale, int32_t* status, hipStream_t s) {
+struct LoadSpec {
+  int core0 = 0;       // first engine core written
+  int reverse = 0;
+  int pad_mid = -1;    // source core before which a padding core goes, or -1
+  int pad_end = 0;     // append a padding core
+  int rotate = 0;      // swap the slices of the source's last core
+  double scale = 1.0;
+};
+
+static int launch_load(const void* cores, int kind, const int32_t* src_ranks, const long long* off,
+                       int d_src, Engine dst, const LoadSpec& sp, int32_t* status, hipStream_t s) {
   LoadArgs L;
   L.status = status;
-  L.src = src ? src->cores : nullptr;
+  L.src = cores;
   L.kind = kind;
   L.src_ranks = src_ranks;
   for (int k = 0; k <= kMaxD; ++k) L.off[k] = k <= d_src ? off[k] : 0;
   L.d_src = d_src;
   L.dst = dst.cores;
   L.dst_ranks = dst.ranks;
-  L.D = D;
-  L.reverse = reverse;
-  L.pad = pad;
-  L.rotate = rotate;
-  L.scale = scale;
-  const long long total = (long long)D * kSlot;
+  L.core0 = sp.core0;
+  L.ncores = d_src + (sp.pad_mid >= 0 ? 1 : 0) + (sp.pad_end ? 1 : 0);
+  L.reverse = sp.reverse;
+  L.pad_mid = sp.pad_mid;
+  L.pad_end = sp.pad_end;
+  L.rotate = sp.rotate;
+  L.scale = sp.scale;
+  const long long total = (long long)L.ncores * kSlot;
   const int grid = (int)((total + 255) / 256);
   ProbeScope ps(QTT_K_OTHER, s);
   hipLaunchKernelGGL(k_fft_load, dim3(grid), dim3(256), 0, s, L);
@@ -956,42 +1053,40 @@ static int launch_load(const qtt_tensor* src, int kind, const int32_t* src_ranks
   return QTT_OK;
 }
 
-static void engine_offsets(int D, long long* off) {
+// element offsets of the cores of a caller's tensor
+static void tensor_offsets(const qtt_tensor* t, long long* off) {
+  long long o = 0;
+  for (int k = 0; k <= t->d; ++k) {
+    off[k] = o;
+    if (k < t->d) o += (long long)t->cap[k] * 2 * t->cap[k + 1];
+  }
+}
+
+static int load_tensor(const qtt_tensor* t, Engine dst, const LoadSpec& sp, int32_t* status,
+                       hipStream_t s) {
+  long long off[kMaxD + 1];
+  tensor_offsets(t, off);
+  const int kind = t->dtype == QTT_F32 ? 0 : (t->dtype == QTT_F64 ? 1 : 2);
+  return launch_load(t->cores, kind, t->ranks, off, t->d, dst, sp, status, s);
+}
+
+static int launch_engine_load(Engine src, int D, Engine dst, int reverse, hipStream_t s) {
+  long long off[kMaxD + 1];
   for (int k = 0; k <= D; ++k) off[k] = (long long)k * kSlot;
+  LoadSpec sp;
+  sp.reverse = reverse;
+  return launch_load(src.cores, 2, src.ranks, off, D, dst, sp, nullptr, s);
 }
 
-static int launch_engine_load(Engine src, int D, Engine dst, int reverse, double scale,
-                              hipStream_t s) {
-  LoadArgs L;
-  L.status = nullptr;
-  L.src = src.cores;
-  L.kind = 2;
-  L.src_ranks = src.ranks;
-  engine_offsets(D, L.off);
-  for (int k = D + 1; k <= kMaxD; ++k) L.off[k] = 0;
-  L.d_src = D;
-  L.dst = dst.cores;
-  L.dst_ranks = dst.ranks;
-  L.D = D;
-  L.reverse = reverse;
-  L.pad = 0;
-  L.rotate = 0;
-  L.scale = scale;
-  const long long total = (long long)D * kSlot;
-  ProbeScope ps(QTT_K_OTHER, s);
-  hipLaunchKernelGGL(k_fft_load, dim3((int)((total + 255) / 256)), dim3(256), 0, s, L);
-  QTT_LAUNCH_CHECK();
-  return QTT_OK;
-}
-
-static int launch_store(Engine src, int D, int reverse, int lower, int realify, double scale,
-                        const qtt_tensor* y, hipStream_t s) {
+static int launch_store(Engine src, int D, int reverse, int lower, int mid, int realify,
+                        double scale, const qtt_tensor* y, hipStream_t s) {
   StoreArgs S;
   S.src = src.cores;
   S.src_ranks = src.ranks;
   S.D = D;
   S.reverse = reverse;
   S.lower = lower;
+  S.mid = mid;
   S.realify = realify;
   S.scale = scale;
   S.dst = y->cores;
@@ -1035,7 +1130,20 @@ static Task make_task(Engine e, int32_t* status, int D, int sign, double eps, in
   T.lib_cap = max_rank > 0 ? 0 : 1;
   T.eps = eps;
   T.delta = delta;
+  T.nblk = 1;
+  T.lo[0] = 0;
+  T.hi[0] = D;
+  T.lo[1] = T.hi[1] = D;
   return T;
+}
+
+// the two axis blocks of an image: column digits (dx) then row digits
+static void set_blocks(Task* T, int b0, int b1) {
+  T->nblk = 2;
+  T->lo[0] = 0;
+  T->hi[0] = b0;
+  T->lo[1] = b0;
+  T->hi[1] = b0 + b1;
 }
 
 // the rank bound of a transform's output: min(2^k, 2^(D-k), cap)
@@ -1109,49 +1217,70 @@ int qtt_fft(const qtt_tensor* x, int inverse, double eps, int max_rank, double d
   hipStream_t s = static_cast<hipStream_t>(stream);
   Arena ar(ws);
   Engine e = take_engine(ar, D);
-  long long off[kMaxD + 1];
-  long long o = 0;
-  for (int k = 0; k <= D; ++k) {
-    off[k] = o;
-    if (k < D) o += (long long)x->cap[k] * 2 * x->cap[k + 1];
-  }
-  rc = launch_load(x, 2, x->ranks, off, D, e, D, inverse ? 1 : 0, 0, 0, 1.0, y->status, s);
+  LoadSpec sp;
+  sp.reverse = inverse ? 1 : 0;
+  rc = load_tensor(x, e, sp, y->status, s);
   if (rc) return rc;
   const Task T = make_task(e, y->status, D, inverse ? 1 : -1, eps, max_rank, delta);
   rc = launch_qfft(&T, 1, s);
   if (rc) return rc;
-  return launch_store(e, D, inverse ? 1 : 0, 0, 0, inverse ? ldexp(1.0, -D) : 1.0, y, s);
+  return launch_store(e, D, inverse ? 1 : 0, 0, -1, 0, inverse ? ldexp(1.0, -D) : 1.0, y, s);
 }
 
-int qtt_query_conv_fft(int d, int max_rank_hat, int oversample, int32_t* y_cap, size_t* ws_bytes) {
-  if (d < 1 || d + 1 > kMaxD || max_rank_hat < 1 || max_rank_hat > kR || oversample < 0 ||
-      max_rank_hat + oversample > kL)
+static int axes_ok(int d, int n_axes, const int32_t* axis_modes) {
+  if (n_axes == 1) return (!axis_modes || axis_modes[0] == d) ? QTT_OK : QTT_EINVAL;
+  if (n_axes != 2 || !axis_modes) return QTT_EINVAL;
+  if (axis_modes[0] < 1 || axis_modes[1] < 1 || axis_modes[0] + axis_modes[1] != d)
     return QTT_EINVAL;
-  if (y_cap) {
-    int32_t c[kMaxD + 1];
-    fft_caps(d + 1, max_rank_hat, c);
-    for (int k = 0; k <= d; ++k) y_cap[k] = (k == 0 || k == d) ? 1 : 2 * c[k];
-  }
-  if (ws_bytes) *ws_bytes = conv_fft_ws(d + 1);
   return QTT_OK;
 }
 
-int qtt_conv_fft(const qtt_tensor* f, const qtt_tensor* w, double eps_hat, int max_rank_hat,
-                 double delta_hat, int oversample, uint64_t seed, qtt_tensor* y, void* ws,
-                 size_t ws_bytes, void* stream) {
+// capacities of the output: the inverse transform's bond bound (doubled by
+// the real part) on the bonds that remain once the padding digits are gone
+static void conv_fft_caps(int d, int n_axes, const int32_t* axis_modes, int R, int32_t* y_cap) {
+  const int D = d + n_axes;
+  int32_t c[kMaxD + 1];
+  fft_caps(D, R, c);
+  const int mid = n_axes == 2 ? axis_modes[0] : -1;  // engine core of the column padding
+  for (int j = 0; j <= d; ++j) {
+    const int lj = j + ((mid >= 0 && j >= mid) ? 1 : 0);
+    y_cap[j] = (j == 0 || j == d) ? 1 : 2 * c[lj];
+  }
+}
+
+int qtt_query_conv_fft(int d, int n_axes, const int32_t* axis_modes, int max_rank_hat,
+                       int oversample, int32_t* y_cap, size_t* ws_bytes) {
+  if (d < 1 || d + n_axes > kMaxD || max_rank_hat < 1 || max_rank_hat > kR || oversample < 0 ||
+      max_rank_hat + oversample > kL)
+    return QTT_EINVAL;
+  if (axes_ok(d, n_axes, axis_modes)) return QTT_EINVAL;
+  if (y_cap) conv_fft_caps(d, n_axes, axis_modes, max_rank_hat, y_cap);
+  if (ws_bytes) *ws_bytes = conv_fft_ws(d + n_axes);
+  return QTT_OK;
+}
+
+int qtt_conv_fft(const qtt_tensor* f, const qtt_tensor* w, int n_axes, const int32_t* axis_modes,
+                 double eps_hat, int max_rank_hat, double delta_hat, int oversample,
+                 uint64_t seed, qtt_tensor* y, void* ws, size_t ws_bytes, void* stream) {
   int rc = tensor_in_ok(f, QTT_F32, QTT_F64);
   if (rc) return rc;
-  rc = tensor_in_ok(w, QTT_F32, QTT_F64);
-  if (rc) return rc;
-  const int d = f->d, D = d + 1;
-  if (w->d != D || D > kMaxD) return w->d != D ? QTT_EINVAL : QTT_ENOTSUP;
+  if (!w || (n_axes != 1 && n_axes != 2)) return QTT_EINVAL;
+  const int d = f->d, D = d + n_axes;
+  if (D > kMaxD) return QTT_ENOTSUP;
+  if (axes_ok(d, n_axes, axis_modes)) return QTT_EINVAL;
+  for (int a = 0; a < n_axes; ++a) {
+    rc = tensor_in_ok(&w[a], QTT_F32, QTT_F64);
+    if (rc) return rc;
+    const int need = (n_axes == 1 ? d : axis_modes[a]) + 1;
+    if (w[a].d != need) return QTT_EINVAL;
+  }
   if (!rule_ok(eps_hat, max_rank_hat, delta_hat) || max_rank_hat < 1 || oversample < 0 ||
       max_rank_hat + oversample > kL)
     return QTT_EINVAL;
   if (!y || y->d != d || y->dtype != f->dtype || !y->ranks || !y->cores) return QTT_EINVAL;
-  int32_t need[kMaxD + 1];
-  qtt_query_conv_fft(d, max_rank_hat, oversample, need, nullptr);
   if (y->cap[0] != 1 || y->cap[d] != 1) return QTT_EINVAL;
+  int32_t need[kMaxD + 1];
+  conv_fft_caps(d, n_axes, axis_modes, max_rank_hat, need);
   for (int k = 0; k <= d; ++k)
     if (y->cap[k] < need[k]) return QTT_ENOSPC;
   if (!ws || ws_bytes < conv_fft_ws(D)) return QTT_ENOSPC;
@@ -1163,24 +1292,27 @@ int qtt_conv_fft(const qtt_tensor* f, const qtt_tensor* w, double eps_hat, int m
   cplx* Mb = ar.take<cplx>((size_t)2 * kHad * kL);
   cplx* T1 = ar.take<cplx>((size_t)2 * kL * kR * kR);
   cplx* Zb = ar.take<cplx>((size_t)kL * kHad);
-  long long off[kMaxD + 1];
-  const int kf = f->dtype == QTT_F32 ? 0 : 1, kw = w->dtype == QTT_F32 ? 0 : 1;
-  long long o = 0;
-  for (int k = 0; k <= d; ++k) {
-    off[k] = o;
-    if (k < d) o += (long long)f->cap[k] * 2 * f->cap[k + 1];
-  }
-  rc = launch_load(f, kf, f->ranks, off, d, ef, D, 0, 1, 0, 1.0, y->status, s);
+  const int dx = n_axes == 2 ? axis_modes[0] : d;
+  // data: a padding digit after each axis
+  LoadSpec sf;
+  sf.pad_mid = n_axes == 2 ? dx : -1;
+  sf.pad_end = 1;
+  rc = load_tensor(f, ef, sf, y->status, s);
   if (rc) return rc;
-  o = 0;
-  for (int k = 0; k <= D; ++k) {
-    off[k] = o;
-    if (k < D) o += (long long)w->cap[k] * 2 * w->cap[k + 1];
+  // kernel: the rotated generator of each axis, one after the other
+  for (int a = 0; a < n_axes; ++a) {
+    LoadSpec sw;
+    sw.core0 = a == 0 ? 0 : dx + 1;
+    sw.rotate = 1;
+    rc = load_tensor(&w[a], eg, sw, y->status, s);
+    if (rc) return rc;
   }
-  rc = launch_load(w, kw, w->ranks, off, D, eg, D, 0, 0, 1, 1.0, y->status, s);
-  if (rc) return rc;
   Task tk[2] = {make_task(ef, y->status, D, -1, eps_hat, max_rank_hat, delta_hat),
                 make_task(eg, y->status, D, -1, eps_hat, max_rank_hat, delta_hat)};
+  if (n_axes == 2) {
+    set_blocks(&tk[0], dx + 1, D - dx - 1);
+    set_blocks(&tk[1], dx + 1, D - dx - 1);
+  }
   rc = launch_qfft(tk, 2, s);
   if (rc) return rc;
   HadArgs H;
@@ -1197,17 +1329,22 @@ int qtt_conv_fft(const qtt_tensor* f, const qtt_tensor* w, double eps_hat, int m
   H.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
   H.k1 = (uint32_t)(seed >> 32);
   {
+    rc = set_attrs();
+    if (rc) return rc;
     ProbeScope ps(QTT_K_QFFT_HADAMARD, s);
     hipLaunchKernelGGL(k_had_round, dim3(1), dim3(kNT), sizeof(HadSmem), s, H);
     QTT_LAUNCH_CHECK();
   }
-  // QiFFT: natural order in, transform with the +1 exponent, reversed back
-  rc = launch_engine_load(eh, D, er, 1, 1.0, s);
+  // QiFFT: reversing restores the digit order inside each axis and mirrors
+  // the axes; the forward stages with the +1 exponent run on the mirrored
+  // blocks and the result is reversed back
+  rc = launch_engine_load(eh, D, er, 1, s);
   if (rc) return rc;
-  const Task ti = make_task(er, y->status, D, 1, eps_hat, max_rank_hat, delta_hat);
+  Task ti = make_task(er, y->status, D, 1, eps_hat, max_rank_hat, delta_hat);
+  if (n_axes == 2) set_blocks(&ti, D - dx - 1, dx + 1);
   rc = launch_qfft(&ti, 1, s);
   if (rc) return rc;
-  return launch_store(er, D, 1, 1, 1, ldexp(1.0, -D), y, s);
+  return launch_store(er, D, 1, 1, n_axes == 2 ? dx : -1, 1, ldexp(1.0, -D), y, s);
 }
 
 }  // extern "C"

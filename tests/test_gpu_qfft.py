@@ -202,3 +202,75 @@ def test_conv_fft_flags_input_ranks_above_the_engine_limit():
     y = q.conv_fft(f, w, 8)
     assert y.status_host() & 4
     assert float(q.full(y).abs().max()) == 0.0
+
+
+def test_conv_fft_2d_exact_equals_direct_convolution():
+    """A 8 x 16 image (3 row and 4 column digits, 9 modes with the padding):
+    every rank fits, so the two-dimensional route is the separable direct
+    convolution (2.2)."""
+    print("case: conv_fft 2-D exact", flush=True)
+    dx, dy = 4, 3
+    rng = np.random.default_rng(11)
+    f = rng.standard_normal((1 << dy, 1 << dx))
+    wx, wy = conv.toeplitz_generator(dx, 6.0), conv.toeplitz_generator(dy, 3.0)
+    F = q.from_cores(tt.tt_svd(f.ravel(), 0.0))
+    Wx, Wy = q.from_cores(tt.tt_svd(wx, 0.0)), q.from_cores(tt.tt_svd(wy, 0.0))
+    y = q.conv_fft(F, [Wx, Wy], 16, oversample=8, seed=2, axis_modes=[dx, dy])
+    out = q.full(y).cpu().numpy()
+    assert rel(out, conv.toeplitz_apply_2d(f, wy, wx, fft=False).ravel()) <= 1e-11
+    assert y.status_host() == 0
+
+
+def test_conv_fft_2d_matches_oracle_route():
+    """Example 3's image at K = 7 (14 digits, 16 with the padding), R^ = 6,
+    p = 4: the same cores and the same Philox sketch on both sides."""
+    print("case: conv_fft 2-D vs oracle", flush=True)
+    K = 7
+    noisy, _, _, _ = G.paper_example3(K, 0)
+    n = noisy.shape[0]
+    x = np.zeros((1 << K, 1 << K))
+    x[:n, :n] = noisy
+    Fc = tt.tt_svd(x.ravel(), 1e-4, 10)
+    Wc = tt.tt_svd(conv.toeplitz_generator(K, (1 << K) / 2.0), 1e-5, 0)
+    ref, info = Q.conv_fft_2d(Fc, K, Wc, Wc, 0.0, 6, 0.0, oversample=4, seed=5,
+                              return_info=True)
+    W = q.from_cores(Wc)
+    y = q.conv_fft(q.from_cores(Fc), [W, W], 6, 0.0, 0.0, 4, 5, axis_modes=[K, K])
+    out = q.full(y).cpu().numpy()
+    want = Q.full(ref).real
+    tol = cut_tolerance(info["cuts"])
+    err = rel(out, want)
+    print(f"2-D route: rel {err:.2e} (tolerance {tol:.1e}) ranks {y.ranks_host()}", flush=True)
+    assert y.ranks_host()[1:-1] == [2 * r for r in Q.ranks(ref)[1:-1]]
+    assert err <= tol
+
+
+def test_paper_example3_through_the_qfft_route():
+    """Example 3 (2-D, K = 10) with the paper's parameters (R_max = 10,
+    R^_max = 15) through pipeline_fft: against the oracle's route, and the
+    error (7.1) within 15 % of Table 7.1's QTT_0 (0.0151)."""
+    print("case: paper example3 via 2-D qfft", flush=True)
+    K = 10
+    noisy, clean, _, _ = G.paper_example3(K, 0)
+    n = noisy.shape[0]
+    x = np.zeros((1 << K, 1 << K))
+    c = np.zeros((1 << K, 1 << K))
+    x[:n, :n] = noisy
+    c[:n, :n] = clean
+    B = (1 << K) / float(GOLD["example3"]["resolution_in_dx"])
+    out, st = q.pipeline_fft(torch.tensor(x.ravel(), device="cuda"), (B, B), 1e-4, 10, 15,
+                             seed=1, shape2d=x.shape)
+    out = out.cpu().numpy()
+    F = tt.tt_svd(x.ravel(), 1e-4, 10)
+    wg = conv.toeplitz_generator(K, B)
+    W = tt.tt_svd(wg, 1e-5, 0)
+    ref, info = Q.conv_fft_2d(F, K, W, W, 0.0, 15, 0.0, oversample=8, seed=1, return_info=True)
+    want = Q.full(ref).real.reshape(x.shape)
+    assert st["f"].ranks_host() == tt.tt_ranks(F)
+    err = rel(out, want)
+    tol = cut_tolerance(info["cuts"], floor=1e-9)
+    e2 = P.relative_error(out, conv.toeplitz_apply_2d(c, wg, wg))
+    print(f"example3: rel to the oracle route {err:.2e} (tolerance {tol:.1e}), E2 {e2:.5f} "
+          f"(Table 7.1 {GOLD['example3']['qtt0']})", flush=True)
+    assert err <= tol
+    assert abs(e2 - GOLD["example3"]["qtt0"]) <= 0.15 * GOLD["example3"]["qtt0"]
