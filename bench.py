@@ -46,6 +46,10 @@ WORKLOADS = {
     # K = 20: max-rank TT-SVD R_max = 10, QFFT/QiFFT truncated at R^_max = 15
     "qfft_example1_k20": dict(qfft_K=20, max_rank=10, max_rank_hat=15, eps=1e-4,
                               oversample=8, seed=1),
+    # the same route on Example 3, the 2-D image at K = 10 (two-dimensional
+    # transforms, one axis block each)
+    "qfft_example3_k10": dict(qfft_K=10, qfft_2d=True, max_rank=10, max_rank_hat=15, eps=1e-4,
+                              oversample=8, seed=1),
 }
 
 
@@ -694,16 +698,30 @@ def bench_qfft(args, wl):
     from synthetic import generators as G
 
     K, R, Rh, eps = wl["qfft_K"], wl["max_rank"], wl["max_rank_hat"], wl["eps"]
-    noisy, clean, _, _ = G.paper_example1(K, 0)
-    xn = np.zeros(1 << K)
-    xn[: noisy.size] = noisy
-    cn = np.zeros(1 << K)
-    cn[: clean.size] = clean
-    B = (1 << K) / 4.0
-    n = 1 << K
-    x = torch.tensor(xn, device="cuda")
+    two_d = wl.get("qfft_2d", False)
+    if two_d:
+        noisy, clean, _, _ = G.paper_example3(K, 0)
+        m = noisy.shape[0]
+        xn = np.zeros((1 << K, 1 << K))
+        cn = np.zeros((1 << K, 1 << K))
+        xn[:m, :m] = noisy
+        cn[:m, :m] = clean
+        B = (1 << K) / 2.0
+        n = 1 << (2 * K)
+    else:
+        noisy, clean, _, _ = G.paper_example1(K, 0)
+        xn = np.zeros(1 << K)
+        xn[: noisy.size] = noisy
+        cn = np.zeros(1 << K)
+        cn[: clean.size] = clean
+        B = (1 << K) / 4.0
+        n = 1 << K
+    x = torch.tensor(xn.ravel(), device="cuda")
 
     def step():
+        if two_d:
+            return q.pipeline_fft(x, (B, B), eps, R, Rh, oversample=wl["oversample"],
+                                  seed=wl["seed"], shape2d=xn.shape)
         return q.pipeline_fft(x, B, eps, R, Rh, oversample=wl["oversample"], seed=wl["seed"])
 
     for _ in range(max(args.warmup, 1)):
@@ -729,9 +747,13 @@ def bench_qfft(args, wl):
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / steps
     spread = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
-    from oracle import pipeline as P
-    e2 = P.relative_error(out.cpu().numpy(), P.clean_reference_1d(cn, B))
-    D = K + 1
+    from oracle import conv as OC, pipeline as P
+    if two_d:
+        wg = OC.toeplitz_generator(K, B)
+        e2 = P.relative_error(out.cpu().numpy(), OC.toeplitz_apply_2d(cn, wg, wg))
+    else:
+        e2 = P.relative_error(out.cpu().numpy(), P.clean_reference_1d(cn, B))
+    D = (2 * K + 2) if two_d else K + 1
     fl = qfft_work(D, Rh)
     ms_q, nq = per["qfft"]
     res = {
@@ -747,10 +769,14 @@ def bench_qfft(args, wl):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"qfft_example1_k20: the paper's Example 1 (Gaussian-windowed "
-                               f"sines, noise std 0.02, N = 2^{K - 1} - 1 samples padded to "
-                               f"2^{K}), kernel resolution 4 dx, R_max = {R}, R^_max = {Rh}, "
-                               f"complex FP64 transforms", "K": K, "samples": n},
+        "config": {"workload": (f"{args.workload}: the paper's Example 3 (2-D, noise std 0.1, "
+                                f"(2^{K - 1} - 1)^2 samples padded to 2^{K} x 2^{K}), kernel "
+                                f"resolution 2 dx per axis" if two_d else
+                                f"{args.workload}: the paper's Example 1 (Gaussian-windowed "
+                                f"sines, noise std 0.02, N = 2^{K - 1} - 1 samples padded to "
+                                f"2^{K}), kernel resolution 4 dx")
+                               + f", R_max = {R}, R^_max = {Rh}, complex FP64 transforms",
+                   "K": K, "samples": n},
         "step_ms_p10_p50_p90": [spread[int(0.1 * (len(spread) - 1))], spread[len(spread) // 2],
                                 spread[int(0.9 * (len(spread) - 1))]],
         "kernels_ms_per_step": {c: round(v[0], 3) for c, v in per.items() if v[1]},
@@ -766,8 +792,10 @@ def bench_qfft(args, wl):
                      "work": f"{fl:.3e} flops per transform (model in bench.py qfft_work), "
                              f"3 transforms per step in {nq} launches"},
         "e2_vs_clean_convolution": e2,
-        "paper_context": {"table_7_1_e2_qtt0": 0.0028, "table_7_2_seconds_k20_qtt0": 0.653,
-                          "hardware": "not stated in the paper"},
+        "paper_context": ({"table_7_1_e2_qtt0": 0.0151, "table_7_4_seconds_k10_qtt0": 0.9209,
+                           "hardware": "not stated in the paper"} if two_d else
+                          {"table_7_1_e2_qtt0": 0.0028, "table_7_2_seconds_k20_qtt0": 0.653,
+                           "hardware": "not stated in the paper"}),
     }
     if args.cpu_seconds > 0:
         from oracle import conv, qfft as QO, tt
@@ -777,9 +805,13 @@ def bench_qfft(args, wl):
         t_end = time.perf_counter() + args.cpu_seconds
         while not ts or (time.perf_counter() < t_end and len(ts) < 5):
             c0 = time.perf_counter()
-            F = tt.tt_svd(xn, eps, R)
+            F = tt.tt_svd(xn.ravel(), eps, R)
             W = tt.tt_svd(conv.toeplitz_generator(K, B), eps / 10.0)
-            QO.full(QO.conv_fft(F, W, 0.0, Rh, 0.0, wl["oversample"], wl["seed"])).real
+            if two_d:
+                QO.full(QO.conv_fft_2d(F, K, W, W, 0.0, Rh, 0.0, wl["oversample"],
+                                       wl["seed"])).real
+            else:
+                QO.full(QO.conv_fft(F, W, 0.0, Rh, 0.0, wl["oversample"], wl["seed"])).real
             ts.append(time.perf_counter() - c0)
         tmed = sorted(ts)[len(ts) // 2]
         res["cpu_baseline"] = {"value": n / tmed, "unit": "samples/s", "cores": threads,
