@@ -22,6 +22,13 @@
 // Gram matrix), the rotated columns are U Sigma and the accumulated rotation
 // is V.
 //
+// An image's transform is two-dimensional: the digits of each axis form a
+// block transformed by the stages above on its own.  Blocks run right to
+// left; a stage doubles only its block's bonds, the QR sweep still starts at
+// the first core and the truncation sweep stops at the block, and between
+// blocks one LQ makes the first core of the block to the right
+// right-orthonormal again (it carried that block's last butterfly).
+//
 // Every stage of one transform runs in one workgroup (the stages are
 // sequential and every matrix is at most 64 x 32 complex); the two forward
 // transforms of the convolution run in two workgroups of one launch.  Cores
