@@ -198,10 +198,15 @@ __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi isc
       // of split storage (A and V in different memories) does not take
       if (E > 64 || !std::is_same<MP, MPV>::value)
         sy_tridiag<NT, 8>(A, E, lda, dg, od, bt, pv);
+      else if (E <= 32)
+        sy_tridiag32w(A, E, lda, dg, od, bt, pv);
       else
         sy_tridiag64(A, E, lda, dg, od, bt, pv);
     } else {
-      sy_tridiag64(A, E, lda, dg, od, bt, pv);
+      if (E <= 32)
+        sy_tridiag32w(A, E, lda, dg, od, bt, pv);
+      else
+        sy_tridiag64(A, E, lda, dg, od, bt, pv);
     }
 #ifdef QTT_EIG_TIMING
     tt[1] = wall_clock64();

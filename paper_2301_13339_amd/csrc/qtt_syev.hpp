@@ -428,6 +428,146 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
   __syncthreads();
 }
 
+// Tridiagonalisation for E <= 32 on the first wave alone; the other waves
+// meet it only at the closing barrier.  Lane l holds column l & 31 of A (and
+// of X), rows 16 (l >> 5) .. 16 (l >> 5) + 15, so the two halves of a column
+// are one permlane32 swap apart: the column norm, A v, v^T X and p^T v are
+// sums over the lane's own 16 rows plus one swap, with no lane reduction.
+// The column, v and p reach every lane through LDS without a workgroup
+// barrier, and v is formed in LDS (the published column with rows <= j + 1
+// cleared by one store per lane, then v_{j+1}), so no lane masks its rows
+// against the step index.  Same reflectors and outputs as sy_tridiag64 (dg,
+// od, beta_j in bt[j], X = Q^T in A for rows and columns < E).
+// buf: >= 160 doubles.
+template <class MP>
+__device__ void sy_tridiag32w(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd buf) {
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x, c = l & 31, h = l >> 5;
+    ldsd colA = buf;       // column j as it stands, 32
+    ldsd colV = buf + 32;  // v of step j, 32
+    ldsd pb = buf + 64;    // p, 32
+    ldsd last = buf + 96;  // columns E-2 and E-1, 2 x 32
+    double a[16], x[16];
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+      const int r = 16 * h + ii;
+      const double t = A[r * lda + c];  // r, c < 32 < lda: in bounds
+      a[ii] = ((r < E) & (c < E)) ? t : 0.0;
+      x[ii] = (r == c) ? 1.0 : 0.0;
+    }
+    // LDS accesses of one wave complete in program order, and the fences
+    // keep the compiler from moving them across the exchange points
+    for (int j = 0; j + 2 < E; ++j) {
+      if (c == j) {  // lanes j and j + 32: column j (= row j)
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) {
+          colA[16 * h + ii] = a[ii];
+          colV[16 * h + ii] = a[ii];
+        }
+      }
+      if (l <= j + 1) colV[l] = 0.0;  // l <= j + 1 <= 30: rows that v leaves out
+      wave_lds_sync();
+      const double x0 = colA[j + 1], dj = colA[j];
+      double m[16];
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) m[ii] = colV[16 * h + ii];
+      double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 16; ii += 4) {
+        n0 = fma(m[ii], m[ii], n0);
+        n1 = fma(m[ii + 1], m[ii + 1], n1);
+        n2 = fma(m[ii + 2], m[ii + 2], n2);
+        n3 = fma(m[ii + 3], m[ii + 3], n3);
+      }
+      const double xs2 = sum_halves((n0 + n1) + (n2 + n3));  // same value in every lane
+      if (xs2 <= 1e-300 + 1e-32 * (xs2 + x0 * x0)) {          // already reduced (uniform)
+        if (l == 0) {
+          bt[j] = 0.0;
+          od[j] = x0;
+          dg[j] = dj;
+        }
+        continue;
+      }
+      const double s2 = xs2 + x0 * x0;
+      const double alpha = s2 * rsq_acc(s2);
+      const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+      const double v0 = x0 + sg * alpha;
+      const double beta = 2.0 * rcp_acc(xs2 + v0 * v0);
+      if (l == 0) colV[j + 1] = v0;
+      wave_lds_sync();
+      double vi[16];
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) vi[ii] = colV[16 * h + ii];
+      const double vc = colV[c];
+      double s0 = 0.0, s1 = 0.0, s2a = 0.0, s3 = 0.0, u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 16; ii += 4) {
+        s0 = fma(a[ii], vi[ii], s0);
+        s1 = fma(a[ii + 1], vi[ii + 1], s1);
+        s2a = fma(a[ii + 2], vi[ii + 2], s2a);
+        s3 = fma(a[ii + 3], vi[ii + 3], s3);
+        u0 = fma(x[ii], vi[ii], u0);
+        u1 = fma(x[ii + 1], vi[ii + 1], u1);
+        u2 = fma(x[ii + 2], vi[ii + 2], u2);
+        u3 = fma(x[ii + 3], vi[ii + 3], u3);
+      }
+      const double p = beta * sum_halves((s0 + s1) + (s2a + s3));   // (beta A v)_c
+      const double bvx = beta * sum_halves((u0 + u1) + (u2 + u3));  // beta (v^T X)_c
+      if (h == 0) pb[c] = p;
+      if (l == 0) {
+        dg[j] = dj;
+        od[j] = -sg * alpha;
+        bt[j] = beta;
+      }
+      wave_lds_sync();
+      double pi[16];
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) pi[ii] = pb[16 * h + ii];
+      double k0 = 0.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 16; ii += 4) {
+        k0 = fma(pi[ii], vi[ii], k0);
+        k1 = fma(pi[ii + 1], vi[ii + 1], k1);
+        k2 = fma(pi[ii + 2], vi[ii + 2], k2);
+        k3 = fma(pi[ii + 3], vi[ii + 3], k3);
+      }
+      const double K = 0.5 * beta * sum_halves((k0 + k1) + (k2 + k3));
+      // A - v w^T - w v^T with w = p - K v: entry (i, c) loses
+      // v_i (p_c - 2 K v_c) + p_i v_c
+      const double g = p - 2.0 * K * vc;
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) {
+        a[ii] = fma(-vi[ii], g, fma(-pi[ii], vc, a[ii]));
+        x[ii] = fma(-bvx, vi[ii], x[ii]);
+      }
+    }
+    // trailing 2 x 2 block: columns E-2 and E-1
+    if (c == E - 2) {
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) last[16 * h + ii] = a[ii];
+    }
+    if (c == E - 1) {
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) last[32 + 16 * h + ii] = a[ii];
+    }
+    wave_lds_sync();
+    if (l == 0) {
+      if (E >= 2) {
+        dg[E - 2] = last[E - 2];
+        od[E - 2] = last[E - 1];
+        bt[E - 2] = 0.0;
+      }
+      if (E >= 1) {
+        dg[E - 1] = last[32 + E - 1];
+        bt[E - 1] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) A[(16 * h + ii) * lda + c] = x[ii];
+  }
+  __syncthreads();
+}
+
 // Z <- Q Z for the r <= 64 columns of Z (E <= 64 rows) with X = Q^T in A
 // (sy_tridiag64), as one product on the FP64 matrix cores: wave w forms the
 // 16-row block w of U = X^T Z, one 16 x 16 block per 16 columns.  All
@@ -745,26 +885,117 @@ __device__ void multisect(lds_ptr<const double> dn, lds_ptr<const double> e2n, i
     if (t < nk && l16 == 0) lam[g16 + t * NG16] = 0.5 * (l[t] + u[t]) * scale;
 }
 
+// Sturm counts on T padded to NE rows: beyond E the diagonal is 4 and the
+// squared off-diagonal 0 (tridiag_eigvals writes the padding), steps that
+// keep the sign of the minor and so add no change.  Same recurrence and
+// rescaling as sturm_counts; the signs of p_1 .. p_NE are shifted into a bit
+// mask, one alignbit per step, and the changes are counted once at the end:
+// with s_0 = 0 (p_0 = 1) and bit k of M holding s_{NE-k}, the changes are
+// the set bits of M xor (M >> 1).
+__device__ __forceinline__ unsigned int shift_sign(unsigned int m, double p) {
+  return __builtin_amdgcn_alignbit(m, (unsigned int)__double2hiint(p), 31);
+}
+
+template <int NE>
+__device__ __forceinline__ int sign_mask_changes(unsigned int mh, unsigned int ml) {
+  if constexpr (NE <= 32) {
+    return __popc(mh ^ (mh >> 1));
+  } else {
+    const unsigned long long m = ((unsigned long long)mh << 32) | ml;
+    return __popcll(m ^ (m >> 1));
+  }
+}
+
+// registers: av[i] = a_i, bv[i] = b_{i-1}^2 (bv[0] unused), NE <= 32
+template <int NE>
+__device__ __forceinline__ int sturm_count_reg(const double* av, const double* bv, double x) {
+  static_assert(NE <= 32, "one 32-bit sign mask");
+  double pm = 1.0, pc = av[0] - x;
+  unsigned int mh = shift_sign(0u, pc);
+#pragma unroll
+  for (int i = 1; i < NE; ++i) {
+    const double pn = fma(av[i] - x, pc, -bv[i] * pm);
+    mh = shift_sign(mh, pn);
+    pm = pc;
+    pc = pn;
+    if ((i & 7) == 0) {
+      const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pc), fabs(pm)));
+      pc = ldexp(pc, -ex);
+      pm = ldexp(pm, -ex);
+    }
+  }
+  return sign_mask_changes<NE>(mh, 0u);
+}
+
+// LDS operands, NE = 64: dn[0..64) and e2n[0..63) padded; loads in blocks of 8
+__device__ __forceinline__ int sturm_count_lds64(lds_ptr<const double> dn,
+                                                 lds_ptr<const double> e2n, double x) {
+  double pm = 1.0, pc = dn[0] - x;
+  unsigned int mh = shift_sign(0u, pc), ml = 0u;
+#pragma unroll
+  for (int i0 = 1; i0 < 64; i0 += 8) {
+    double av[8], bv[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      av[u] = (i0 + u < 64) ? dn[i0 + u] : 0.0;
+      bv[u] = (i0 + u < 64) ? e2n[i0 - 1 + u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = i0 + u;
+      if (i < 64) {
+        const double pn = fma(av[u] - x, pc, -bv[u] * pm);
+        if (i < 32)
+          mh = shift_sign(mh, pn);
+        else
+          ml = shift_sign(ml, pn);
+        pm = pc;
+        pc = pn;
+        if ((i & 7) == 0) {
+          const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(pc), fabs(pm)));
+          pc = ldexp(pc, -ex);
+          pm = ldexp(pm, -ex);
+        }
+      }
+    }
+  }
+  return sign_mask_changes<64>(mh, ml);
+}
+
 // Multisection for the K largest eigenvalues (K <= 256 / G) with a group of
 // G lanes per eigenvalue: group g brackets eigenvalue E-1-g (ascending
 // index) and narrows its bracket (G+1)x per pass with one Sturm count per
 // lane.  All brackets start equal and shrink by the same factor, so the pass
-// count is fixed up front.
-template <int NT, int G>
-__device__ void multisect_top(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E, int K,
-                              double lo, double hi, double width_stop, double scale, ldsd lam) {
+// count is fixed up front.  T is padded to NE rows; for NE <= 32 it is read
+// from LDS once and every pass runs on registers, for NE = 64 from LDS in
+// blocks of 8.
+template <int NT, int G, int NE>
+__device__ void multisect_top_pad(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E,
+                                  int K, double lo, double hi, double width_stop, double scale,
+                                  ldsd lam) {
   static_assert(NT == 256 && (G == 4 || G == 8 || G == 16), "lane groups of a 256-thread block");
   const int tid = threadIdx.x;
   const int grp = tid / G, lg = tid & (G - 1);
   const int k = E - 1 - grp;
-  const int gshift = (tid & 63) & ~(G - 1);  // first lane of the group within the wave
+  const int gshift = (tid & 63) & ~(G - 1);
   const double frac = (double)(lg + 1) * (1.0 / (double)(G + 1));
   const int passes = (int)ceil(log((hi - lo) / width_stop) / log((double)(G + 1)));
+  double av[NE <= 32 ? NE : 1], bv[NE <= 32 ? NE : 1];
+  if constexpr (NE <= 32) {
+#pragma unroll
+    for (int i = 0; i < NE; ++i) {
+      av[i] = dn[i];
+      bv[i] = (i >= 1) ? e2n[i - 1] : 0.0;
+    }
+  }
   double l = lo, u = hi;
   for (int it = 0; it < passes; ++it) {
     const double x = l + (u - l) * frac;
     int c;
-    sturm_counts<1>(dn, e2n, E, &x, &c);
+    if constexpr (NE <= 32)
+      c = sturm_count_reg<NE>(av, bv, x);
+    else
+      c = sturm_count_lds64(dn, e2n, x);
     const unsigned long long bal = __ballot(c > k);
     const unsigned int gb = (unsigned int)((bal >> gshift) & ((1ull << G) - 1));
     const int first = gb ? __builtin_ctz(gb) : G;
@@ -775,6 +1006,22 @@ __device__ void multisect_top(lds_ptr<const double> dn, lds_ptr<const double> e2
     u = nu;
   }
   if (lg == 0 && grp < K && k >= 0) lam[k] = 0.5 * (l + u) * scale;
+}
+
+template <int NT, int G>
+__device__ void multisect_top_any(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E,
+                                  int K, double lo, double hi, double width_stop, double scale,
+                                  ldsd lam) {
+  if (E <= 8)
+    multisect_top_pad<NT, G, 8>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
+  else if (E <= 16)
+    multisect_top_pad<NT, G, 16>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
+  else if (E <= 24)
+    multisect_top_pad<NT, G, 24>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
+  else if (E <= 32)
+    multisect_top_pad<NT, G, 32>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
+  else
+    multisect_top_pad<NT, G, 64>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
 }
 
 // All eigenvalues of T in ascending order into lam[0..E), to an absolute
@@ -798,6 +1045,13 @@ __device__ void tridiag_eigvals(lds_ptr<const double> dg, lds_ptr<const double> 
       e2[i] = fmax(b * b, 1e-60);
     }
   }
+  // padding to 64 rows for the fixed-length counts (multisect_top_pad):
+  // diagonal 4, off-diagonal 0 (dn, e2: >= 64 doubles)
+  if (E <= 64) {
+    for (int i = E + tid; i < 64; i += NT) dn[i] = 4.0;
+    for (int i = E - 1 + tid; i < 64; i += NT)
+      if (i >= 0) e2[i] = 0.0;
+  }
   __syncthreads();
   // scaled Gershgorin interval lies inside [-1, 1]; widen by the stop width
   const double ws = 1e-15;
@@ -809,11 +1063,11 @@ __device__ void tridiag_eigvals(lds_ptr<const double> dg, lds_ptr<const double> 
     // only the K largest (ascending slots E-K..E-1 of lam); finer groups
     // when fewer are wanted, fewer passes
     if (K <= 16)
-      multisect_top<NT, 16>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
+      multisect_top_any<NT, 16>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
     else if (K <= 32)
-      multisect_top<NT, 8>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
+      multisect_top_any<NT, 8>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
     else
-      multisect_top<NT, 4>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
+      multisect_top_any<NT, 4>(dn, e2, E, K, -1.0 - ws, 1.0 + ws, 2e-16, nrm, lam);
   } else if (nkmax <= 1)
     multisect<NT, 1>(dn, e2, E, -1.0 - ws, 1.0 + ws, ws, nrm, lam);
   else if (nkmax <= 2)
@@ -921,21 +1175,35 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
     wave_lds_sync();
     return;
   }
-  // sweeps: step t handles row i = t (top-down) or i = E-1-t (bottom-up)
+  // sweeps: step t handles row i = t (top-down) or i = E-1-t (bottom-up);
+  // T is loaded eight steps at a time, so one LDS latency per eight steps
+  // (the stores of the factors would otherwise order every load behind them)
   {
     const int i0 = hb ? E - 1 : 0;
     double dcur = dg[i0] - lm;
     if (fabs(dcur) < tiny) dcur = tiny;
-#pragma unroll 4
-    for (int t = 0; t + 1 < E; ++t) {
-      const int ie = hb ? E - 2 - t : t;      // off-diagonal entry b_ie
-      const int is = hb ? E - 1 - t : t;      // row of the stored factor
-      const int in = hb ? E - 2 - t : t + 1;  // next diagonal entry
-      const double bo = od[ie];
-      const double x = bo * rcp_acc(dcur);
-      if (act) own[is * ldz] = x;
-      dcur = (dg[in] - lm) - x * bo;
-      if (fabs(dcur) < tiny) dcur = tiny;
+    for (int t0 = 0; t0 + 1 < E; t0 += 8) {
+      double bo[8], dn[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u;
+        const bool in_range = t + 1 < E;
+        const int ie = in_range ? (hb ? E - 2 - t : t) : 0;      // off-diagonal entry b_ie
+        const int in = in_range ? (hb ? E - 2 - t : t + 1) : 0;  // next diagonal entry
+        bo[u] = od[ie];
+        dn[u] = dg[in];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u;
+        if (t + 1 < E) {  // uniform
+          const int is = hb ? E - 1 - t : t;  // row of the stored factor
+          const double x = bo[u] * rcp_acc(dcur);
+          if (act) own[is * ldz] = x;
+          dcur = (dn[u] - lm) - x * bo[u];
+          if (fabs(dcur) < tiny) dcur = tiny;
+        }
+      }
     }
   }
   wave_lds_sync();
@@ -975,14 +1243,23 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
     const int steps = hb ? (E - 1 - tw) : tw;
     const int smax = (tw > E - 1 - tw) ? tw : E - 1 - tw;
     double zp = 1.0;
-#pragma unroll 4
-    for (int t = 0; t < smax; ++t) {
-      if (t < steps) {
-        const int i = hb ? tw + 1 + t : tw - 1 - t;
-        const double x = act ? own[i * ldz] : 0.0;
-        zp = -x * zp;
-        if (act) zc[i * ldz] = zp;
-        nrm2 = fma(zp, zp, nrm2);
+    for (int t0 = 0; t0 < smax; t0 += 8) {
+      double xs[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u;
+        const int i = (t < steps) ? (hb ? tw + 1 + t : tw - 1 - t) : tw;
+        xs[u] = own[i * ldz];  // 0 <= i < E
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u;
+        if (t < steps) {
+          const int i = hb ? tw + 1 + t : tw - 1 - t;
+          zp = -(act ? xs[u] : 0.0) * zp;
+          if (act) zc[i * ldz] = zp;
+          nrm2 = fma(zp, zp, nrm2);
+        }
       }
     }
   }
@@ -995,8 +1272,14 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
   if (act) {
     const int half = (E + 1) / 2;
     const int lo = hb ? half : 0, hi = hb ? E : half;
-#pragma unroll 4
-    for (int i = lo; i < hi; ++i) zc[i * ldz] *= inv;
+    for (int i0 = lo; i0 < hi; i0 += 8) {
+      double zs[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) zs[u] = zc[(i0 + u < hi ? i0 + u : lo) * ldz];
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (i0 + u < hi) zc[(i0 + u) * ldz] = zs[u] * inv;
+    }
   }
   wave_lds_sync();
 }
