@@ -1175,31 +1175,34 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
     wave_lds_sync();
     return;
   }
-  // sweeps: step t handles row i = t (top-down) or i = E-1-t (bottom-up);
-  // T is loaded eight steps at a time, so one LDS latency per eight steps
-  // (the stores of the factors would otherwise order every load behind them)
+  // The two halves mirror each other: every row index below is linear in
+  // the step with slope dir (+1 top-down, -1 bottom-up), so the lanes
+  // compute their indices without branches.  Lanes without a vector (b >= r)
+  // run the same steps on lam[0] and write only columns that no later step
+  // reads.
+  const int dir = hb ? -1 : 1;
+  // sweeps: step t handles row is = t (top-down) or E-1-t (bottom-up), with
+  // off-diagonal b_ie and next diagonal entry a_in; T is loaded eight steps
+  // at a time (the stores of the factors would otherwise order every load
+  // behind them)
   {
-    const int i0 = hb ? E - 1 : 0;
-    double dcur = dg[i0] - lm;
+    const int is0 = hb ? E - 1 : 0, ie0 = hb ? E - 2 : 0, in0 = hb ? E - 2 : 1;
+    double dcur = dg[is0] - lm;
     if (fabs(dcur) < tiny) dcur = tiny;
     for (int t0 = 0; t0 + 1 < E; t0 += 8) {
       double bo[8], dn[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        const int t = t0 + u;
-        const bool in_range = t + 1 < E;
-        const int ie = in_range ? (hb ? E - 2 - t : t) : 0;      // off-diagonal entry b_ie
-        const int in = in_range ? (hb ? E - 2 - t : t + 1) : 0;  // next diagonal entry
-        bo[u] = od[ie];
-        dn[u] = dg[in];
+        const int t = (t0 + u + 1 < E) ? t0 + u : t0;  // past the end: a valid row
+        bo[u] = od[ie0 + dir * t];
+        dn[u] = dg[in0 + dir * t];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int t = t0 + u;
         if (t + 1 < E) {  // uniform
-          const int is = hb ? E - 1 - t : t;  // row of the stored factor
           const double x = bo[u] * rcp_acc(dcur);
-          if (act) own[is * ldz] = x;
+          own[(is0 + dir * t) * ldz] = x;
           dcur = (dn[u] - lm) - x * bo[u];
           if (fabs(dcur) < tiny) dcur = tiny;
         }
@@ -1207,21 +1210,40 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
     }
   }
   wave_lds_sync();
-  // twist index: lane hb scans i in [lo, hi)
+  // twist index: lane hb scans i in [lo, hi), downward
   int best = -1;
   double gbest = 0.0;
   {
     const int half = (E + 1) / 2;
     const int lo = hb ? half : 0, hi = hb ? E : half;
-#pragma unroll 4
-    for (int i = hi - 1; i >= lo; --i) {
-      double g = dg[i] - lm;
-      if (i > 0) g -= (act ? zc[(i - 1) * ldz] : 0.0) * od[i - 1];
-      if (i + 1 < E) g -= (act ? Z[(i + 1) * ldz + b + 32] : 0.0) * od[i];
-      const double ag = fabs(g);
-      if (best < 0 || ag < gbest) {
-        best = i;
-        gbest = ag;
+    const int n = hi - lo, nmax = E - half > half ? E - half : half;
+    for (int t0 = 0; t0 < nmax; t0 += 8) {
+      // the operands of eight rows first, then the scan on registers
+      double dv[8], zl[8], ol[8], zu[8], ou[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u;
+        const int i = hi - 1 - (t < n ? t : 0);
+        const int im = i > 0 ? i - 1 : 0, ip = i + 1 < E ? i + 1 : i;
+        dv[u] = dg[i];
+        zl[u] = zc[im * ldz];
+        ol[u] = od[im];
+        zu[u] = Z[ip * ldz + b + 32];
+        ou[u] = od[i];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int t = t0 + u;
+        const int i = hi - 1 - t;
+        double g = dv[u] - lm;
+        const double g1 = g - (act ? zl[u] : 0.0) * ol[u];
+        g = (i > 0) ? g1 : g;
+        const double g2 = g - (act ? zu[u] : 0.0) * ou[u];
+        g = (i + 1 < E) ? g2 : g;
+        const double ag = fabs(g);
+        const bool take = (t < n) & ((best < 0) | (ag < gbest));
+        best = take ? i : best;
+        gbest = take ? ag : gbest;
       }
     }
   }
@@ -1237,7 +1259,10 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
     best = (b1 >= 0 && (b0 < 0 || g1 <= g0)) ? b1 : b0;
   }
   const int tw = best;
-  // outward recurrences from the twist: lane hb = 0 up, hb = 1 down
+  // outward recurrences from the twist: lane hb = 0 up (z_i = -l_i z_{i+1}),
+  // hb = 1 down (z_i = -u_i z_{i-1}); row i = tw - dir (t + 1).  A lane whose
+  // steps are done repeats its last value into row tw, which is set to 1
+  // afterwards.
   double nrm2 = 0.0;
   {
     const int steps = hb ? (E - 1 - tw) : tw;
@@ -1248,17 +1273,20 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int t = t0 + u;
-        const int i = (t < steps) ? (hb ? tw + 1 + t : tw - 1 - t) : tw;
-        xs[u] = own[i * ldz];  // 0 <= i < E
+        const int i = tw - dir * ((t < steps ? t : -1) + 1);  // 0 <= i < E
+        xs[u] = own[i * ldz];
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int t = t0 + u;
-        if (t < steps) {
-          const int i = hb ? tw + 1 + t : tw - 1 - t;
-          zp = -(act ? xs[u] : 0.0) * zp;
-          if (act) zc[i * ldz] = zp;
-          nrm2 = fma(zp, zp, nrm2);
+        if (t < smax) {  // uniform
+          const bool on = t < steps;
+          const int i = tw - dir * ((on ? t : -1) + 1);
+          const double zn = -(act ? xs[u] : 0.0) * zp;
+          zp = on ? zn : zp;
+          zc[i * ldz] = zp;
+          const double n2 = fma(zp, zp, nrm2);
+          nrm2 = on ? n2 : nrm2;
         }
       }
     }
@@ -1266,7 +1294,7 @@ __device__ void tridiag_vec_pair(lds_ptr<const double> dg, lds_ptr<const double>
   // total squared norm: both halves plus z_tw = 1
   const double tot = sum_halves(nrm2) + 1.0;
   wave_lds_sync();
-  if (act && hb == 0) zc[tw * ldz] = 1.0;
+  if (hb == 0) zc[tw * ldz] = 1.0;
   wave_lds_sync();
   const double inv = rsq_acc(tot);
   if (act) {
