@@ -29,8 +29,10 @@ namespace qtt {
 // ---------------------------------------------------------- lane reductions
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, 0xF, 0xF, false);
+  // every lane reads a valid lane under the patterns used here, so no old
+  // value is needed (mov_dpp, not update_dpp: no register initialisation)
+  const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 // sum over the 16 lanes of a DPP row (all lanes of the row get the sum)
