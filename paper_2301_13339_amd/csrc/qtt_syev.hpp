@@ -576,31 +576,38 @@ __device__ void sy_tridiag32w(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, l
 // threads; Z is read completely before it is overwritten.
 typedef double syev_f64x4 __attribute__((ext_vector_type(4)));
 
-template <class MP>
-__device__ void backtr_gemm64(MP X, int E, int lda, MP Z, int r) {
+template <int NBJ, class MP>
+__device__ __forceinline__ void backtr_gemm64_n(MP X, int E, int lda, MP Z, int r) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
-  const int nbj = (r + 15) >> 4;  // <= 4
-  syev_f64x4 acc[4];
+  syev_f64x4 acc[NBJ];
 #pragma unroll
-  for (int t = 0; t < 4; ++t) acc[t] = syev_f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < E; k0 += 4) {
-    const int c = k0 + lk;
-    const bool cin = c < E;
-    const int cc = cin ? c : 0;
-    const double a = X[cc * lda + 16 * w + lr];  // X^T(i, c), i = 16w + lr < 64 <= lda
+  for (int t = 0; t < NBJ; ++t) acc[t] = syev_f64x4{0.0, 0.0, 0.0, 0.0};
+  // sixteen rows of Z per pass, four products each, with no branch inside
+  // (operands loaded first, accumulators stay in place)
+  for (int k16 = 0; k16 < E; k16 += 16) {
+    double a[4], bz[4][NBJ];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      if (t < nbj) {  // uniform
-        const double bz = Z[cc * lda + 16 * t + lr];  // column < 64 <= lda
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(cin ? a : 0.0, cin ? bz : 0.0, acc[t], 0,
-                                                      0, 0);
+    for (int u = 0; u < 4; ++u) {
+      const int c = k16 + 4 * u + lk;
+      const bool cin = c < E;
+      const int cc = cin ? c : 0;
+      const double av = X[cc * lda + 16 * w + lr];  // X^T(i, c), i = 16w + lr < 64 <= lda
+      a[u] = cin ? av : 0.0;
+#pragma unroll
+      for (int t = 0; t < NBJ; ++t) {
+        const double bv = Z[cc * lda + 16 * t + lr];  // column < 64 <= lda
+        bz[u][t] = cin ? bv : 0.0;
       }
     }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int t = 0; t < NBJ; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], bz[u][t], acc[t], 0, 0, 0);
   }
   __syncthreads();  // every wave has read Z
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    if (t >= nbj) break;
+  for (int t = 0; t < NBJ; ++t) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       const int i = 16 * w + 4 * e + lk, b = 16 * t + lr;
@@ -608,6 +615,19 @@ __device__ void backtr_gemm64(MP X, int E, int lda, MP Z, int r) {
     }
   }
   __syncthreads();
+}
+
+template <class MP>
+__device__ void backtr_gemm64(MP X, int E, int lda, MP Z, int r) {
+  const int nbj = (r + 15) >> 4;  // <= 4, uniform
+  if (nbj <= 1)
+    backtr_gemm64_n<1>(X, E, lda, Z, r);
+  else if (nbj == 2)
+    backtr_gemm64_n<2>(X, E, lda, Z, r);
+  else if (nbj == 3)
+    backtr_gemm64_n<3>(X, E, lda, Z, r);
+  else
+    backtr_gemm64_n<4>(X, E, lda, Z, r);
 }
 
 // x summed over the four DPP rows at the same position, in every lane
@@ -631,15 +651,23 @@ __device__ bool polish_backtr64(MP A, int E, int lda, MP Z, int r, ldsd cs) {
   ldsd dev = cs + 32 * LC;  // per-wave max |C - I|
   const int nb = (r + 15) >> 4;  // <= 2
   double dmax = 0.0;
-  for (int blk = w; blk < nb * nb; blk += 4) {  // <= 4 blocks: one per wave
+  if (w < nb * nb) {  // <= 4 blocks: one per wave
+    const int blk = w;
     const int bi = blk / nb, bj = blk - bi * nb;
     syev_f64x4 acc = syev_f64x4{0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < E; k0 += 4) {
-      const int c = k0 + lk;
-      const bool cin = c < E;
-      const int cc = cin ? c : 0;
-      const double a = Z[cc * lda + 16 * bi + lr], bz = Z[cc * lda + 16 * bj + lr];
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(cin ? a : 0.0, cin ? bz : 0.0, acc, 0, 0, 0);
+    for (int k16 = 0; k16 < E; k16 += 16) {  // operands first, no branch among the products
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = k16 + 4 * u + lk;
+        const bool cin = c < E;
+        const int cc = cin ? c : 0;
+        const double a = Z[cc * lda + 16 * bi + lr], bz = Z[cc * lda + 16 * bj + lr];
+        av[u] = cin ? a : 0.0;
+        bv[u] = cin ? bz : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
@@ -669,14 +697,21 @@ __device__ bool polish_backtr64(MP A, int E, int lda, MP Z, int r, ldsd cs) {
     const int row = 16 * rb + lr;
     const bool rin = row < E;
     const int rr = rin ? row : 0;
-    for (int k0 = 0; k0 < r; k0 += 4) {
-      const int kk = k0 + lk;
-      const bool kin = kk < r;
-      const int kc = kin ? kk : 0;
-      const double a = Z[rr * lda + kc];
-      const double b = S[kc * LC + 16 * cb + lr];
-      zo[t] = __builtin_amdgcn_mfma_f64_16x16x4f64((rin & kin) ? a : 0.0, kin ? b : 0.0, zo[t],
-                                                   0, 0, 0);
+    for (int k16 = 0; k16 < r; k16 += 16) {  // operands first, no branch among the products
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k16 + 4 * u + lk;
+        const bool kin = kk < r;
+        const int kc = kin ? kk : 0;
+        const double a = Z[rr * lda + kc];
+        const double b = S[kc * LC + 16 * cb + lr];
+        av[u] = (rin & kin) ? a : 0.0;
+        bv[u] = kin ? b : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        zo[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], zo[t], 0, 0, 0);
     }
   }
   __syncthreads();  // every wave has read Z
