@@ -504,15 +504,33 @@ __global__ void __launch_bounds__(256) k_project_mfma(const T* Ain, double B, in
 #pragma unroll
   for (int t = 0; t < GPW; ++t) g[t] = f64x4{0.0, 0.0, 0.0, 0.0};
   const long long nstage = (rowsA + SR - 1) / SR;
+  // the stage's 32 x WA block, read one stage ahead into registers so that
+  // its HBM latency overlaps the products of the current stage
+  constexpr int PER = SR * kMaxM / 256;
+  double pre[PER];
+  auto fetch = [&](long long sidx) {
+    const long long r0 = sidx * SR;
+    const int nr = (int)((rowsA - r0) < SR ? (rowsA - r0) : SR);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = tid + 256 * j;
+      const int row = e / WA, c = e - row * WA;
+      pre[j] = (e < SR * WA && row < nr) ? sample<T, GEN>(Ain, (r0 + row) * WA + c, B, nk) : 0.0;
+    }
+  };
+  if ((long long)blockIdx.x < nstage) fetch(blockIdx.x);
   for (long long sidx = blockIdx.x; sidx < nstage; sidx += gridDim.x) {
     const long long r0 = sidx * SR;
     const int nr = (int)((rowsA - r0) < SR ? (rowsA - r0) : SR);
     __syncthreads();  // At, Ys of the previous stage consumed (Us written)
-    for (int e = tid; e < SR * WA; e += 256) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = tid + 256 * j;
       const int row = e / WA, c = e - row * WA;
-      At[c * LT + row] = row < nr ? sample<T, GEN>(Ain, (r0 + row) * WA + c, B, nk) : 0.0;
+      if (e < SR * WA) At[c * LT + row] = pre[j];
     }
     __syncthreads();
+    if (sidx + gridDim.x < nstage) fetch(sidx + gridDim.x);
     // Y = A U
     {
       const int rb = w & 1;
@@ -523,11 +541,22 @@ __global__ void __launch_bounds__(256) k_project_mfma(const T* Ain, double B, in
         f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
         const int col = 16 * cb + lr;
         const bool cin = col < r;
-        for (int k0 = 0; k0 < WA; k0 += 4) {
-          const int kk = k0 + lk;
-          const double a = kk < WA ? At[kk * LT + 16 * rb + lr] : 0.0;
-          const double bv = (kk < WA && cin) ? Us[kk * r + col] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        // sixteen rows of U per pass: operands first, then four products
+        for (int k16 = 0; k16 < WA; k16 += 16) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kk = k16 + 4 * u + lk;
+            const bool kin = kk < WA;
+            const int kc = kin ? kk : 0;
+            const double a = At[kc * LT + 16 * rb + lr];
+            const double b = Us[kc * r + (cin ? col : 0)];
+            av[u] = kin ? a : 0.0;
+            bv[u] = (kin && cin) ? b : 0.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u)
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
