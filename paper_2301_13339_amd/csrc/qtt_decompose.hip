@@ -104,17 +104,28 @@ __device__ __forceinline__ void level_gram_acc(const T* x, double B, int nk, lon
   gsum = 0.0;
   fin = 1;
   const long long nstage = (rows + SR - 1) / SR;
-  for (long long sidx = bid; sidx < nstage; sidx += nblk) {
+  // the next stage is read into registers while the current one is summed
+  constexpr int PER = SR * W / 256;
+  double pre[PER];
+  auto fetch = [&](long long sidx) {
     const long long r0 = sidx * SR;
-    const long long base = r0 * W;
-    for (int e = tid; e < SR * W; e += 256) {
-      double v = 0.0;
-      if (r0 + e / W < rows) v = sample<T, GEN>(x, base + e, B, nk);
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const int e = tid + 256 * j;
+      pre[j] = (r0 + e / W < rows) ? sample<T, GEN>(x, r0 * W + e, B, nk) : 0.0;
+    }
+  };
+  if (bid < nstage) fetch(bid);
+  for (long long sidx = bid; sidx < nstage; sidx += nblk) {
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+      const double v = pre[j];
       fin &= finite_d(v);
       gsum += v;
-      st[e] = v;
+      st[tid + 256 * j] = v;
     }
     __syncthreads();
+    if (sidx + nblk < nstage) fetch(sidx + nblk);
     for (int rr = 0; rr < SR; ++rr) {
       double xa[4], xb[4];
 #pragma unroll
