@@ -223,47 +223,46 @@ int launch_reduce(const double* partials, int pstride, int nparts, int count, do
 
 // ------------------------------------------------------ small LDS products
 // C (M x N) = A (M x K) B (K x N) with all operands in LDS: A(i, k) =
-// A[i*ai + k*ak], B(k, j) = B[k*bk + j*bj].  The 256 threads form a 16 x 16
-// grid and each keeps a 4 x 4 tile of C in registers (64 x 64 per pass over
-// the grid), so every pair of loads feeds four FMAs and the sixteen
-// accumulators are independent.  store(i, j, v) receives the results.
+// A[i*ai + k*ak], B(k, j) = B[k*bk + j*bj]; store(i, j, v) receives the
+// results.  On the FP64 matrix cores: 16 x 16 blocks of C spread
+// over the four waves, and for each block the operands of sixteen k loaded
+// before four MFMAs (v_mfma_f64_16x16x4f64: lane (lk, lr) supplies
+// A(16 bi + lr, k + lk) and B(k + lk, 16 bj + lr) and receives
+// C(16 bi + 4 e + lk, 16 bj + lr) in element e).  Operands outside M, N, K
+// enter as zeros.
 template <class F>
-__device__ __forceinline__ void lds_gemm(int M, int N, int K, lds_ptr<const double> A, int ai,
-                                         int ak, lds_ptr<const double> B, int bk, int bj,
-                                         F store) {
-  const int ty = threadIdx.x >> 4, tx = threadIdx.x & 15;
-  for (int i0 = 0; i0 < M; i0 += 64)
-    for (int j0 = 0; j0 < N; j0 += 64) {
-      const int ib = i0 + 4 * ty, jb = j0 + 4 * tx;
-      if (ib >= M || jb >= N) continue;
-      double acc[4][4];
+__device__ __forceinline__ void lds_gemm_mfma(int M, int N, int K, lds_ptr<const double> A,
+                                              int ai, int ak, lds_ptr<const double> B, int bk,
+                                              int bj, F store) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, lr = l & 15, lk = l >> 4;
+  const int mb = (M + 15) >> 4, nb = (N + 15) >> 4;
+  for (int blk = w; blk < mb * nb; blk += 4) {  // wave-uniform
+    const int bi = blk / nb, bjb = blk - bi * nb;
+    const int row = 16 * bi + lr, col = 16 * bjb + lr;
+    const bool rin = row < M, cin = col < N;
+    const int rc = rin ? row : 0, cc = cin ? col : 0;
+    syev_f64x4 acc = syev_f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int k16 = 0; k16 < K; k16 += 16) {
+      double av[4], bv[4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c) acc[a][c] = 0.0;
-      int ia[4], jc[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) ia[a] = (ib + a < M ? ib + a : M - 1) * ai;  // clamped rows: in bounds, results unused
-#pragma unroll
-      for (int c = 0; c < 4; ++c) jc[c] = (jb + c < N ? jb + c : N - 1) * bj;
-#pragma unroll 2
-      for (int k = 0; k < K; ++k) {
-        double xa[4], xb[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) xa[a] = A[ia[a] + k * ak];
-#pragma unroll
-        for (int c = 0; c < 4; ++c) xb[c] = B[k * bk + jc[c]];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int c = 0; c < 4; ++c) acc[a][c] = fma(xa[a], xb[c], acc[a][c]);
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k16 + 4 * u + lk;
+        const bool kin = kk < K;
+        const int kc = kin ? kk : 0;
+        const double a = A[rc * ai + kc * ak];
+        const double b = B[kc * bk + cc * bj];
+        av[u] = (rin & kin) ? a : 0.0;
+        bv[u] = (cin & kin) ? b : 0.0;
       }
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-          if (ib + a < M && jb + c < N) store(ib + a, jb + c, acc[a][c]);
+      for (int u = 0; u < 4; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * bi + 4 * e + lk, j = 16 * bjb + lr;
+      if (i < M && j < N) store(i, j, acc[e]);
+    }
+  }
 }
 
 // ------------------------------------------------------------- level eig
@@ -317,7 +316,7 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
     {
       ldsd T1l = lds(T1);
       for (int i = 0; i < 2; ++i)
-        lds_gemm(w, rp, half, lds<const double>(V + half * i), LDA, 1, lds<const double>(Phi), 32, 1,
+        lds_gemm_mfma(w, rp, half, lds<const double>(V + half * i), LDA, 1, lds<const double>(Phi), 32, 1,
                  [&](int c, int a, double v) { T1l[c * m + i * rp + a] = v; });
     }
     __syncthreads();
@@ -325,7 +324,7 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
     {
       ldsd Al = lds(A);
       for (int i = 0; i < 2; ++i)
-        lds_gemm(rp, m, half, lds<const double>(Phi), 1, 32, lds<const double>(T1 + half * i * m), m,
+        lds_gemm_mfma(rp, m, half, lds<const double>(Phi), 1, 32, lds<const double>(T1 + half * i * m), m,
                  1, [&](int a, int col, double v) { Al[(i * rp + a) * LDA + col] = v; });
     }
     __syncthreads();
@@ -352,7 +351,7 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
     {
       ldsd T1l = lds(T1);
       for (int i = 0; i < 2; ++i)
-        lds_gemm(half, r, rp, lds<const double>(Phi), 32, 1, lds<const double>(V + rp * i * LDA), LDA,
+        lds_gemm_mfma(half, r, rp, lds<const double>(Phi), 32, 1, lds<const double>(V + rp * i * LDA), LDA,
                  1, [&](int cl, int b, double v) { T1l[(cl + half * i) * r + b] = v; });
     }
     __syncthreads();
@@ -769,9 +768,9 @@ __device__ void tail_steps(double* smem, const T* Xin, double B, int nk, int k0,
       ldsd Al = lds(A);
       auto st = [&](int i, int j, double v) { Al[i * LDA + j] = v; };
       if (!dual)
-        lds_gemm(E, E, n, lds<const double>(X), 1, m, lds<const double>(X), m, 1, st);
+        lds_gemm_mfma(E, E, n, lds<const double>(X), 1, m, lds<const double>(X), m, 1, st);
       else
-        lds_gemm(E, E, m, lds<const double>(X), m, 1, lds<const double>(X), 1, m, st);
+        lds_gemm_mfma(E, E, m, lds<const double>(X), m, 1, lds<const double>(X), 1, m, st);
     }
     __syncthreads();
 #ifdef QTT_EIG_TIMING
@@ -794,7 +793,7 @@ __device__ void tail_steps(double* smem, const T* Xin, double B, int nk, int k0,
       }
     } else {
       // U[:, b] = X^T v_b / sigma_b
-      lds_gemm(m, r, n, lds<const double>(X), 1, m, lds<const double>(V), LDA, 1,
+      lds_gemm_mfma(m, r, n, lds<const double>(X), 1, m, lds<const double>(V), LDA, 1,
                [&](int c, int b, double v) {
                  const double sg = lam[b] > 0.0 ? sqrt(lam[b]) : 0.0;
                  const int i = c / rp, a = c - i * rp;
@@ -805,7 +804,7 @@ __device__ void tail_steps(double* smem, const T* Xin, double B, int nk, int k0,
       // Y (n x r, dense) into A, which the solve no longer needs
       ldsd Yl = lds(A);
       if (!dual) {
-        lds_gemm(n, r, m, lds<const double>(X), m, 1, lds<const double>(V), LDA, 1,
+        lds_gemm_mfma(n, r, m, lds<const double>(X), m, 1, lds<const double>(V), LDA, 1,
                  [&](int row, int b, double v) { Yl[row * r + b] = v; });
       } else {
         for (int e = tid; e < n * r; e += NT) {
