@@ -150,6 +150,90 @@ __device__ inline int sturm_below(lds_ptr<const double> dg, lds_ptr<const double
   return c;
 }
 
+// Eigenpairs of a symmetric E x E matrix, E = 2 or 4, by cyclic Jacobi in
+// one lane on registers (orders this small would spend most of the
+// reduction, multisection and twisted factorisation on synchronisation):
+// rotations J of (p, q) with tan of twice the angle 2 a_pq / (a_qq - a_pp),
+// the smaller root t, A <- J^T A J, V <- V J, sweeps until the off-diagonal
+// mass is below 1e-34 of the diagonal's.  la: ascending eigenvalues; V:
+// eigenvectors as columns in descending order of eigenvalue.
+template <int E, class MP>
+__device__ void jacobi_small(MP A, MP V, int lda, ldsd la) {
+  double a[E][E], v[E][E];
+#pragma unroll
+  for (int i = 0; i < E; ++i)
+#pragma unroll
+    for (int j = 0; j < E; ++j) {
+      a[i][j] = 0.5 * (A[i * lda + j] + A[j * lda + i]);
+      v[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+  for (int sweep = 0; sweep < 12; ++sweep) {
+    double off = 0.0, dia = 0.0;
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      dia = fma(a[i][i], a[i][i], dia);
+#pragma unroll
+      for (int j = i + 1; j < E; ++j) off = fma(a[i][j], a[i][j], off);
+    }
+    if (!(off > 1e-34 * dia)) break;
+#pragma unroll
+    for (int p = 0; p < E; ++p)
+#pragma unroll
+      for (int q = p + 1; q < E; ++q) {
+        const double apq = a[p][q];
+        if (apq == 0.0) continue;
+        // divisions and square roots from the hardware estimates with Newton
+        // steps (rcp_acc, rsq_acc): one lane's chain of dependent operations
+        const double th = (a[q][q] - a[p][p]) * rcp_acc(2.0 * apq);
+        const double th2 = fma(th, th, 1.0);
+        const double t = fabs(th) > 1e150 ? 0.5 * rcp_acc(th)
+                                          : copysign(1.0, th) * rcp_acc(fabs(th) + th2 * rsq_acc(th2));
+        const double c = rsq_acc(fma(t, t, 1.0)), s = t * c;
+        a[p][p] -= t * apq;
+        a[q][q] += t * apq;
+        a[p][q] = a[q][p] = 0.0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          if (r == p || r == q) continue;
+          const double arp = a[r][p], arq = a[r][q];
+          a[r][p] = a[p][r] = c * arp - s * arq;
+          a[r][q] = a[q][r] = s * arp + c * arq;
+        }
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const double vrp = v[r][p], vrq = v[r][q];
+          v[r][p] = c * vrp - s * vrq;
+          v[r][q] = s * vrp + c * vrq;
+        }
+      }
+  }
+  // descending order (selection sort, columns of v with their values)
+  double d[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) d[i] = a[i][i];
+#pragma unroll
+  for (int i = 0; i < E; ++i)
+#pragma unroll
+    for (int j = i + 1; j < E; ++j)
+      if (d[j] > d[i]) {
+        const double t = d[i];
+        d[i] = d[j];
+        d[j] = t;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const double u = v[r][i];
+          v[r][i] = v[r][j];
+          v[r][j] = u;
+        }
+      }
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    la[E - 1 - i] = d[i];
+#pragma unroll
+    for (int r = 0; r < E; ++r) V[r * lda + i] = v[r][i];
+  }
+}
+
 // any_basis: the caller uses only the kept columns of V as a basis (not the
 // eigenvalues, and not the vectors as singular vectors).  Then a step whose
 // rank is E by the rule (the smallest eigenvalue above tau2, the cap not
@@ -188,11 +272,23 @@ __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi isc
   tt[0] = wall_clock64();
 #endif
   double tnrm = 0.0;  // Gershgorin bound of T
+  // orders 2 and 4: every eigenpair by jacobi_small
+  const bool small = std::is_same<MP, MPV>::value && finite && (E == 2 || E == 4);
   // eigenvalues computed: all when the singular values are reported, the cap
   // does not bind or the tolerance is zero, else the cap largest (the rank
   // rule then works from the trace)
-  const int K = (so.sv || cap >= E || !(tau2 > 0.0)) ? E : cap;
-  if (finite) {
+  const int K = (small || so.sv || cap >= E || !(tau2 > 0.0)) ? E : cap;
+  if (small) {
+    if constexpr (std::is_same<MP, MPV>::value) {
+      if (tid == 0) {
+        if (E == 2)
+          jacobi_small<2>(A, V, lda, la);
+        else
+          jacobi_small<4>(A, V, lda, la);
+      }
+    }
+    __syncthreads();
+  } else if (finite) {
     if constexpr (BIG) {
       // the E <= 64 reduction leaves Q^T in A, which the back transformation
       // of split storage (A and V in different memories) does not take
@@ -269,6 +365,18 @@ __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi isc
   }
   __syncthreads();
   const int r = iscr[2];
+  if (small) {  // V holds every eigenvector, in order
+#ifdef QTT_EIG_TIMING
+    if (tid == 0 && so.dbg) {
+      so.dbg[k] = E;
+      int* t5 = so.dbg + 64 + 5 * k;
+      t5[0] = 0;
+      t5[1] = (int)(wall_clock64() - tt[0]);
+      t5[2] = t5[3] = t5[4] = 0;
+    }
+#endif
+    return r;
+  }
   if (!finite) {
     for (int idx = tid; idx < E * E; idx += NT) {
       const int a = idx / E, c = idx - a * E;
