@@ -333,7 +333,7 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
 #endif
     const int r =
         solve_and_truncate<NT>(lds(A), lds(V), m, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
-                               tau2, meta.caps[k], k, so, true);
+                               tau2, meta.caps[k], k, so, true, rp == (1 << (k - 1)));
 #ifdef QTT_EIG_TIMING
     const long long ls2 = wall_clock64();
 #endif

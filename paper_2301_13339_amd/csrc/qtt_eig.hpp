@@ -234,6 +234,57 @@ __device__ void jacobi_small(MP A, MP V, int lda, ldsd la) {
   }
 }
 
+// Whether A - mu I is positive definite (E <= 32), by a Cholesky
+// factorisation on the first wave that stops at the first pivot <= 0: the
+// layout of sy_tridiag32w (lane l holds column l & 31, rows 16 (l >> 5) ..),
+// the column of step j published in LDS twice, once with rows <= j cleared,
+// so the update l_i l_c needs no masks.  A is not modified.  The answer is
+// in every thread.  buf: >= 64 doubles; flag: one int of LDS.
+template <class MP>
+__device__ bool chol_pd32w(MP A, int E, int lda, double mu, ldsd buf, ldsi flag) {
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x, c = l & 31, h = l >> 5;
+    ldsd colA = buf, colV = buf + 32;
+    double a[16];
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) {
+      const int r = 16 * h + ii;
+      const double t = A[r * lda + c];  // r, c < 32 < lda
+      a[ii] = ((r < E) & (c < E)) ? (r == c ? t - mu : t) : (r == c ? 1.0 : 0.0);
+    }
+    int ok = 1;
+    for (int j = 0; j < E; ++j) {
+      if (c == j) {
+#pragma unroll
+        for (int ii = 0; ii < 16; ++ii) {
+          colA[16 * h + ii] = a[ii];
+          colV[16 * h + ii] = a[ii];
+        }
+      }
+      if (l <= j) colV[l] = 0.0;  // l <= j <= 31
+      wave_lds_sync();
+      const double d = colA[j];
+      if (!(d > 0.0)) {  // uniform
+        ok = 0;
+        break;
+      }
+      const double inv = rsq_acc(d);
+      const double lc = colV[c] * inv;
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) a[ii] = fma(-colV[16 * h + ii] * inv, lc, a[ii]);
+      wave_lds_sync();  // colA, colV are rewritten next step
+    }
+    if (l == 0) flag[0] = ok;
+  }
+  __syncthreads();
+  const bool pd = flag[0] != 0;
+  __syncthreads();
+  return pd;
+}
+
+// try_chol: the caller expects rank E (every earlier step kept full rank), so
+// the positive-definiteness test of A - mu I is tried first; when it fails
+// (at the pivot of the numerical rank) the usual path decides.
 // any_basis: the caller uses only the kept columns of V as a basis (not the
 // eigenvalues, and not the vectors as singular vectors).  Then a step whose
 // rank is E by the rule (the smallest eigenvalue above tau2, the cap not
@@ -245,7 +296,8 @@ __device__ void jacobi_small(MP A, MP V, int lda, ldsd la) {
 template <int NT, bool BIG = false, class MP, class MPV>
 __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi iscr, ldsd lam,
                                   ldsi perm, double tau2, int cap, int k,
-                                  const StepOut& so, bool any_basis = false) {
+                                  const StepOut& so, bool any_basis = false,
+                                  bool try_chol = false) {
   const int tid = threadIdx.x;
   ldsd dg = sx;
   ldsd od = dg + kMaxM;
@@ -278,6 +330,29 @@ __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi isc
   // does not bind or the tolerance is zero, else the cap largest (the rank
   // rule then works from the trace)
   const int K = (small || so.sv || cap >= E || !(tau2 > 0.0)) ? E : cap;
+  // rank E by the rule (any basis then serves): decided before any reduction
+  // when A - mu I is positive definite, mu a little above tau2
+  auto keep_all = [&]() {
+    for (int i = tid; i < E; i += NT) {
+      lam[i] = 0.0;
+      perm[i] = i;
+    }
+    for (int idx = tid; idx < E * E; idx += NT) {
+      const int a = idx / E, c = idx - a * E;
+      V[a * lda + c] = (a == c) ? 1.0 : 0.0;
+    }
+    if (tid == 0) {
+      iscr[2] = E;
+      so.ranks[k] = E;
+    }
+    __syncthreads();
+  };
+  const bool full_test = any_basis && !so.sv && !(so.delta2 > 0.0) && cap >= E;
+  if (try_chol && finite && !small && full_test && E <= 32 &&
+      chol_pd32w(A, E, lda, tau2 * (1.0 + 1e-6) + 1e-12 * sx[kEigNrmSlot + 1], pv, iscr + 4)) {
+    keep_all();
+    return E;
+  }
   if (small) {
     if constexpr (std::is_same<MP, MPV>::value) {
       if (tid == 0) {
@@ -308,23 +383,11 @@ __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi isc
     tt[1] = wall_clock64();
 #endif
     tnrm = tridiag_gersh(dg, od, E, sx + kEigNrmSlot);
-    if (any_basis && !so.sv && !(so.delta2 > 0.0) && cap >= E && tnrm > 0.0) {
+    if (full_test && E > 32 && tnrm > 0.0) {
       if (tid == 0) iscr[4] = sturm_below(dg, od, E, tau2 * (1.0 + 1e-6) + 1e-12 * tnrm, tnrm);
       __syncthreads();
       if (iscr[4] == 0) {  // uniform: rank E, any orthonormal basis
-        for (int i = tid; i < E; i += NT) {
-          lam[i] = 0.0;
-          perm[i] = i;
-        }
-        for (int idx = tid; idx < E * E; idx += NT) {
-          const int a = idx / E, c = idx - a * E;
-          V[a * lda + c] = (a == c) ? 1.0 : 0.0;
-        }
-        if (tid == 0) {
-          iscr[2] = E;
-          so.ranks[k] = E;
-        }
-        __syncthreads();
+        keep_all();
         return E;
       }
     }
