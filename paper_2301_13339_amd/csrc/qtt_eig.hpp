@@ -469,6 +469,7 @@ __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi isc
       // orthonormal to first order take one polishing step, others (or more
       // than 32) Gram-Schmidt
       const bool done = (r <= 32 && polish_backtr64(A, E, lda, V, r, pv)) ||
+                        (r > 32 && polish_backtr64_wide(A, E, lda, V, r, pv)) ||
                         mgs_backtr64(A, E, lda, V, lda, r, pv, iscr + 3);
 #ifdef QTT_EIG_TIMING
       tt[4] = wall_clock64();

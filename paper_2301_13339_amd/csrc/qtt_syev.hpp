@@ -731,6 +731,120 @@ __device__ bool polish_backtr64(MP A, int E, int lda, MP Z, int r, ldsd cs) {
   return true;
 }
 
+// The same for 32 < r <= 64 kept eigenvectors (columns of Z,
+// E <= 64 rows) when they are already orthonormal to first order, with the
+// back-transformation.  Vectors from the twisted factorisation are
+// orthogonal to about u ||T|| / gap (as above).  S no longer fits the
+// scratch, so C is formed first (up to four 16 x 16 blocks per wave, kept in registers); when
+// the test passes, Z <- Q Z (backtr_gemm64), which frees A, S = (3I - C) / 2
+// goes into A and Z <- Z S (Q Z S = Q (Z S)).  Otherwise (clustered
+// eigenvalues) the routine returns false with Z untouched and the caller
+// takes the Gram-Schmidt path.  All threads; cs: >= 8 doubles.
+template <class MP>
+__device__ bool polish_backtr64_wide(MP A, int E, int lda, MP Z, int r, ldsd cs) {
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63, lr = l & 15, lk = l >> 4;
+  ldsd dev = cs;  // per-wave max |C - I|
+  const int nb = (r + 15) >> 4;  // <= 4
+  double dmax = 0.0;
+  syev_f64x4 cacc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    cacc[t] = syev_f64x4{0.0, 0.0, 0.0, 0.0};
+    const int blk = w + 4 * t;
+    if (blk >= nb * nb) continue;  // wave-uniform
+    const int bi = blk / nb, bj = blk - bi * nb;
+    for (int k16 = 0; k16 < E; k16 += 16) {  // operands first, no branch among the products
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int c = k16 + 4 * u + lk;
+        const bool cin = c < E;
+        const int cc = cin ? c : 0;
+        const double a = Z[cc * lda + 16 * bi + lr], bz = Z[cc * lda + 16 * bj + lr];
+        av[u] = cin ? a : 0.0;
+        bv[u] = cin ? bz : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        cacc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], cacc[t], 0, 0, 0);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * bi + 4 * e + lk, j = 16 * bj + lr;
+      if (i < r && j < r) {
+        const double d = cacc[t][e] - (i == j ? 1.0 : 0.0);
+        dmax = fmax(dmax, fabs(d));
+        if (!(d == d)) dmax = 1.0;  // NaN
+      }
+    }
+  }
+  dmax = max64(dmax);
+  if (l == 0) dev[w] = dmax;
+  __syncthreads();
+  const double dm = fmax(fmax(dev[0], dev[1]), fmax(dev[2], dev[3]));
+  if (!(dm <= 1e-8)) return false;  // uniform; Z untouched
+  backtr_gemm64(A, E, lda, Z, r);   // Z <- Q Z; A is free from here
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int blk = w + 4 * t;
+    if (blk >= nb * nb) continue;
+    const int bi = blk / nb, bj = blk - bi * nb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * bi + 4 * e + lk, j = 16 * bj + lr;
+      if (i < r && j < r) {
+        const double d = cacc[t][e] - (i == j ? 1.0 : 0.0);
+        A[i * lda + j] = (i == j ? 1.0 : 0.0) - 0.5 * d;
+      }
+    }
+  }
+  __syncthreads();
+  // Z' = Z S: 16 x 16 blocks (row block rb < nrb, column block cb < nb)
+  syev_f64x4 zo[4];
+  const int nrb = (E + 15) >> 4;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    zo[t] = syev_f64x4{0.0, 0.0, 0.0, 0.0};
+    const int blk = w + 4 * t;
+    if (blk >= nrb * nb) continue;  // wave-uniform
+    const int rb = blk / nb, cb = blk - rb * nb;
+    const int row = 16 * rb + lr;
+    const bool rin = row < E;
+    const int rr = rin ? row : 0;
+    for (int k16 = 0; k16 < r; k16 += 16) {
+      double av[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int kk = k16 + 4 * u + lk;
+        const bool kin = kk < r;
+        const int kc = kin ? kk : 0;
+        const double a = Z[rr * lda + kc];
+        const double b = A[kc * lda + 16 * cb + lr];
+        av[u] = (rin & kin) ? a : 0.0;
+        bv[u] = kin ? b : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        zo[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], zo[t], 0, 0, 0);
+    }
+  }
+  __syncthreads();  // every wave has read Z
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int blk = w + 4 * t;
+    if (blk >= nrb * nb) continue;
+    const int rb = blk / nb, cb = blk - rb * nb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int i = 16 * rb + 4 * e + lk, j = 16 * cb + lr;
+      if (i < E && j < r) Z[i * lda + j] = zo[t][e];
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
 // Modified Gram-Schmidt of the r kept eigenvectors of T (columns 0..r-1 of
 // Z, E <= 64 rows, r <= 64) in registers, followed by Z <- Q Z with the
 // accumulated Q^T of sy_tridiag64 in A.  Column b lives in wave b / 16, in the
@@ -938,7 +1052,8 @@ __device__ __forceinline__ int sign_mask_changes(unsigned int mh, unsigned int m
   if constexpr (NE <= 32) {
     return __popc(mh ^ (mh >> 1));
   } else {
-    const unsigned long long m = ((unsigned long long)mh << 32) | ml;
+    // mh holds s_1 .. s_32, ml the remaining NE - 32 signs
+    const unsigned long long m = ((unsigned long long)mh << (NE - 32)) | ml;
     return __popcll(m ^ (m >> 1));
   }
 }
@@ -964,23 +1079,26 @@ __device__ __forceinline__ int sturm_count_reg(const double* av, const double* b
   return sign_mask_changes<NE>(mh, 0u);
 }
 
-// LDS operands, NE = 64: dn[0..64) and e2n[0..63) padded; loads in blocks of 8
-__device__ __forceinline__ int sturm_count_lds64(lds_ptr<const double> dn,
-                                                 lds_ptr<const double> e2n, double x) {
+// LDS operands, NE = 48 or 64: dn[0..NE) and e2n[0..NE-1) padded; loads
+// in blocks of 8
+template <int NE>
+__device__ __forceinline__ int sturm_count_lds(lds_ptr<const double> dn,
+                                               lds_ptr<const double> e2n, double x) {
+  static_assert(NE > 32 && NE <= 64, "two sign masks");
   double pm = 1.0, pc = dn[0] - x;
   unsigned int mh = shift_sign(0u, pc), ml = 0u;
 #pragma unroll
-  for (int i0 = 1; i0 < 64; i0 += 8) {
+  for (int i0 = 1; i0 < NE; i0 += 8) {
     double av[8], bv[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
-      av[u] = (i0 + u < 64) ? dn[i0 + u] : 0.0;
-      bv[u] = (i0 + u < 64) ? e2n[i0 - 1 + u] : 0.0;
+      av[u] = (i0 + u < NE) ? dn[i0 + u] : 0.0;
+      bv[u] = (i0 + u < NE) ? e2n[i0 - 1 + u] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int i = i0 + u;
-      if (i < 64) {
+      if (i < NE) {
         const double pn = fma(av[u] - x, pc, -bv[u] * pm);
         if (i < 32)
           mh = shift_sign(mh, pn);
@@ -996,7 +1114,7 @@ __device__ __forceinline__ int sturm_count_lds64(lds_ptr<const double> dn,
       }
     }
   }
-  return sign_mask_changes<64>(mh, ml);
+  return sign_mask_changes<NE>(mh, ml);
 }
 
 // Multisection for the K largest eigenvalues (K <= 256 / G) with a group of
@@ -1004,8 +1122,8 @@ __device__ __forceinline__ int sturm_count_lds64(lds_ptr<const double> dn,
 // index) and narrows its bracket (G+1)x per pass with one Sturm count per
 // lane.  All brackets start equal and shrink by the same factor, so the pass
 // count is fixed up front.  T is padded to NE rows; for NE <= 32 it is read
-// from LDS once and every pass runs on registers, for NE = 64 from LDS in
-// blocks of 8.
+// from LDS once and every pass runs on registers, for NE = 48 or 64 from LDS
+// in blocks of 8.
 template <int NT, int G, int NE>
 __device__ void multisect_top_pad(lds_ptr<const double> dn, lds_ptr<const double> e2n, int E,
                                   int K, double lo, double hi, double width_stop, double scale,
@@ -1032,7 +1150,7 @@ __device__ void multisect_top_pad(lds_ptr<const double> dn, lds_ptr<const double
     if constexpr (NE <= 32)
       c = sturm_count_reg<NE>(av, bv, x);
     else
-      c = sturm_count_lds64(dn, e2n, x);
+      c = sturm_count_lds<NE>(dn, e2n, x);
     const unsigned long long bal = __ballot(c > k);
     const unsigned int gb = (unsigned int)((bal >> gshift) & ((1ull << G) - 1));
     const int first = gb ? __builtin_ctz(gb) : G;
@@ -1057,6 +1175,8 @@ __device__ void multisect_top_any(lds_ptr<const double> dn, lds_ptr<const double
     multisect_top_pad<NT, G, 24>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
   else if (E <= 32)
     multisect_top_pad<NT, G, 32>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
+  else if (E <= 48)
+    multisect_top_pad<NT, G, 48>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
   else
     multisect_top_pad<NT, G, 64>(dn, e2n, E, K, lo, hi, width_stop, scale, lam);
 }
