@@ -294,6 +294,20 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Sixteen consecutive doubles from 16-byte aligned LDS as eight 128-bit
+// loads: their 16-bit immediate offsets reach every buffer of the solver from
+// one base register, where pairs of 64-bit loads needed an address add each.
+typedef double lds_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void lds_load16(lds_ptr<const double> p, double (&v)[16]) {
+  const lds_ptr<const lds_d2> q = (lds_ptr<const lds_d2>)p;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    const lds_d2 t = q[i];
+    v[2 * i] = t.x;
+    v[2 * i + 1] = t.y;
+  }
+}
+
 template <class MP>
 __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd buf) {
   const int tid = threadIdx.x;
@@ -351,8 +365,7 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
       double vi[16];
       double pp = 0.0, px = 0.0;
       if (q >= jb) {
-#pragma unroll
-        for (int ii = 0; ii < 16; ++ii) vi[ii] = colb[16 * q + ii];
+        lds_load16(colb + 16 * q, vi);
         if (q == jb) {
 #pragma unroll
           for (int ii = 0; ii <= jj; ++ii) vi[ii] = 0.0;
@@ -395,8 +408,7 @@ __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ld
         wb[c] = w;
         wave_lds_sync();
         double wi[16];
-#pragma unroll
-        for (int ii = 0; ii < 16; ++ii) wi[ii] = wb[16 * q + ii];
+        lds_load16(wb + 16 * q, wi);
 #pragma unroll
         for (int ii = 0; ii < 16; ++ii) a[ii] = fma(-vi[ii], w, fma(-wi[ii], vc, a[ii]));
         // X <- H_j X = X - beta v (v^T X)
