@@ -483,8 +483,7 @@ __device__ void sy_tridiag32w(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, l
       wave_lds_sync();
       const double x0 = colA[j + 1], dj = colA[j];
       double m[16];
-#pragma unroll
-      for (int ii = 0; ii < 16; ++ii) m[ii] = colV[16 * h + ii];
+      lds_load16(colV + 16 * h, m);
       double n0 = 0.0, n1 = 0.0, n2 = 0.0, n3 = 0.0;
 #pragma unroll
       for (int ii = 0; ii < 16; ii += 4) {
@@ -510,8 +509,7 @@ __device__ void sy_tridiag32w(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, l
       if (l == 0) colV[j + 1] = v0;
       wave_lds_sync();
       double vi[16];
-#pragma unroll
-      for (int ii = 0; ii < 16; ++ii) vi[ii] = colV[16 * h + ii];
+      lds_load16(colV + 16 * h, vi);
       const double vc = colV[c];
       double s0 = 0.0, s1 = 0.0, s2a = 0.0, s3 = 0.0, u0 = 0.0, u1 = 0.0, u2 = 0.0, u3 = 0.0;
 #pragma unroll
@@ -535,8 +533,7 @@ __device__ void sy_tridiag32w(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, l
       }
       wave_lds_sync();
       double pi[16];
-#pragma unroll
-      for (int ii = 0; ii < 16; ++ii) pi[ii] = pb[16 * h + ii];
+      lds_load16(pb + 16 * h, pi);
       double k0 = 0.0, k1 = 0.0, k2 = 0.0, k3 = 0.0;
 #pragma unroll
       for (int ii = 0; ii < 16; ii += 4) {
