@@ -311,7 +311,9 @@ __device__ __forceinline__ void lds_load16(lds_ptr<const double> p, double (&v)[
 template <class MP>
 __device__ void sy_tridiag64(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd buf) {
   const int tid = threadIdx.x;
-  const int q = tid >> 6, c = tid & 63;
+  // the wave index is uniform in the wave: in a scalar register, the
+  // branches on it are scalar branches, not exec-mask updates
+  const int q = __builtin_amdgcn_readfirstlane(tid >> 6), c = tid & 63;
   ldsd part = buf + 128;         // 4 x 64: partial A v of each wave
   ldsd wb = buf + 384 + 64 * q;  // 64 per wave (wave-private): w
   ldsd last = buf + 576;         // 2 x 64: rows E-2 and E-1 at the end
