@@ -369,12 +369,16 @@ __device__ int solve_and_truncate(MP A, MPV V, int E, int lda, ldsd sx, ldsi isc
       // of split storage (A and V in different memories) does not take
       if (E > 64 || !std::is_same<MP, MPV>::value)
         sy_tridiag<NT, 8>(A, E, lda, dg, od, bt, pv);
+      else if (E <= 16)
+        sy_tridiag16w(A, E, lda, dg, od, bt, pv);
       else if (E <= 32)
         sy_tridiag32w(A, E, lda, dg, od, bt, pv);
       else
         sy_tridiag64(A, E, lda, dg, od, bt, pv);
     } else {
-      if (E <= 32)
+      if (E <= 16)
+        sy_tridiag16w(A, E, lda, dg, od, bt, pv);
+      else if (E <= 32)
         sy_tridiag32w(A, E, lda, dg, od, bt, pv);
       else
         sy_tridiag64(A, E, lda, dg, od, bt, pv);

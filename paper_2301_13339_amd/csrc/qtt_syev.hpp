@@ -61,6 +61,8 @@ __device__ __forceinline__ double sum_row_pairs(double x) {
 __device__ __forceinline__ double sum32(double v) { return sum_row_pairs(sum16(v)); }
 // sum over the whole wave (every lane gets the sum)
 __device__ __forceinline__ double sum64(double v) { return sum_halves(sum_row_pairs(sum16(v))); }
+// x summed over the four DPP rows at the same position, in every lane
+__device__ __forceinline__ double sum_rows4(double x) { return sum_halves(sum_row_pairs(x)); }
 
 // max over the whole wave of non-negative values (every lane gets it)
 __device__ __forceinline__ double max64(double v) {
@@ -581,6 +583,110 @@ __device__ void sy_tridiag32w(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, l
   __syncthreads();
 }
 
+// The same reduction for E <= 16, with four rows per lane: lane l holds
+// column l & 15, rows 4 (l >> 4) .. 4 (l >> 4) + 3, so a column's four row
+// groups are the four DPP rows at one position and every per-column sum is
+// a sum over the own four rows plus sum_rows4.  buf: >= 96 doubles.
+template <class MP>
+__device__ void sy_tridiag16w(MP A, int E, int lda, ldsd dg, ldsd od, ldsd bt, ldsd buf) {
+  if (threadIdx.x < 64) {
+    const int l = threadIdx.x, c = l & 15, g = l >> 4;
+    ldsd colA = buf;       // column j as it stands, 16
+    ldsd colV = buf + 16;  // v of step j, 16
+    ldsd pb = buf + 32;    // p, 16
+    ldsd last = buf + 48;  // columns E-2 and E-1, 2 x 16
+    double a[4], x[4];
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int r = 4 * g + ii;
+      const double t = A[r * lda + c];  // r, c < 16 < lda: in bounds
+      a[ii] = ((r < E) & (c < E)) ? t : 0.0;
+      x[ii] = (r == c) ? 1.0 : 0.0;
+    }
+    for (int j = 0; j + 2 < E; ++j) {
+      if (c == j) {  // the four lanes of column j (= row j)
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          colA[4 * g + ii] = a[ii];
+          colV[4 * g + ii] = a[ii];
+        }
+      }
+      if (l <= j + 1) colV[l] = 0.0;  // l <= j + 1 <= 14: rows that v leaves out
+      wave_lds_sync();
+      const double x0 = colA[j + 1], dj = colA[j];
+      double m[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) m[ii] = colV[4 * g + ii];
+      const double xs2 = sum_rows4(fma(m[0], m[0], m[1] * m[1]) + fma(m[2], m[2], m[3] * m[3]));
+      if (xs2 <= 1e-300 + 1e-32 * (xs2 + x0 * x0)) {  // already reduced (uniform)
+        if (l == 0) {
+          bt[j] = 0.0;
+          od[j] = x0;
+          dg[j] = dj;
+        }
+        continue;
+      }
+      const double s2 = xs2 + x0 * x0;
+      const double alpha = s2 * rsq_acc(s2);
+      const double sg = x0 >= 0.0 ? 1.0 : -1.0;
+      const double v0 = x0 + sg * alpha;
+      const double beta = 2.0 * rcp_acc(xs2 + v0 * v0);
+      if (l == 0) colV[j + 1] = v0;
+      wave_lds_sync();
+      double vi[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) vi[ii] = colV[4 * g + ii];
+      const double vc = colV[c];
+      const double p =
+          beta * sum_rows4(fma(a[0], vi[0], a[1] * vi[1]) + fma(a[2], vi[2], a[3] * vi[3]));
+      const double bvx =
+          beta * sum_rows4(fma(x[0], vi[0], x[1] * vi[1]) + fma(x[2], vi[2], x[3] * vi[3]));
+      if (g == 0) pb[c] = p;
+      if (l == 0) {
+        dg[j] = dj;
+        od[j] = -sg * alpha;
+        bt[j] = beta;
+      }
+      wave_lds_sync();
+      double pi[4];
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) pi[ii] = pb[4 * g + ii];
+      const double K = 0.5 * beta *
+                       sum_rows4(fma(pi[0], vi[0], pi[1] * vi[1]) + fma(pi[2], vi[2], pi[3] * vi[3]));
+      // A - v w^T - w v^T with w = p - K v (as in sy_tridiag32w)
+      const double gg = p - 2.0 * K * vc;
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        a[ii] = fma(-vi[ii], gg, fma(-pi[ii], vc, a[ii]));
+        x[ii] = fma(-bvx, vi[ii], x[ii]);
+      }
+    }
+    if (c == E - 2) {
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) last[4 * g + ii] = a[ii];
+    }
+    if (c == E - 1) {
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) last[16 + 4 * g + ii] = a[ii];
+    }
+    wave_lds_sync();
+    if (l == 0) {
+      if (E >= 2) {
+        dg[E - 2] = last[E - 2];
+        od[E - 2] = last[E - 1];
+        bt[E - 2] = 0.0;
+      }
+      if (E >= 1) {
+        dg[E - 1] = last[16 + E - 1];
+        bt[E - 1] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) A[(4 * g + ii) * lda + c] = x[ii];
+  }
+  __syncthreads();
+}
+
 // Z <- Q Z for the r <= 64 columns of Z (E <= 64 rows) with X = Q^T in A
 // (sy_tridiag64), as one product on the FP64 matrix cores: wave w forms the
 // 16-row block w of U = X^T Z, one 16 x 16 block per 16 columns.  All
@@ -641,8 +747,6 @@ __device__ void backtr_gemm64(MP X, int E, int lda, MP Z, int r) {
     backtr_gemm64_n<4>(X, E, lda, Z, r);
 }
 
-// x summed over the four DPP rows at the same position, in every lane
-__device__ __forceinline__ double sum_rows4(double x) { return sum_halves(sum_row_pairs(x)); }
 
 // Orthonormalisation of the r <= 32 kept eigenvectors of T (columns of Z,
 // E <= 64 rows) when they are already orthonormal to first order, then
