@@ -70,6 +70,11 @@ DECOMP_CASES = [
     ("scatter_d20_R32_e2", lambda: G.scatterers_1d(20, 2)[0], 1e-2, 32),
     # cap 48: unfoldings of 96 rows use the global-memory eigensolver path
     ("scatter_d17_R48", lambda: G.scatterers_1d(17, 2)[0], 1e-4, 48),
+    # caps 20 and 24: Grams of order 40 and 48 (Sturm counts padded to 48
+    # rows) and orders 10..16 (the four-rows-per-lane reduction)
+    ("scatter_d14_R20", lambda: G.scatterers_1d(14, 2)[0], 1e-4, 20),
+    ("scatter_d15_R24", lambda: G.scatterers_1d(15, 5)[0], 1e-4, 24),
+    ("scatter_d13_R6", lambda: G.scatterers_1d(13, 7)[0], 1e-4, 6),
 ]
 
 
