@@ -183,15 +183,24 @@ __global__ void __launch_bounds__(256) k_level_gram(const T* x, double B, int nk
 // out[e] = sum_b partials[b*pstride + e] for e < count.  Block of 256 threads
 // = 64 entries x 4 partial groups; group g sums partials g, g+4, ... and the
 // four group sums are added in a fixed order (deterministic).  Block 0 also
-// sums the generator partial sums into scal[2].
+// sums the generator partial sums into scal[2].  With mranks, the entries
+// are an M x M Gram at row stride mstride, M = 2 mranks[mk - 1] on the
+// device, and entries outside it (never written by the pass) are skipped.
 __global__ void __launch_bounds__(256) k_reduce(const double* partials, int pstride, int nparts,
                                                 int count, double* out, const double* gsum_part,
-                                                double* scal) {
+                                                double* scal, const int32_t* mranks = nullptr,
+                                                int mk = 0, int mstride = 1) {
   __shared__ double red[4][64];
   const int el = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + el;
   double s = 0.0;
-  if (e < count) {
+  bool in = e < count;
+  if (mranks) {
+    const int M = 2 * mranks[mk - 1];
+    const int row = e / mstride, col = e - row * mstride;
+    in = in && row < M && col < M;
+  }
+  if (in) {
     // eight independent loads in flight per thread, summed in a fixed order
     int b = g;
     for (; b + 28 < nparts; b += 32) {
@@ -204,7 +213,7 @@ __global__ void __launch_bounds__(256) k_reduce(const double* partials, int pstr
   }
   red[g][el] = s;
   __syncthreads();
-  if (g == 0 && e < count) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
+  if (g == 0 && in) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
   if (gsum_part && blockIdx.x == 0 && threadIdx.x == 0) {
     double t = 0.0;
     for (int b = 0; b < nparts; ++b) t += gsum_part[b];
@@ -1329,7 +1338,8 @@ static int run_decompose_t(const DecompPlan& P, const Source& src, double eps,
     {
       ProbeScope _ps(QTT_K_REDUCE, stream);
       k_reduce<<<(mstride * mstride + 63) / 64, 256, 0, stream>>>(
-        P.partials, P.pstride, nparts, mstride * mstride, P.gram, nullptr, nullptr);
+        P.partials, P.pstride, nparts, mstride * mstride, P.gram, nullptr, nullptr, out.ranks, k,
+        mstride);
     }
     QTT_LAUNCH_CHECK();
     {
