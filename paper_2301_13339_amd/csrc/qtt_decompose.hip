@@ -214,10 +214,14 @@ __global__ void __launch_bounds__(256) k_reduce(const double* partials, int pstr
   red[g][el] = s;
   __syncthreads();
   if (g == 0 && in) out[e] = (red[0][el] + red[1][el]) + (red[2][el] + red[3][el]);
-  if (gsum_part && blockIdx.x == 0 && threadIdx.x == 0) {
+  if (gsum_part && blockIdx.x == 0 && threadIdx.x < 64) {  // uniform in the wave
+    // the squared norm: every lane sums a stride of the block partials, then
+    // a butterfly over the wave; each lane's order is fixed, lane 0's is kept
     double t = 0.0;
-    for (int b = 0; b < nparts; ++b) t += gsum_part[b];
-    scal[2] = t;
+    for (int b = threadIdx.x; b < nparts; b += 64) t += gsum_part[b];
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) t += __shfl_xor(t, m, 64);
+    if (threadIdx.x == 0) scal[2] = t;
   }
 }
 
