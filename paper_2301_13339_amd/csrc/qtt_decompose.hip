@@ -308,6 +308,57 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
     scal[0] = nrm2;
     scal[1] = tau2;
   }
+  // Full-rank pre-test of steps 1 .. min(L, 5).  While every earlier step
+  // keeps its full rank 2^(k-1) with U = I, Phi_{k-1} and P_k are
+  // permutations, so the matrix A of step k is G_k with rows and columns
+  // permuted: A - mu I is positive definite exactly when G_k - mu I is, and
+  // the trace that mu takes is the same.  The tests of these steps are then
+  // independent and run on separate waves (step 5 on wave 0, 4 on wave 1, 3
+  // on wave 2, 2 and 1 on wave 3).  The leading steps that pass keep V = I
+  // without forming A or solving; the first that fails, and every later
+  // one, take the usual path.  Not with singular values or a drop-off
+  // requested (those need the eigenvalues).
+  int npre = 0;
+  const int KP = L < 5 ? L : 5;
+  if (!so.sv && !(so.delta2 > 0.0)) {
+    double* Gs = A;                      // slots of 32 x 32 (lda 32) over A and V
+    ldsi okf = lds(perm);                // okf[k]: step k passed (perm is free here)
+    for (int k = 1; k <= KP; ++k) {
+      const int w = 1 << k, reps = W / w;
+      for (int e = tid; e < w * w; e += NT) {
+        const int c = e / w, c2 = e - c * w;
+        double g = 0.0;
+        for (int h = 0; h < reps; ++h) g += GZ[(c + h * w) * W + c2 + h * w];
+        Gs[(k - 1) * 1024 + c * 32 + c2] = g;
+      }
+    }
+    __syncthreads();
+    const int q = __builtin_amdgcn_readfirstlane(tid >> 6), l = tid & 63;
+    ldsd cb = lds(A + 5 * 1024 + 64 * q);  // per-wave Cholesky buffer
+    auto test = [&](int k) {
+      const int E = 1 << k;
+      const lds_ptr<const double> G = lds<const double>(Gs + (k - 1) * 1024);
+      double tr = 0.0;
+      for (int i = l; i < E; i += 64) tr += G[i * 32 + i];
+      tr = sum64(tr);
+      const bool ok = isfinite(tr) && meta.caps[k] >= E &&
+                      chol_pd_wave(G, E, 32, tau2 * (1.0 + 1e-6) + 1e-12 * tr, cb);
+      if (l == 0) okf[k] = ok ? 1 : 0;
+    };
+    if (q == 0) {
+      if (KP >= 5) test(5);
+    } else if (q == 1) {
+      if (KP >= 4) test(4);
+    } else if (q == 2) {
+      if (KP >= 3) test(3);
+    } else {
+      if (KP >= 2) test(2);
+      test(1);
+    }
+    __syncthreads();
+    while (npre < KP && okf[npre + 1]) ++npre;
+    __syncthreads();  // perm is rewritten by the steps
+  }
   int rp = 1;  // r_{k-1}
   for (int k = 1; k <= L; ++k) {
 #ifdef QTT_EIG_TIMING
@@ -315,41 +366,58 @@ __device__ void level_steps(double* smem, int L, int D, double eps, const Meta& 
 #endif
     const int w = 1 << k, half = w >> 1;
     const int m = 2 * rp;
-    // G_k[c][c'] = sum_h GZ[c + h w][c' + h w]  (w x w, into V before the solve)
-    const int reps = W / w;
-    for (int e = tid; e < w * w; e += NT) {
-      const int c = e / w, c2 = e - c * w;
-      double g = 0.0;
-      for (int h = 0; h < reps; ++h) g += GZ[(c + h * w) * W + c2 + h * w];
-      V[c * LDA + c2] = g;
-    }
-    __syncthreads();
-    // T1 = G_k P_k (w x m): P_k[cl + half i][i' rp + a] = [i == i'] Phi[cl][a],
-    // so column block i of T1 is G_k[:, half i .. half i + half) Phi
-    {
-      ldsd T1l = lds(T1);
-      for (int i = 0; i < 2; ++i)
-        lds_gemm_mfma(w, rp, half, lds<const double>(V + half * i), LDA, 1, lds<const double>(Phi), 32, 1,
-                 [&](int c, int a, double v) { T1l[c * m + i * rp + a] = v; });
-    }
-    __syncthreads();
-    // A = P_k^T T1 (m x m): row block i is Phi^T T1[half i .. half i + half, :]
-    {
-      ldsd Al = lds(A);
-      for (int i = 0; i < 2; ++i)
-        lds_gemm_mfma(rp, m, half, lds<const double>(Phi), 1, 32, lds<const double>(T1 + half * i * m), m,
-                 1, [&](int a, int col, double v) { Al[(i * rp + a) * LDA + col] = v; });
-    }
-    __syncthreads();
+    int r;
 #ifdef QTT_EIG_TIMING
-    const long long ls1 = wall_clock64();
+    long long ls1, ls2;
 #endif
-    const int r =
-        solve_and_truncate<NT>(lds(A), lds(V), m, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
-                               tau2, meta.caps[k], k, so, true, rp == (1 << (k - 1)));
+    if (k <= npre) {  // rank m by the pre-test: V = I in the identity order
+      for (int i = tid; i < m; i += NT) perm[i] = i;
+      for (int idx = tid; idx < m * m; idx += NT) {
+        const int a = idx / m, c = idx - a * m;
+        V[a * LDA + c] = (a == c) ? 1.0 : 0.0;
+      }
+      if (tid == 0) so.ranks[k] = m;
+      __syncthreads();
+      r = m;
 #ifdef QTT_EIG_TIMING
-    const long long ls2 = wall_clock64();
+      ls1 = ls2 = wall_clock64();
 #endif
+    } else {
+      // G_k[c][c'] = sum_h GZ[c + h w][c' + h w]  (w x w, into V before the solve)
+      const int reps = W / w;
+      for (int e = tid; e < w * w; e += NT) {
+        const int c = e / w, c2 = e - c * w;
+        double g = 0.0;
+        for (int h = 0; h < reps; ++h) g += GZ[(c + h * w) * W + c2 + h * w];
+        V[c * LDA + c2] = g;
+      }
+      __syncthreads();
+      // T1 = G_k P_k (w x m): P_k[cl + half i][i' rp + a] = [i == i'] Phi[cl][a],
+      // so column block i of T1 is G_k[:, half i .. half i + half) Phi
+      {
+        ldsd T1l = lds(T1);
+        for (int i = 0; i < 2; ++i)
+          lds_gemm_mfma(w, rp, half, lds<const double>(V + half * i), LDA, 1, lds<const double>(Phi), 32, 1,
+                   [&](int c, int a, double v) { T1l[c * m + i * rp + a] = v; });
+      }
+      __syncthreads();
+      // A = P_k^T T1 (m x m): row block i is Phi^T T1[half i .. half i + half, :]
+      {
+        ldsd Al = lds(A);
+        for (int i = 0; i < 2; ++i)
+          lds_gemm_mfma(rp, m, half, lds<const double>(Phi), 1, 32, lds<const double>(T1 + half * i * m), m,
+                   1, [&](int a, int col, double v) { Al[(i * rp + a) * LDA + col] = v; });
+      }
+      __syncthreads();
+#ifdef QTT_EIG_TIMING
+      ls1 = wall_clock64();
+#endif
+      r = solve_and_truncate<NT>(lds(A), lds(V), m, LDA, lds(sx), lds(iscr), lds(lam), lds(perm),
+                                 tau2, meta.caps[k], k, so, true, rp == (1 << (k - 1)));
+#ifdef QTT_EIG_TIMING
+      ls2 = wall_clock64();
+#endif
+    }
     // core k = V[:, perm[:r]]
     {
       const int total = rp * 2 * r;

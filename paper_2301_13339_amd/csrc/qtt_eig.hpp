@@ -235,46 +235,56 @@ __device__ void jacobi_small(MP A, MP V, int lda, ldsd la) {
 }
 
 // Whether A - mu I is positive definite (E <= 32), by a Cholesky
-// factorisation on the first wave that stops at the first pivot <= 0: the
+// factorisation on the calling wave that stops at the first pivot <= 0: the
 // layout of sy_tridiag32w (lane l holds column l & 31, rows 16 (l >> 5) ..),
 // the column of step j published in LDS twice, once with rows <= j cleared,
-// so the update l_i l_c needs no masks.  A is not modified.  The answer is
-// in every thread.  buf: >= 64 doubles; flag: one int of LDS.
+// so the update l_i l_c needs no masks.  A is not modified; rows and
+// columns < 32 are read (>= 32 rows allocated, 32 <= lda).  The answer is
+// the same in every lane.  buf: >= 64 doubles of LDS private to the wave.
+template <class MP>
+__device__ bool chol_pd_wave(MP A, int E, int lda, double mu, ldsd buf) {
+  const int l = threadIdx.x & 63, c = l & 31, h = l >> 5;
+  ldsd colA = buf, colV = buf + 32;
+  double a[16];
+#pragma unroll
+  for (int ii = 0; ii < 16; ++ii) {
+    const int r = 16 * h + ii;
+    const double t = A[r * lda + c];  // r, c < 32 <= lda
+    a[ii] = ((r < E) & (c < E)) ? (r == c ? t - mu : t) : (r == c ? 1.0 : 0.0);
+  }
+  bool ok = true;
+  for (int j = 0; j < E; ++j) {
+    if (c == j) {
+#pragma unroll
+      for (int ii = 0; ii < 16; ++ii) {
+        colA[16 * h + ii] = a[ii];
+        colV[16 * h + ii] = a[ii];
+      }
+    }
+    if (l <= j) colV[l] = 0.0;  // l <= j <= 31
+    wave_lds_sync();
+    const double d = colA[j];
+    if (!(d > 0.0)) {  // uniform
+      ok = false;
+      break;
+    }
+    const double inv = rsq_acc(d);
+    const double lc = colV[c] * inv;
+#pragma unroll
+    for (int ii = 0; ii < 16; ++ii) a[ii] = fma(-colV[16 * h + ii] * inv, lc, a[ii]);
+    wave_lds_sync();  // colA, colV are rewritten next step
+  }
+  wave_lds_sync();  // the next user of buf follows every read above
+  return ok;
+}
+
+// chol_pd_wave on the first wave, the answer in every thread; flag: one int
+// of LDS.  Called by all threads.
 template <class MP>
 __device__ bool chol_pd32w(MP A, int E, int lda, double mu, ldsd buf, ldsi flag) {
   if (threadIdx.x < 64) {
-    const int l = threadIdx.x, c = l & 31, h = l >> 5;
-    ldsd colA = buf, colV = buf + 32;
-    double a[16];
-#pragma unroll
-    for (int ii = 0; ii < 16; ++ii) {
-      const int r = 16 * h + ii;
-      const double t = A[r * lda + c];  // r, c < 32 < lda
-      a[ii] = ((r < E) & (c < E)) ? (r == c ? t - mu : t) : (r == c ? 1.0 : 0.0);
-    }
-    int ok = 1;
-    for (int j = 0; j < E; ++j) {
-      if (c == j) {
-#pragma unroll
-        for (int ii = 0; ii < 16; ++ii) {
-          colA[16 * h + ii] = a[ii];
-          colV[16 * h + ii] = a[ii];
-        }
-      }
-      if (l <= j) colV[l] = 0.0;  // l <= j <= 31
-      wave_lds_sync();
-      const double d = colA[j];
-      if (!(d > 0.0)) {  // uniform
-        ok = 0;
-        break;
-      }
-      const double inv = rsq_acc(d);
-      const double lc = colV[c] * inv;
-#pragma unroll
-      for (int ii = 0; ii < 16; ++ii) a[ii] = fma(-colV[16 * h + ii] * inv, lc, a[ii]);
-      wave_lds_sync();  // colA, colV are rewritten next step
-    }
-    if (l == 0) flag[0] = ok;
+    const bool ok = chol_pd_wave(A, E, lda, mu, buf);
+    if (threadIdx.x == 0) flag[0] = ok ? 1 : 0;
   }
   __syncthreads();
   const bool pd = flag[0] != 0;
