@@ -145,6 +145,40 @@ def _lowrank_noise(d, seed, noise):
     return v + noise * rng.standard_normal(v.size)
 
 
+def _sinusoids(d, seed, n=12):
+    """n cosines spread up to 0.46 N cycles: every unfolding of QTT level k
+    (rows = the low k index bits) has rank min(2^k, 2n), well conditioned."""
+    N = 1 << d
+    t = np.arange(N) / float(N)
+    rng = np.random.default_rng(seed)
+    return sum(np.cos(2 * np.pi * round(N * (j + 0.37) / (2 * n + 3)) * t + rng.uniform(0, 2 * np.pi))
+               for j in range(1, n + 1))
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_decompose_level_full_rank_then_deficient(dt):
+    """Level steps without the singular-value output: steps 1-4 keep full rank
+    (their positive-definiteness tests pass and they keep V = I), step 5 has
+    rank 24 of 32 with no cap (its test fails on a pivot, and it and every
+    later step take the eigensolver): same ranks and tensor as the oracle,
+    left-orthonormal cores."""
+    announce("decompose level full rank then deficient", dt)
+    x = _sinusoids(16, 11)
+    if dt == torch.float32:
+        x = x.astype(np.float32).astype(np.float64)
+    eps, R = 1e-6, 0
+    ref, info = tt.tt_svd(x, eps, R, return_info=True)
+    assert info["ranks"][:7] == [1, 2, 4, 8, 16, 24, 24] and info["margin"] > 0.5
+    t = q.decompose(torch.tensor(x, dtype=dt, device=DEV), eps, R)
+    assert t.ranks_host() == info["ranks"]
+    assert t.status_host() == 0
+    assert rel(q.full(t).cpu().numpy(), tt.tt_full(ref)) <= tol_for(dt, eps)
+    for c in t.core_list()[:-1]:
+        U = c.reshape(-1, c.shape[2], order="F")
+        assert np.max(np.abs(U.T @ U - np.eye(U.shape[1]))) <= (1e-10 if dt == torch.float64
+                                                                   else 1e-5)
+
+
 # Modification (3) of Section 5: the singular-value drop-off cut, alone
 # (eps = 0) or with the tolerance and the cap.  The cases cut at several
 # unfoldings (to rank 1 where the two sample halves are nearly equal) and run
